@@ -1,0 +1,245 @@
+"""Block stochastic gradient descent, step by step, on an explicit sparse A.
+
+TEST INFRASTRUCTURE (oracle), FP64. Follows Algorithms 1 (BSGD), 2 (BSGD-IM)
+and 4 (BSGD-TV) in the paper's order and notation, in the precise form of the
+state-update equations of the fixed-point analysis (Eqs. (Updaz), (Updag),
+(Updax)):
+
+  state: x, z^j (one r-vector per column block), g^i_hat (one c-vector per row
+  block), g; initially z = 0, g_hat = 0, g = 0, r = y.
+
+  iteration k:
+    1. choose alpha M row blocks R and gamma N column blocks C at random
+    2. rows(i, j) = all rays of the views of I_i; with importance sampling, for
+       each view of I_i one sub-detector drawn with probability proportional to
+       the quantised weight table q[v][s][j] (views with no weight are skipped)
+    3. with x frozen, z^j[rows(i, j)] = A[rows(i, j), J_j] x[J_j]   for (i, j) in R x C
+    4. r = y - sum_j z^j
+    5. g_hat^i[J_j] = 2 A[rows(i, j), J_j]^T r[rows(i, j)]          for (i, j) in R x C
+    6. g = sum_i g_hat^i
+    7. x[J_j] += mu g[J_j]                                            for j in C
+    8. k <- k + 1; with TV, when k is a multiple of T = round(1/(alpha gamma)):
+       x <- argmin_t ||t - x||^2 + 2 mu lambda TV(t)
+
+Readings of unstated details (each listed in the design notes):
+* the factor 2 in the gradient is kept literally (g = 2 A^T r, x += mu g);
+* blocks are drawn uniformly without replacement within an iteration and
+  independently across iterations (counter-based stream, see ``rng``);
+* importance weights are squared Frobenius norms of the sub-matrices A[sub-detector
+  rows, J_j] ("block column norms"), quantised to integers q_s = round(2^20 w_s /
+  sum w) with q_s >= 1 whenever w_s > 0; the drawn sub-detector is the first s
+  whose running sum of q exceeds bounded(hash(seed, IM, k, v, j), sum q);
+* the IM gradient memory is overwritten without reweighting (literal Algorithm 2).
+
+Pinned by: closed-form gradient (mu = 0, all blocks), the gradient-descent special
+case alpha = gamma = 1, the SAG special case gamma = 1, convergence to the least
+squares solution (fixed-point analysis), monotone objective decrease in the GD
+case, the invariants r = y - sum z and g = sum g_hat, and Eq. 1's worked examples.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+from bsgd_inputs.configs import GeometrySpec
+from . import geometry as geo
+from . import rng
+from .tv import fgp_prox
+
+Q_BITS = 20
+
+
+def eq1(node_count: int, M: int, N: int):
+    """Eq. 1: gamma = min(1, P/N), alpha = P/(M N gamma). Returns (alpha, gamma)."""
+    gamma = min(1.0, node_count / N)
+    alpha = node_count / (M * N * gamma)
+    return alpha, gamma
+
+
+@dataclass
+class Problem:
+    g: GeometrySpec
+    A: sp.csr_matrix
+    groups: List[List[int]]
+    blocks: List[np.ndarray]
+    A_cols: list = field(default_factory=list)  # A[:, J_j] as CSR, one per block
+
+    @staticmethod
+    def build(g: GeometrySpec, A: Optional[sp.csr_matrix] = None) -> "Problem":
+        if A is None:
+            from .system import matrix
+            A = matrix(g)
+        A = sp.csr_matrix(A)
+        blocks = geo.column_blocks(g)
+        groups = geo.view_groups(g)
+        cols = [sp.csr_matrix(A[:, J]) for J in blocks]
+        return Problem(g=g, A=A, groups=groups, blocks=blocks, A_cols=cols)
+
+    @property
+    def M(self):
+        return len(self.groups)
+
+    @property
+    def N(self):
+        return len(self.blocks)
+
+
+def im_weights(p: Problem) -> np.ndarray:
+    """w[v][s][j] = || A[rows of sub-detector s of view v, J_j] ||_F^2 (float64)."""
+    g = p.g
+    S = g.su * g.sv
+    w = np.zeros((g.n_views, S, p.N))
+    A2 = [Aj.multiply(Aj).tocsr() for Aj in p.A_cols]
+    for j, Aj2 in enumerate(A2):
+        per_ray = np.asarray(Aj2.sum(axis=1)).reshape(-1)
+        for v in range(g.n_views):
+            for s in range(S):
+                w[v, s, j] = per_ray[geo.subdetector_rays(g, v, s)].sum()
+    return w
+
+
+def quantise(w: np.ndarray) -> np.ndarray:
+    """q = round(2^20 w / sum_s w) per (view, block), forced >= 1 where w > 0."""
+    tot = w.sum(axis=1, keepdims=True)
+    q = np.zeros(w.shape, dtype=np.int64)
+    nz = tot > 0
+    ratio = np.where(nz, w / np.where(nz, tot, 1.0), 0.0)
+    q = np.floor(ratio * (1 << Q_BITS) + 0.5).astype(np.int64)
+    q = np.where((w > 0) & (q == 0), 1, q)
+    return q.astype(np.uint32)
+
+
+def im_table(p: Problem, mode: str) -> Optional[np.ndarray]:
+    g = p.g
+    S = g.su * g.sv
+    if mode == "none":
+        return None
+    if mode == "uniform":
+        return np.ones((g.n_views, S, p.N), dtype=np.uint32)
+    if mode == "colnorm":
+        return quantise(im_weights(p))
+    raise ValueError(mode)
+
+
+def draw_subdetector(seed: int, k: int, view: int, block: int, qcol) -> int:
+    """Sub-detector for (iteration, view, block), or -1 when the view has no weight."""
+    qcol = [int(v) for v in qcol]
+    total = sum(qcol)
+    if total == 0:
+        return -1
+    u = rng.bounded(rng.hash_keys(seed, rng.STREAM_IM, k, view, block), total)
+    acc = 0
+    for s, qs in enumerate(qcol):
+        acc += qs
+        if acc > u:
+            return s
+    raise AssertionError("unreachable")
+
+
+@dataclass
+class State:
+    x: np.ndarray
+    z: np.ndarray       # [N][r]
+    ghat: np.ndarray    # [M][c]
+    gsum: np.ndarray    # [c]
+    r: np.ndarray       # [r]
+    k: int = 0
+
+
+def initial_state(p: Problem, y: np.ndarray, x0: Optional[np.ndarray] = None) -> State:
+    r_n, c_n = p.A.shape
+    x = np.zeros(c_n) if x0 is None else np.array(x0, dtype=np.float64)
+    return State(x=x, z=np.zeros((p.N, r_n)), ghat=np.zeros((p.M, c_n)), gsum=np.zeros(c_n),
+                 r=np.array(y, dtype=np.float64))
+
+
+def rows_for_pair(p: Problem, i: int, j: int, k: int, seed: int, q, draws_out=None):
+    g = p.g
+    if q is None:
+        return geo.rays_of_group(g, p.groups[i])
+    parts = []
+    for v in p.groups[i]:
+        s = draw_subdetector(seed, k, v, j, q[v, :, j])
+        if draws_out is not None:
+            draws_out[(v, j)] = s
+        if s >= 0:
+            parts.append(geo.subdetector_rays(g, v, s))
+    return np.concatenate(parts) if parts else np.zeros(0, dtype=np.int64)
+
+
+def iterate(p: Problem, st: State, y: np.ndarray, mu: float, rows_per_iter: int,
+            blocks_per_iter: int, seed: int, q=None, tv_lambda: float = 0.0,
+            tv_iters: int = 20, trace: Optional[list] = None):
+    """One BSGD iteration (Algorithm 1 / 2 / 4) in place on ``st``."""
+    k = st.k
+    R = rng.choose(seed, rng.STREAM_ROWS, k, p.M, rows_per_iter)
+    C = rng.choose(seed, rng.STREAM_BLOCKS, k, p.N, blocks_per_iter)
+    draws = {} if trace is not None else None
+    pairs = [(i, j, rows_for_pair(p, i, j, k, seed, q, draws)) for i in R for j in C]
+    x_frozen = st.x.copy()
+    for i, j, rows in pairs:
+        st.z[j][rows] = p.A_cols[j][rows] @ x_frozen[p.blocks[j]]
+    st.r = y - st.z.sum(axis=0)
+    for i, j, rows in pairs:
+        st.ghat[i][p.blocks[j]] = 2.0 * (p.A_cols[j][rows].T @ st.r[rows])
+    st.gsum = st.ghat.sum(axis=0)
+    for j in C:
+        st.x[p.blocks[j]] += mu * st.gsum[p.blocks[j]]
+    st.k += 1
+    if tv_lambda > 0.0:
+        T = tv_period(p.M, p.N, rows_per_iter, blocks_per_iter)
+        if st.k % T == 0:
+            shape = image_shape(p.g)
+            st.x = fgp_prox(st.x.reshape(shape), mu * tv_lambda, tv_iters).reshape(-1)
+    if trace is not None:
+        trace.append({"k": k, "rows": R, "blocks": C, "draws": draws})
+
+
+def tv_period(M: int, N: int, rows_per_iter: int, blocks_per_iter: int) -> int:
+    """Iterations per effective epoch, round(1/(alpha gamma))."""
+    return max(1, int(round((M * N) / (rows_per_iter * blocks_per_iter))))
+
+
+def image_shape(g: GeometrySpec):
+    return (g.nz, g.ny, g.nx) if g.is_3d else (g.ny, g.nx)
+
+
+def run(p: Problem, y: np.ndarray, mu: float, rows_per_iter: int, blocks_per_iter: int,
+        n_iters: int, seed: int, q=None, x0=None, tv_lambda: float = 0.0, tv_iters: int = 20,
+        trace: Optional[list] = None, callback=None) -> State:
+    st = initial_state(p, y, x0)
+    for _ in range(n_iters):
+        iterate(p, st, y, mu, rows_per_iter, blocks_per_iter, seed, q, tv_lambda, tv_iters, trace)
+        if callback is not None:
+            callback(st)
+    return st
+
+
+def lipschitz(A: sp.spmatrix, iters: int = 30, seed: int = 0) -> float:
+    """sigma_max(A)^2 by power iteration on A^T A."""
+    v = np.random.Generator(np.random.PCG64(seed)).uniform(size=A.shape[1])
+    lam = 0.0
+    for _ in range(iters):
+        w = A.T @ (A @ v)
+        lam = float(np.linalg.norm(w))
+        v = w / lam
+    return lam
+
+
+def ds(x_rec, x_lsq) -> float:
+    """Distance to the least-squares solution (Sec. III-A)."""
+    return float(np.linalg.norm(np.asarray(x_rec) - np.asarray(x_lsq)))
+
+
+def gap(A, y, x) -> float:
+    """GAP = ||y - A x|| (Sec. III-E)."""
+    return float(np.linalg.norm(y - A @ x))
+
+
+def snr_db(x_true, x) -> float:
+    """SNR = 20 log10(||x_true|| / ||x_true - x||) (Sec. III-D)."""
+    return 20.0 * math.log10(np.linalg.norm(x_true) / np.linalg.norm(np.asarray(x_true) - x))

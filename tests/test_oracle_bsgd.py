@@ -1,0 +1,149 @@
+"""Pins of the oracle's BSGD iteration (Algorithms 1, 2, 4) against closed forms and invariants."""
+import math
+
+import numpy as np
+import pytest
+
+from bsgd_inputs.configs import GeometrySpec
+from bsgd_inputs.phantoms import ellipse_phantom_2d, add_gaussian_noise
+from oracle import rng
+from oracle import geometry as geo
+from oracle.bsgd import (Problem, run, initial_state, iterate, lipschitz, ds, im_weights,
+                         quantise, im_table, tv_period)
+from oracle.tv import fgp_prox
+
+
+def _e1_problem(M=4, bx=2, by=1, su=1, im="none"):
+    # the paper's first 2D experiment: 16x16 image, OP = OD = 50, 30 bins, 10 degree steps
+    g = GeometrySpec(kind="fan2d", nx=16, ny=16, nz=1, vx=1.0, vy=1.0, vz=1.0, n_views=36,
+                     angle_span=2 * math.pi, nu=30, nv=1, du=1.0, dv=1.0, sod=50.0, sdd=100.0,
+                     bx=bx, by=by, bz=1, n_row_blocks=M, partition_seed=3, su=su, im_mode=im)
+    return Problem.build(g)
+
+
+@pytest.fixture(scope="module")
+def e1():
+    p = _e1_problem()
+    x_true = ellipse_phantom_2d(16, 16, 6, 5).ravel()
+    y = add_gaussian_noise(p.A @ x_true, 0.05, 9)
+    L = lipschitz(p.A)
+    return p, y, L
+
+
+def test_partitions_cover_everything(e1):
+    p, _, _ = e1
+    views = sorted(v for grp in p.groups for v in grp)
+    assert views == list(range(p.g.n_views))
+    vox = np.sort(np.concatenate(p.blocks))
+    assert np.array_equal(vox, np.arange(p.A.shape[1]))
+
+
+def test_full_sweep_gives_closed_form_gradient(e1):
+    p, y, _ = e1
+    x0 = np.random.Generator(np.random.PCG64(1)).uniform(size=p.A.shape[1])
+    st = initial_state(p, y, x0)
+    iterate(p, st, y, 0.0, p.M, p.N, seed=3)
+    assert np.allclose(st.gsum, 2.0 * p.A.T @ (y - p.A @ x0), rtol=1e-12, atol=1e-12)
+    assert np.array_equal(st.x, x0)
+
+
+@pytest.mark.parametrize("M,bx", [(4, 2), (1, 1)])
+def test_all_blocks_is_gradient_descent(M, bx):
+    p = _e1_problem(M=M, bx=bx)
+    r = np.random.Generator(np.random.PCG64(2))
+    y = p.A @ r.uniform(size=p.A.shape[1]) + r.normal(size=p.A.shape[0])
+    mu = 0.4 / (2 * lipschitz(p.A))
+    st = run(p, y, mu, p.M, p.N, 25, seed=5)
+    x = np.zeros(p.A.shape[1])
+    for _ in range(25):
+        x = x + 2 * mu * (p.A.T @ (y - p.A @ x))
+    assert np.allclose(st.x, x, rtol=1e-11, atol=1e-12)
+
+
+def test_gradient_descent_objective_is_monotone(e1):
+    p, y, L = e1
+    mu = 0.5 / (2 * L)
+    f = []
+    run(p, y, mu, p.M, p.N, 30, seed=1, callback=lambda st: f.append(np.sum((y - p.A @ st.x) ** 2)))
+    assert all(b <= a * (1 + 1e-14) for a, b in zip(f, f[1:]))
+
+
+def test_gamma_one_is_sag_over_row_blocks(e1):
+    p, y, L = e1
+    mu = 0.3 / (2 * L)
+    seed, n_iter = 11, 60
+    st = run(p, y, mu, 1, p.N, n_iter, seed=seed)
+    # an independent SAG: one stored gradient per row block, refreshed at the current x
+    rows = [geo.rays_of_group(p.g, grp) for grp in p.groups]
+    mem = np.zeros((p.M, p.A.shape[1]))
+    x = np.zeros(p.A.shape[1])
+    for k in range(n_iter):
+        (i,) = rng.choose(seed, rng.STREAM_ROWS, k, p.M, 1)
+        Ai = p.A[rows[i]]
+        mem[i] = 2 * Ai.T @ (y[rows[i]] - Ai @ x)
+        x = x + mu * mem.sum(axis=0)
+    assert np.allclose(st.x, x, rtol=1e-10, atol=1e-12)
+
+
+def test_converges_to_least_squares(e1):
+    p, y, L = e1
+    x_lsq = np.linalg.lstsq(p.A.toarray(), y, rcond=None)[0]
+    d = []
+    run(p, y, 0.5 / (2 * L), 1, 1, 3000, seed=7,
+        callback=lambda st: d.append(ds(st.x, x_lsq)) if st.k % 500 == 0 else None)
+    assert d[-1] < 3e-3 * np.linalg.norm(x_lsq)
+    assert d[-1] < 0.1 * d[0] and d[-1] < d[-2] < d[-3]
+
+
+def test_invariants_after_importance_sampled_run():
+    p = _e1_problem(M=3, bx=2, by=2, su=3, im="colnorm")
+    r = np.random.Generator(np.random.PCG64(8))
+    y = p.A @ r.uniform(size=p.A.shape[1])
+    q = im_table(p, "colnorm")
+    trace = []
+    st = run(p, y, 0.3 / (2 * lipschitz(p.A)), 2, 2, 40, seed=4, q=q, trace=trace)
+    assert np.allclose(st.r, y - st.z.sum(axis=0), atol=1e-12)
+    assert np.allclose(st.gsum, st.ghat.sum(axis=0), atol=1e-12)
+    # z entries outside the footprint of their block stay zero
+    for j, J in enumerate(p.blocks):
+        touched = np.asarray(abs(p.A[:, J]).sum(axis=1)).ravel() > 0
+        assert not np.any(st.z[j][~touched])
+    # every draw is a sub-detector with nonzero weight
+    for t in trace:
+        for (v, j), s in t["draws"].items():
+            assert s >= 0 and q[v, s, j] > 0
+
+
+def test_colnorm_weights_partition_frobenius_norm():
+    p = _e1_problem(M=3, bx=2, by=2, su=3, im="colnorm")
+    w = im_weights(p)
+    A2 = p.A.multiply(p.A)
+    assert np.isclose(w.sum(), A2.sum(), rtol=1e-12)
+    per_view_block = w.sum(axis=1)
+    for v in (0, 7, 35):
+        rows = geo.rays_of_view(p.g, v)
+        for j, J in enumerate(p.blocks):
+            assert np.isclose(per_view_block[v, j], A2[rows][:, J].sum(), rtol=1e-12)
+    q = quantise(w)
+    tot = q.sum(axis=1).astype(np.int64)
+    assert np.all(np.abs(tot - (1 << 20)) <= q.shape[1])
+    assert np.all((q > 0) == (w > 0))
+
+
+def test_tv_period_and_zero_lambda(e1):
+    p, y, L = e1
+    assert tv_period(20, 4, 1, 2) == 40 and tv_period(5, 8, 1, 2) == 20
+    a = run(p, y, 0.3 / (2 * L), 1, 1, 20, seed=2)
+    b = run(p, y, 0.3 / (2 * L), 1, 1, 20, seed=2, tv_lambda=0.0)
+    assert np.array_equal(a.x, b.x)
+    # with TV on, the prox fires exactly at multiples of T = M N / (alpha M gamma N)
+    mu, lam = 0.3 / (2 * L), 0.5
+    st = initial_state(p, y)
+    T = tv_period(p.M, p.N, 1, 1)
+    plain = initial_state(p, y)
+    for k in range(T):
+        iterate(p, plain, y, mu, 1, 1, 2)
+        iterate(p, st, y, mu, 1, 1, 2, tv_lambda=lam)
+        if k < T - 1:
+            assert np.array_equal(st.x, plain.x)
+    assert np.allclose(st.x, fgp_prox(plain.x.reshape(16, 16), mu * lam, 20).ravel(), atol=1e-14)
