@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the BSGD hot path on one MI355X.
+
+Workload: 2D fan beam 512x512 (0.5 mm), 720 views over 360 deg, 768 bins (1 mm),
+SOD 500 mm, SDD 1000 mm, 8x8 image blocks, 16 angle subsets, importance sampling
+by block column norms over 4 sub-detectors (BSGD-IM), node count 64 (Eq. 1:
+one row block and all 64 column blocks per iteration). Synthetic seeded data:
+24 random ellipses, Poisson noise at 1e5 incident photons, log transformed.
+
+One step = one effective epoch (16 iterations): forward projection of the sampled
+rays, residual rebuild, matched back projection fused with the block update.
+Throughput = (forward + back projection ray-voxel updates) / s, where an update is
+one nonzero a_ij applied; counts come from the exact per-(view, sub-detector,
+block) nonzero table and the iteration's draws.
+
+Prints one JSON line (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "c2_fan512_im"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def lipschitz_gpu(geom, n_vox, iters=20, seed=0):
+    import torch
+    v = torch.tensor(np.random.Generator(np.random.PCG64(seed)).uniform(size=n_vox), dtype=torch.float32,
+                     device="cuda")
+    lam = 0.0
+    for _ in range(iters):
+        w = geom.back_project(geom.forward_project(v))
+        lam = float(torch.linalg.norm(w.double()))
+        v = (w / lam).contiguous()
+    return lam
+
+
+def schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w):
+    """Per-iteration exact update counts, z writes and selected voxels."""
+    groups = geom.groups()
+    S = spec.su * spec.sv
+    per_it = []
+    for it in range(rows.shape[0]):
+        views = [v for i in rows[it] for v in groups[i]]
+        U = 0
+        zw = 0
+        for a, v in enumerate(views):
+            for b, j in enumerate(blocks[it]):
+                s = int(draws[it, a, b])
+                if s == -1:
+                    continue
+                if s == -2:
+                    U += int(nnz_tab[v, :, j].sum())
+                    u0, u1, v0, v1 = fp_rect[v, j]
+                    zw += max(0, u1 - u0) * max(0, v1 - v0)
+                else:
+                    U += int(nnz_tab[v, s, j])
+                    u0, u1, v0, v1 = fp_rect[v, j]
+                    k0, k1 = subdet_w[s]
+                    zw += max(0, min(u1, k1) - max(u0, k0)) * max(0, v1 - v0)
+        per_it.append((U, zw, len(views)))
+    return per_it
+
+
+def cpu_baseline(spec, x, budget_s=12.0):
+    """The FP64 oracle's matrix-free FP + BP on the rays of a bounded set of views."""
+    from oracle.cfast import Projector
+    from oracle import geometry as ogeo
+    threads = max(1, min(16, os.cpu_count() or 1))
+    order = np.random.Generator(np.random.PCG64(77)).permutation(spec.n_views)
+
+    def run(nv):
+        rays = np.concatenate([ogeo.rays_of_view(spec, int(v)) for v in order[:nv]])
+        P = Projector(spec, rays=rays)
+        t0 = time.perf_counter()
+        y = P.fp(x, threads=threads)
+        t1 = time.perf_counter()
+        P.bp(y, threads=threads)
+        t2 = time.perf_counter()
+        return 2 * P.last_nnz, t2 - t0
+
+    u, t = run(4)
+    n_views = int(min(spec.n_views, max(4, round(4 * budget_s / max(t, 1e-3)))))
+    u, t = run(n_views)
+    return {"value": u / t, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP+BP (FP64, matrix-free Siddon, {threads} threads) of all rays of {n_views} of "
+                      f"{spec.n_views} views over the full 512x512 image: {u:.3e} updates in {t:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="untimed extra steps with per-kernel events (0 = events on in the timed region)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the hot path has no multi-GPU mode)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from bsgd_inputs.configs import workload
+    from bsgd_inputs.phantoms import phantom_for, poisson_log_noise
+    from paper_1903_11874_amd import Geometry, Solver
+
+    wl = workload(WORKLOAD)
+    spec = wl.geometry
+    dev = torch.device("cuda:0")
+    log("geometry")
+    geom = Geometry(spec)
+    n_vox = spec.nx * spec.ny * spec.nz
+    x_true = phantom_for(spec, wl.n_shapes, wl.phantom_seed)
+    xt = torch.tensor(x_true, dtype=torch.float32, device=dev)
+    y_clean = geom.forward_project(xt).double().cpu().numpy()
+    y = poisson_log_noise(y_clean, wl.noise_level, wl.noise_seed)
+    yd = torch.tensor(y, dtype=torch.float32, device=dev)
+    L = lipschitz_gpu(geom, n_vox)
+    mu = wl.solver.mu_scale / (2.0 * L)
+    log(f"L = {L:.4e}, mu = {mu:.4e}")
+
+    x = torch.zeros(n_vox, dtype=torch.float32, device=dev)
+    solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed)
+    T = solver.epoch_iters
+    log(f"alpha M = {solver.rows_per_iter}, gamma N = {solver.blocks_per_iter}, epoch = {T} iterations")
+
+    for _ in range(args.warmup):
+        solver.step(T)
+    r0 = solver.step(0, residual=True)
+    torch.cuda.synchronize()
+
+    prof_in_timed = args.profile_steps == 0
+    solver.set_profiling(prof_in_timed)
+    base_times = solver.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(T * args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    rows, blocks, draws = solver.last_schedule()
+    times = solver.kernel_times()
+    if not prof_in_timed:
+        solver.set_profiling(True)
+        solver.step(T * args.profile_steps)
+        times_p = solver.kernel_times()
+        times = {k: (times_p[k][0] - times[k][0], times_p[k][1] - times[k][1]) for k in times}
+        prow, pblk, pdr = solver.last_schedule()
+    else:
+        times = {k: (times[k][0] - base_times[k][0], times[k][1] - base_times[k][1]) for k in times}
+        prow, pblk, pdr = rows, blocks, draws
+    r1 = solver.step(0, residual=True)
+
+    nnz_tab = geom.table("nnz")
+    fp_rect = geom.table("footprint")
+    subdet_w = [((a * spec.nu) // spec.su, ((a + 1) * spec.nu) // spec.su) for a in range(spec.su)]
+    per_it = schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w)
+    U_fp = sum(p[0] for p in per_it)
+    updates = 2 * U_fp
+    value = updates / elapsed
+
+    # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
+    per_it_p = schedule_counts(geom, spec, prow, pblk, pdr, nnz_tab, fp_rect, subdet_w)
+    n_it = len(per_it_p)
+    vsel = n_vox * solver.blocks_per_iter // geom.info["n_blocks"]
+    bytes_fp = sum(4 * u + 4 * zw for u, zw, _ in per_it_p) / n_it
+    bytes_bp = sum(4 * u for u, _, _ in per_it_p) / n_it + vsel * (8 * solver.rows_per_iter + 16)
+    avg_ms = {k: (ms / n if n else 0.0) for k, (ms, n) in times.items()}
+    dominant = max(("forward_project", "back_project_step"), key=lambda k: times[k][0])
+    alg_bytes = bytes_fp if dominant == "forward_project" else bytes_bp
+    achieved = alg_bytes / (avg_ms[dominant] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms[dominant]}
+
+    out = {
+        "metric": "FP+BP ray-voxel updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded random-ellipse phantom, Poisson noise)",
+        "config": {"workload": "2D fan-beam BSGD-IM 512x512 @0.5 mm, 720 views/360 deg, 768 bins @1 mm, "
+                               "SOD 500 SDD 1000, 8x8 blocks, 16 angle subsets, 4 sub-detectors, node count 64",
+                   "rows_per_iter": solver.rows_per_iter, "blocks_per_iter": solver.blocks_per_iter,
+                   "iters_per_step": T, "step": "one effective epoch"},
+        "roofline": roofline,
+        "kernels_avg_ms": avg_ms,
+        "kernel_launches": {k: n for k, (ms, n) in times.items()},
+        "profiled_in_timed_region": prof_in_timed,
+        "residual_norm": {"before": r0, "after": r1},
+        "updates_per_step": updates / args.steps,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(spec, x_true)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * bsgd.h - C ABI of the MI355X block stochastic gradient descent (BSGD) library.
+ *
+ * The operations follow Gao, Biguri, Blumensath, "Block stochastic gradient
+ * descent for large-scale tomographic reconstruction in a parallel network":
+ *
+ *   y = A x + e,  min_x 1/2 ||y - A x||^2                     (Sec. I, Eqs. (yax), (min))
+ *   a_ij = length of ray i inside voxel j (Siddon)              (Sec. I, after Eq. (yax))
+ *   A is never stored; A x and A^T r are computed on the fly    (Sec. I)
+ *   A partitioned into M row blocks I_i and N column blocks J_j (Sec. II, Eq. (e1))
+ *   BSGD / BSGD-IM / BSGD-TV iterations                         (Algorithms 1, 2, 4)
+ *   alpha, gamma from the node count                            (Eq. 1)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units are millimetres; A's entries are lengths in mm. Device arrays are FP32.
+ * The volume is centred at the origin, voxel (i,j,k) centred at
+ * ((i-(nx-1)/2) vx, (j-(ny-1)/2) vy, (k-(nz-1)/2) vz), stored [z][y][x] (x fastest).
+ * View m has angle angles_rad[m]; the source is at sod (cos t, sin t, 0), the flat
+ * detector is centred at -(sdd-sod)(cos t, sin t, 0) with u-axis (-sin t, cos t, 0)
+ * and v-axis (0,0,1); pixel (k,l) is centred at u=(k-(nu-1)/2)du, v=(l-(nv-1)/2)dv.
+ * Parallel beam (2D) ray k passes through u_k (-sin t, cos t) along (cos t, sin t).
+ * Projections are stored [view][v][u] (u fastest). 2D kinds need nz = nv = 1.
+ * Column block j = (tz by + ty) bx + tx covers the tile [floor(t n/b), floor((t+1) n/b))
+ * along each axis. Row blocks are groups of whole views: a permutation of the views
+ * drawn from partition_seed is cut into M consecutive groups (the first n_views mod M
+ * one view longer), views ascending within a group.
+ *
+ * Ownership: the caller owns every pointer it passes (device pointers for x, y, r;
+ * host pointers where stated) and the stream; the library owns geometry tables and
+ * solver state, allocates them with hipMalloc and frees them in *_destroy.
+ * Calls are asynchronous on the given stream (a hipStream_t, NULL = default stream)
+ * unless they return host values, which synchronise that stream.
+ * Errors: every call returns a status; no exception crosses the ABI. Invalid
+ * arguments return BSGD_E_INVALID_ARG before any device work is enqueued.
+ * bsgd_last_error() gives a thread-local message for the last non-OK status.
+ * Thread safety: distinct objects may be used from distinct threads; one object
+ * must not be used concurrently.
+ */
+#ifndef BSGD_H
+#define BSGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSGD_OK = 0,
+    BSGD_E_INVALID_ARG = 1,
+    BSGD_E_UNSUPPORTED = 2,
+    BSGD_E_OUT_OF_MEMORY = 3,
+    BSGD_E_DEVICE = 4,
+    BSGD_E_DIVERGED = 5,
+    BSGD_E_STATE = 6
+} bsgd_status;
+
+typedef enum { BSGD_PARALLEL_2D = 0, BSGD_FAN_FLAT_2D = 1, BSGD_CONE_FLAT_3D = 2 } bsgd_kind;
+
+/* Sub-detector sampling of Algorithm 2 (BSGD-IM, Fig. 2).
+ * NONE    : plain BSGD, every ray of the selected views is used.
+ * COLNORM : probability of sub-detector s for (view v, block j) proportional to
+ *           ||A[rows of s in v, J_j]||_F^2 (the denser sub-matrix is the likelier,
+ *           Sec. II-A), quantised to integers q = round(2^20 w / sum w) (>= 1 if w > 0).
+ * UNIFORM : every sub-detector equally likely (BSGD-RAN, Sec. III-E-3). */
+typedef enum { BSGD_IM_NONE = 0, BSGD_IM_COLNORM = 1, BSGD_IM_UNIFORM = 3 } bsgd_im_mode;
+
+typedef struct {
+    int32_t kind;                 /* bsgd_kind */
+    int32_t nx, ny, nz;           /* voxels per axis (nz = 1 in 2D) */
+    double vx, vy, vz;            /* voxel size, mm */
+    int32_t n_views;
+    const double* angles_rad;     /* host [n_views], copied */
+    int32_t nu, nv;               /* detector pixels (nv = 1 in 2D) */
+    double du, dv;                /* detector pitch, mm */
+    double sod, sdd;              /* source-to-centre, source-to-detector, mm (fan/cone) */
+    int32_t bx, by, bz;           /* column-block tiling, N = bx by bz (bz = 1 in 2D) */
+    int32_t n_row_blocks;         /* M */
+    uint64_t partition_seed;      /* seed of the view-to-row-block permutation */
+    int32_t su, sv;               /* sub-detectors per view (IM), S = su sv <= 16 */
+    int32_t im_mode;              /* bsgd_im_mode */
+    const uint32_t* im_table;     /* optional host [n_views][S][N] sampling weights; NULL = computed */
+} bsgd_geometry_desc;
+
+typedef struct bsgd_geometry bsgd_geometry;
+typedef struct bsgd_solver bsgd_solver;
+
+/* Validate the descriptor, build the partitions, the per-(view, block) detector
+ * footprints and, on the device, the per-(view, sub-detector, block) squared
+ * norms and nonzero counts of A (the IM weights; computed for every mode).
+ * Synchronises `stream` once. *out is NULL on failure. */
+bsgd_status bsgd_geometry_create(const bsgd_geometry_desc* desc, void* stream, bsgd_geometry** out);
+void bsgd_geometry_destroy(bsgd_geometry* geom);
+
+typedef struct {
+    int64_t n_rays;          /* n_views nv nu */
+    int64_t n_voxels;        /* nx ny nz */
+    int32_t n_blocks;        /* N */
+    int32_t n_row_blocks;    /* M */
+    int32_t n_subdet;        /* S */
+    int32_t max_group_views; /* views in the largest row block */
+    int64_t z_floats;        /* floats of compact z storage (sum of footprint areas) */
+    int64_t nnz;             /* nonzeros of A (segments of positive FP32 length) */
+} bsgd_geometry_info;
+
+bsgd_status bsgd_geometry_get_info(const bsgd_geometry* geom, bsgd_geometry_info* out);
+
+/* Host copies of geometry tables (out must hold `bytes`):
+ * VIEW_ORDER  int32 [n_views]          views of row block 0, then 1, ... (ascending in a group)
+ * GROUP_START int32 [M + 1]            offsets of each row block into VIEW_ORDER
+ * IM_WEIGHTS  double [n_views][S][N]   ||A[rows of sub-detector s of view v, J_j]||_F^2
+ * IM_TABLE    uint32 [n_views][S][N]   quantised sampling table in use
+ * NNZ         int64 [n_views][S][N]    nonzeros of each such sub-matrix
+ * FOOTPRINT   int32 [n_views][N][4]    detector rectangle [u0, u1) x [v0, v1) of block j */
+typedef enum {
+    BSGD_TABLE_VIEW_ORDER = 0,
+    BSGD_TABLE_GROUP_START = 1,
+    BSGD_TABLE_IM_WEIGHTS = 2,
+    BSGD_TABLE_IM_TABLE = 3,
+    BSGD_TABLE_NNZ = 4,
+    BSGD_TABLE_FOOTPRINT = 5
+} bsgd_table;
+bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* out, size_t bytes);
+
+#define BSGD_ACCUMULATE 1u
+
+/* Forward projection (Sec. I: FP = A x):
+ *   y[a][l][k] (= or +=) sum_{j in blocks} (A_{views[a]}^{J_j} x_{J_j})[l][k]
+ * x: device [nz][ny][nx]; y: device [n_sel][nv][nu] with n_sel = n_views_sel, or
+ * all views in index order when views == NULL. views: host int32 list (copied).
+ * block = -1 projects the whole volume, otherwise only column block `block`.
+ * flags: BSGD_ACCUMULATE adds into y instead of overwriting. */
+bsgd_status bsgd_forward_project(const bsgd_geometry* geom, const float* x, float* y,
+                                 const int32_t* views, int32_t n_views_sel, int32_t block,
+                                 uint32_t flags, void* stream);
+
+/* Matched back projection (Sec. I: BP = A^T r), same lengths as the forward projection:
+ *   x[J] (= or +=) scale * (A_{views}^{J})^T y
+ * for every voxel of `block` (all voxels when block = -1); voxels outside J are untouched.
+ * y: device [n_sel][nv][nu] as for bsgd_forward_project. */
+bsgd_status bsgd_back_project(const bsgd_geometry* geom, const float* y, float* x,
+                              const int32_t* views, int32_t n_views_sel, int32_t block,
+                              float scale, uint32_t flags, void* stream);
+
+/* Solver options.
+ * rows_per_iter, blocks_per_iter: alpha M and gamma N of Algorithm 1. If both are 0,
+ *   node_count P gives them through Eq. 1: gamma = min(1, P/N), alpha = P/(M N gamma)
+ *   (non-integer results are rejected).
+ * mu: the paper's step length; the update is g = 2 A^T r, x += mu g (Eq. (SGDITE)).
+ * seed: selection and importance-sampling streams (counter-based, see DESIGN notes).
+ * tv_lambda > 0 enables Algorithm 4: every tv_every iterations (0 = round(1/(alpha gamma)))
+ *   x <- argmin_t ||t - x||^2 + 2 mu lambda TV(t) by tv_inner_iters fast-gradient-projection
+ *   steps (isotropic TV, backward differences, zero difference across the low boundary).
+ * max_effective_epochs, tol: bsgd_solve stops after max_effective_epochs effective epochs
+ *   (one epoch = round(1/(alpha gamma)) iterations), or earlier when tol > 0 and the
+ *   relative normal-equation residual ||A^T(y - A x)|| / ||A^T y|| <= tol, checked
+ *   every check_every epochs (0 = every epoch). */
+typedef struct {
+    int32_t rows_per_iter;
+    int32_t blocks_per_iter;
+    int32_t node_count;
+    int32_t tv_inner_iters;
+    double mu;
+    uint64_t seed;
+    double tv_lambda;
+    int32_t tv_every;
+    int32_t max_effective_epochs;
+    double tol;
+    int32_t check_every;
+    int32_t reserved;
+} bsgd_options;
+
+/* Create a solver for y (device [n_views][nv][nu], must stay valid and unchanged while
+ * the solver lives) and x (device [nz][ny][nx], the initial image, updated in place by
+ * bsgd_step). State z = 0, g_hat = 0, g = 0 (Algorithm 1, initialisation). */
+bsgd_status bsgd_solver_create(const bsgd_geometry* geom, const float* y, float* x,
+                               const bsgd_options* opt, void* stream, bsgd_solver** out);
+
+/* Run n_iters iterations of Algorithm 1/2/4 on the solver's stream. If resid_norm_out
+ * is not NULL, synchronise and return ||y - sum_j z^j|| (the maintained residual r of
+ * Algorithm 1); a non-finite value returns BSGD_E_DIVERGED. */
+bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_norm_out);
+
+/* Iterations done so far, and alpha M, gamma N, iterations per effective epoch. */
+bsgd_status bsgd_solver_counts(const bsgd_solver* s, int64_t* iters_done, int32_t* rows_per_iter,
+                               int32_t* blocks_per_iter, int32_t* epoch_iters);
+
+/* Host copy of the schedule of the last bsgd_step call (synchronises):
+ * rows [n][rows_per_iter], blocks [n][blocks_per_iter] (ascending), and the drawn
+ * sub-detectors draws [n][max_group_views * rows_per_iter][blocks_per_iter]
+ * (int16; view slot order = row blocks in `rows` order, views ascending in each;
+ * -1 = view skipped, -2 = no sampling). Any output may be NULL. n = iterations of that call. */
+bsgd_status bsgd_solver_last_schedule(const bsgd_solver* s, int32_t* n_out, int32_t* rows,
+                                      int32_t* blocks, int16_t* draws, size_t draws_bytes);
+
+/* Copy solver state to caller device memory: which = 0 g [c], 1 g_hat [M][c], 2 z (compact, z_floats). */
+bsgd_status bsgd_solver_state(const bsgd_solver* s, int32_t which, float* out, size_t bytes);
+
+/* Per-kernel time accounting with HIP events on the solver's stream (off by default).
+ * kernel ids: 0 forward projection, 1 residual rebuild, 2 back projection + step,
+ * 3 TV prox, 4 sampling draws. ms_out[5] total milliseconds, launches_out[5] counts. */
+bsgd_status bsgd_solver_set_profiling(bsgd_solver* s, int32_t on);
+bsgd_status bsgd_solver_kernel_times(bsgd_solver* s, double* ms_out, int64_t* launches_out);
+
+void bsgd_solver_destroy(bsgd_solver* s);
+
+/* Create, iterate to the stopping rule, write x, destroy. Synchronises. */
+bsgd_status bsgd_solve(const bsgd_geometry* geom, const float* y, float* x, const bsgd_options* opt,
+                       void* stream, int32_t* iters_out, double* resid_norm_out);
+
+const char* bsgd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSGD_H */

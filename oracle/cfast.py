@@ -65,9 +65,7 @@ class Projector:
         self.n = np.array(grid.n, dtype=np.int64)
         self.lo = np.array(grid.lo, dtype=np.float64)
         self.v = np.array(grid.v, dtype=np.float64)
-        p0, p1 = ray_endpoints(g)
-        if rays is not None:
-            p0, p1 = p0[rays], p1[rays]
+        p0, p1 = ray_endpoints(g, rays)
         self.p0 = np.ascontiguousarray(p0)
         self.p1 = np.ascontiguousarray(p1)
         self.n_rays = self.p0.shape[0]

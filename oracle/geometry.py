@@ -58,38 +58,30 @@ def detector_v(g: GeometrySpec) -> np.ndarray:
     return (np.arange(g.nv) - (g.nv - 1) / 2.0) * g.dv
 
 
-def ray_endpoints(g: GeometrySpec):
-    """Return (p0, p1), each [n_rays, dim] float64, rays ordered [view][v][u]."""
-    th = g.angles()
-    us = detector_u(g)
-    p0s, p1s = [], []
+def ray_endpoints(g: GeometrySpec, rays=None):
+    """Return (p0, p1), each [n, dim] float64, for all rays ([view][v][u] order) or a subset."""
+    per_view = g.nu * g.nv
+    idx = np.arange(g.n_views * per_view) if rays is None else np.asarray(rays, dtype=np.int64)
+    m = idx // per_view
+    l = (idx // g.nu) % g.nv
+    k = idx % g.nu
+    th = g.angles()[m]
+    c, s = np.cos(th), np.sin(th)
+    u = (k - (g.nu - 1) / 2.0) * g.du
     if g.kind == "parallel2d":
         grid = grid_of(g)
         reach = math.hypot(*[ni * vi for ni, vi in zip(grid.n, grid.v)]) + 10.0
-        for t in th:
-            c, s = math.cos(t), math.sin(t)
-            q = np.stack([-us * s, us * c], axis=1)
-            e = np.array([c, s])
-            p0s.append(q - reach * e)
-            p1s.append(q + reach * e)
-    elif g.kind == "fan2d":
-        for t in th:
-            c, s = math.cos(t), math.sin(t)
-            src = np.array([g.sod * c, g.sod * s])
-            det = np.stack([-(g.sdd - g.sod) * c - us * s, -(g.sdd - g.sod) * s + us * c], axis=1)
-            p0s.append(np.repeat(src[None, :], g.nu, axis=0))
-            p1s.append(det)
-    else:
-        vs = detector_v(g)
-        for t in th:
-            c, s = math.cos(t), math.sin(t)
-            src = np.array([g.sod * c, g.sod * s, 0.0])
-            V, U = np.meshgrid(vs, us, indexing="ij")  # [nv][nu]
-            det = np.stack([-(g.sdd - g.sod) * c - U * s, -(g.sdd - g.sod) * s + U * c, V], axis=-1)
-            det = det.reshape(-1, 3)
-            p0s.append(np.repeat(src[None, :], det.shape[0], axis=0))
-            p1s.append(det)
-    return np.concatenate(p0s), np.concatenate(p1s)
+        q = np.stack([-u * s, u * c], axis=1)
+        e = np.stack([c, s], axis=1)
+        return q - reach * e, q + reach * e
+    if g.kind == "fan2d":
+        src = np.stack([g.sod * c, g.sod * s], axis=1)
+        det = np.stack([-(g.sdd - g.sod) * c - u * s, -(g.sdd - g.sod) * s + u * c], axis=1)
+        return src, det
+    v = (l - (g.nv - 1) / 2.0) * g.dv
+    src = np.stack([g.sod * c, g.sod * s, np.zeros_like(c)], axis=1)
+    det = np.stack([-(g.sdd - g.sod) * c - u * s, -(g.sdd - g.sod) * s + u * c, v], axis=1)
+    return src, det
 
 
 def tile_bounds(n: int, b: int) -> List[tuple]:

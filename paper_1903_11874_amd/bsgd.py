@@ -1,0 +1,332 @@
+"""Python binding of the BSGD C ABI (include/bsgd.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+libbsgd.so. PyTorch supplies device memory and the current stream. The binding
+refuses to work when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsgd.so")
+
+BSGD_OK = 0
+STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_UNSUPPORTED", 3: "E_OUT_OF_MEMORY", 4: "E_DEVICE",
+                5: "E_DIVERGED", 6: "E_STATE"}
+KIND = {"parallel2d": 0, "fan2d": 1, "cone3d": 2}
+IM_MODE = {"none": 0, "colnorm": 1, "uniform": 3}
+TABLE = {"view_order": 0, "group_start": 1, "im_weights": 2, "im_table": 3, "nnz": 4, "footprint": 5}
+KERNELS = ("forward_project", "residual", "back_project_step", "tv_prox", "draws")
+ACCUMULATE = 1
+
+
+class BsgdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bsgd {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GeometryDesc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("vx", ctypes.c_double), ("vy", ctypes.c_double), ("vz", ctypes.c_double),
+        ("n_views", ctypes.c_int32), ("angles_rad", ctypes.POINTER(ctypes.c_double)),
+        ("nu", ctypes.c_int32), ("nv", ctypes.c_int32), ("du", ctypes.c_double), ("dv", ctypes.c_double),
+        ("sod", ctypes.c_double), ("sdd", ctypes.c_double),
+        ("bx", ctypes.c_int32), ("by", ctypes.c_int32), ("bz", ctypes.c_int32),
+        ("n_row_blocks", ctypes.c_int32), ("partition_seed", ctypes.c_uint64),
+        ("su", ctypes.c_int32), ("sv", ctypes.c_int32), ("im_mode", ctypes.c_int32),
+        ("im_table", ctypes.POINTER(ctypes.c_uint32)),
+    ]
+
+
+class GeometryInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_rays", ctypes.c_int64), ("n_voxels", ctypes.c_int64), ("n_blocks", ctypes.c_int32),
+        ("n_row_blocks", ctypes.c_int32), ("n_subdet", ctypes.c_int32), ("max_group_views", ctypes.c_int32),
+        ("z_floats", ctypes.c_int64), ("nnz", ctypes.c_int64),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("rows_per_iter", ctypes.c_int32), ("blocks_per_iter", ctypes.c_int32), ("node_count", ctypes.c_int32),
+        ("tv_inner_iters", ctypes.c_int32), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("tv_lambda", ctypes.c_double), ("tv_every", ctypes.c_int32), ("max_effective_epochs", ctypes.c_int32),
+        ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+EXPORTED = (
+    "bsgd_geometry_create", "bsgd_geometry_destroy", "bsgd_geometry_get_info", "bsgd_geometry_table",
+    "bsgd_forward_project", "bsgd_back_project", "bsgd_solver_create", "bsgd_step", "bsgd_solver_counts",
+    "bsgd_solver_last_schedule", "bsgd_solver_state", "bsgd_solver_set_profiling", "bsgd_solver_kernel_times",
+    "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error",
+)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbsgd.so (raises if it has not been built) and declare the signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1903_11874_amd.build`")
+    L = ctypes.CDLL(path)
+    P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "bsgd_geometry_create": (i32, [ctypes.POINTER(GeometryDesc), P, ctypes.POINTER(P)]),
+        "bsgd_geometry_destroy": (None, [P]),
+        "bsgd_geometry_get_info": (i32, [P, ctypes.POINTER(GeometryInfo)]),
+        "bsgd_geometry_table": (i32, [P, i32, P, ctypes.c_size_t]),
+        "bsgd_forward_project": (i32, [P, P, P, P, i32, i32, u32, P]),
+        "bsgd_back_project": (i32, [P, P, P, P, i32, i32, ctypes.c_float, u32, P]),
+        "bsgd_solver_create": (i32, [P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(P)]),
+        "bsgd_step": (i32, [P, i32, ctypes.POINTER(ctypes.c_double)]),
+        "bsgd_solver_counts": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32)]),
+        "bsgd_solver_last_schedule": (i32, [P, ctypes.POINTER(i32), P, P, P, ctypes.c_size_t]),
+        "bsgd_solver_state": (i32, [P, i32, P, ctypes.c_size_t]),
+        "bsgd_solver_set_profiling": (i32, [P, i32]),
+        "bsgd_solver_kernel_times": (i32, [P, P, P]),
+        "bsgd_solver_destroy": (None, [P]),
+        "bsgd_solve": (i32, [P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(i32),
+                             ctypes.POINTER(ctypes.c_double)]),
+        "bsgd_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != BSGD_OK:
+        msg = load_library().bsgd_last_error()
+        raise BsgdError(status, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def _dev_ptr(t, dtype_name="float32"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _views_arg(views):
+    if views is None:
+        return None, 0, None
+    arr = np.ascontiguousarray(np.asarray(views, dtype=np.int32))
+    return arr.ctypes.data_as(ctypes.c_void_p), int(arr.size), arr
+
+
+class Geometry:
+    """A scan geometry, its block partition and sampling tables (bsgd_geometry)."""
+
+    def __init__(self, spec, im_table: Optional[np.ndarray] = None, stream=None):
+        self.spec = spec
+        lib = load_library()
+        angles = np.ascontiguousarray(spec.angles(), dtype=np.float64)
+        self._angles = angles
+        d = GeometryDesc()
+        d.kind = KIND[spec.kind]
+        d.nx, d.ny, d.nz = spec.nx, spec.ny, spec.nz
+        d.vx, d.vy, d.vz = spec.vx, spec.vy, spec.vz
+        d.n_views = spec.n_views
+        d.angles_rad = angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.nu, d.nv, d.du, d.dv = spec.nu, spec.nv, spec.du, spec.dv
+        d.sod, d.sdd = spec.sod, spec.sdd
+        d.bx, d.by, d.bz = spec.bx, spec.by, spec.bz
+        d.n_row_blocks = spec.n_row_blocks
+        d.partition_seed = spec.partition_seed
+        d.su, d.sv = spec.su, spec.sv
+        d.im_mode = IM_MODE[spec.im_mode] if spec.im_mode in IM_MODE else 2
+        self._im = None
+        if im_table is not None:
+            self._im = np.ascontiguousarray(im_table, dtype=np.uint32)
+            d.im_table = self._im.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        h = ctypes.c_void_p()
+        _check(lib.bsgd_geometry_create(ctypes.byref(d), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        info = GeometryInfo()
+        _check(lib.bsgd_geometry_get_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in GeometryInfo._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bsgd_geometry_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def table(self, name: str) -> np.ndarray:
+        g = self.spec
+        V, S, N, M = g.n_views, g.su * g.sv, g.n_blocks, g.n_row_blocks
+        shapes = {"view_order": ((V,), np.int32), "group_start": ((M + 1,), np.int32),
+                  "im_weights": ((V, S, N), np.float64), "im_table": ((V, S, N), np.uint32),
+                  "nnz": ((V, S, N), np.int64), "footprint": ((V, N, 4), np.int32)}
+        shape, dt = shapes[name]
+        out = np.zeros(shape, dtype=dt)
+        _check(load_library().bsgd_geometry_table(self._h, TABLE[name], out.ctypes.data_as(ctypes.c_void_p),
+                                                  out.nbytes))
+        return out
+
+    def groups(self):
+        order, start = self.table("view_order"), self.table("group_start")
+        return [list(order[start[i]:start[i + 1]]) for i in range(len(start) - 1)]
+
+    def forward_project(self, x, views: Optional[Sequence[int]] = None, block: int = -1, out=None,
+                        accumulate: bool = False, stream=None):
+        import torch
+        g = self.spec
+        n_sel = g.n_views if views is None else len(views)
+        if x.numel() != g.nx * g.ny * g.nz:
+            raise ValueError("x has the wrong size")
+        if out is None:
+            out = torch.zeros(n_sel * g.nv * g.nu, device=x.device, dtype=torch.float32)
+        elif out.numel() != n_sel * g.nv * g.nu:
+            raise ValueError("out has the wrong size")
+        vp, nv, keep = _views_arg(views)
+        _check(load_library().bsgd_forward_project(self._h, _dev_ptr(x), _dev_ptr(out), vp,
+                                                   nv if views is not None else n_sel, block,
+                                                   ACCUMULATE if accumulate else 0, _stream_ptr(stream)))
+        return out
+
+    def back_project(self, y, views: Optional[Sequence[int]] = None, block: int = -1, scale: float = 1.0,
+                     out=None, accumulate: bool = False, stream=None):
+        import torch
+        g = self.spec
+        n_sel = g.n_views if views is None else len(views)
+        if y.numel() != n_sel * g.nv * g.nu:
+            raise ValueError("y has the wrong size")
+        if out is None:
+            out = torch.zeros(g.nx * g.ny * g.nz, device=y.device, dtype=torch.float32)
+        elif out.numel() != g.nx * g.ny * g.nz:
+            raise ValueError("out has the wrong size")
+        vp, nv, keep = _views_arg(views)
+        _check(load_library().bsgd_back_project(self._h, _dev_ptr(y), _dev_ptr(out), vp,
+                                                nv if views is not None else n_sel, block, float(scale),
+                                                ACCUMULATE if accumulate else 0, _stream_ptr(stream)))
+        return out
+
+
+def make_options(rows_per_iter=0, blocks_per_iter=0, node_count=0, mu=0.0, seed=0, tv_lambda=0.0,
+                 tv_inner_iters=20, tv_every=0, max_effective_epochs=0, tol=0.0, check_every=0) -> Options:
+    o = Options()
+    o.rows_per_iter, o.blocks_per_iter, o.node_count = rows_per_iter, blocks_per_iter, node_count
+    o.tv_inner_iters, o.mu, o.seed, o.tv_lambda, o.tv_every = tv_inner_iters, mu, seed, tv_lambda, tv_every
+    o.max_effective_epochs, o.tol, o.check_every, o.reserved = max_effective_epochs, tol, check_every, 0
+    return o
+
+
+class Solver:
+    """BSGD state for one reconstruction (bsgd_solver); x is updated in place."""
+
+    def __init__(self, geom: Geometry, y, x, stream=None, **opts):
+        self.geom = geom
+        self.y, self.x = y, x
+        self._stream = stream
+        self.options = make_options(**opts)
+        h = ctypes.c_void_p()
+        _check(load_library().bsgd_solver_create(geom.handle, _dev_ptr(y), _dev_ptr(x), ctypes.byref(self.options),
+                                                 _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        k, r, b, t = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().bsgd_solver_counts(h, ctypes.byref(k), ctypes.byref(r), ctypes.byref(b),
+                                                 ctypes.byref(t)))
+        self.rows_per_iter, self.blocks_per_iter, self.epoch_iters = r.value, b.value, t.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bsgd_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def iterations(self) -> int:
+        k = ctypes.c_int64()
+        _check(load_library().bsgd_solver_counts(self._h, ctypes.byref(k), None, None, None))
+        return k.value
+
+    def step(self, n_iters: int = 1, residual: bool = False):
+        out = ctypes.c_double() if residual else None
+        _check(load_library().bsgd_step(self._h, int(n_iters), ctypes.byref(out) if residual else None))
+        return out.value if residual else None
+
+    def last_schedule(self):
+        lib = load_library()
+        n = ctypes.c_int32()
+        _check(lib.bsgd_solver_last_schedule(self._h, ctypes.byref(n), None, None, None, 0))
+        n = n.value
+        maxv = self.rows_per_iter * self.geom.info["max_group_views"]
+        rows = np.zeros((n, self.rows_per_iter), dtype=np.int32)
+        blocks = np.zeros((n, self.blocks_per_iter), dtype=np.int32)
+        draws = np.zeros((n, maxv, self.blocks_per_iter), dtype=np.int16)
+        _check(lib.bsgd_solver_last_schedule(self._h, None, rows.ctypes.data_as(ctypes.c_void_p),
+                                             blocks.ctypes.data_as(ctypes.c_void_p),
+                                             draws.ctypes.data_as(ctypes.c_void_p), draws.nbytes))
+        return rows, blocks, draws
+
+    def state(self, which: str):
+        import torch
+        idx = {"g": 0, "ghat": 1, "z": 2}[which]
+        g = self.geom.spec
+        n = {0: g.nx * g.ny * g.nz, 1: g.n_row_blocks * g.nx * g.ny * g.nz, 2: self.geom.info["z_floats"]}[idx]
+        out = torch.empty(max(n, 1), device=self.x.device, dtype=torch.float32)
+        _check(load_library().bsgd_solver_state(self._h, idx, _dev_ptr(out), out.numel() * 4))
+        return out[:n]
+
+    def set_profiling(self, on: bool = True):
+        _check(load_library().bsgd_solver_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        ms = np.zeros(5, dtype=np.float64)
+        n = np.zeros(5, dtype=np.int64)
+        _check(load_library().bsgd_solver_kernel_times(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                                       n.ctypes.data_as(ctypes.c_void_p)))
+        return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(KERNELS)}
+
+
+def solve(geom: Geometry, y, x, stream=None, **opts):
+    """Run the solver to its stopping rule (bsgd_solve); returns (iterations, ||r||)."""
+    o = make_options(**opts)
+    it, rn = ctypes.c_int32(), ctypes.c_double()
+    _check(load_library().bsgd_solve(geom.handle, _dev_ptr(y), _dev_ptr(x), ctypes.byref(o), _stream_ptr(stream),
+                                     ctypes.byref(it), ctypes.byref(rn)))
+    return it.value, rn.value

@@ -1,0 +1,1032 @@
+// Host runtime and C ABI of the BSGD library: geometry tables (partitions,
+// detector footprints, block-local ray anchors, importance-sampling tables),
+// solver state, the per-iteration schedule and kernel sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bsgd.h"
+#include "bsgd_device.h"
+#include "bsgd_kernels.h"
+
+using namespace bsgd;
+
+// ------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static bsgd_status fail(bsgd_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? BSGD_E_OUT_OF_MEMORY : BSGD_E_DEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                              \
+    } while (0)
+
+extern "C" const char* bsgd_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------ counter-based streams (host)
+
+namespace {
+
+constexpr uint64_t GOLDEN = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t STREAM_PARTITION = 1, STREAM_ROWS = 2, STREAM_BLOCKS = 3;
+
+uint64_t mix64h(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t hash_keys(uint64_t seed, uint64_t stream, std::initializer_list<uint64_t> keys)
+{
+    uint64_t h = mix64h(seed + GOLDEN * (1 + stream));
+    for (uint64_t k : keys) h = mix64h(h ^ k);
+    return h;
+}
+
+uint64_t bounded(uint64_t h, uint64_t n) { return (uint64_t)(((unsigned __int128)h * n) >> 64); }
+
+// m distinct indices of [0, n) for iteration k: partial Fisher-Yates, then ascending.
+void choose(uint64_t seed, uint64_t stream, int64_t k, int n, int m, int32_t* out, std::vector<int32_t>& scratch)
+{
+    scratch.resize(n);
+    for (int i = 0; i < n; ++i) scratch[i] = i;
+    for (int t = 0; t < m; ++t) {
+        int jj = t + (int)bounded(hash_keys(seed, stream, {(uint64_t)k, (uint64_t)t}), (uint64_t)(n - t));
+        std::swap(scratch[t], scratch[jj]);
+    }
+    std::sort(scratch.begin(), scratch.begin() + m);
+    std::copy(scratch.begin(), scratch.begin() + m, out);
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t b)
+    {
+        release();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    template <class T>
+    T* as() const
+    {
+        return reinterpret_cast<T*>(p);
+    }
+};
+
+// Pinned host staging buffer whose reuse waits for the previous copy out of it.
+struct Staging {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    ~Staging()
+    {
+        if (done) {
+            if (pending) (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
+        if (host) (void)hipHostFree(host);
+    }
+    hipError_t reserve(size_t b)
+    {
+        if (!done) {
+            hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        if (pending) {
+            hipError_t e = hipEventSynchronize(done);
+            if (e != hipSuccess) return e;
+            pending = false;
+        }
+        if (b <= bytes) return hipSuccess;
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+        bytes = 0;
+        hipError_t e = hipHostMalloc(&host, b, hipHostMallocDefault);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    hipError_t upload(void* dst, size_t b, hipStream_t st)
+    {
+        hipError_t e = hipMemcpyAsync(dst, host, b, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        e = hipEventRecord(done, st);
+        pending = (e == hipSuccess);
+        return e;
+    }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------ geometry
+
+struct bsgd_geometry {
+    bsgd_geometry_desc d{};
+    std::vector<double> angles;
+    int dim = 2, N = 1, M = 1, S = 1, max_group = 1;
+    int64_t n_rays = 0, n_vox = 0, z_floats = 0, nnz_total = 0;
+    std::vector<int32_t> view_order, group_start;
+    std::vector<PairInfo> pairs;
+    std::vector<BlockInfo> blocks;
+    std::vector<double> im_w;
+    std::vector<int64_t> im_nnz;
+    std::vector<uint32_t> im_q;
+    DevBuf d_cs, d_pairs, d_blocks, d_q, d_all_views, d_views;
+    Staging stage;
+    DevGeom dg{};
+};
+
+static bsgd_status validate(const bsgd_geometry_desc* d)
+{
+    if (!d) return fail(BSGD_E_INVALID_ARG, "descriptor is NULL");
+    if (d->kind < 0 || d->kind > 2) return fail(BSGD_E_INVALID_ARG, "unknown geometry kind %d", d->kind);
+    const bool is3d = d->kind == BSGD_CONE_FLAT_3D;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(BSGD_E_INVALID_ARG, "grid sizes must be >= 1");
+    if (!is3d && (d->nz != 1 || d->nv != 1 || d->bz != 1 || d->sv != 1))
+        return fail(BSGD_E_INVALID_ARG, "2D geometries need nz = nv = bz = sv = 1");
+    if (!(d->vx > 0 && d->vy > 0 && d->vz > 0) || !std::isfinite(d->vx) || !std::isfinite(d->vy) ||
+        !std::isfinite(d->vz))
+        return fail(BSGD_E_INVALID_ARG, "voxel sizes must be positive and finite");
+    if (d->n_views < 1 || d->n_views > 65535) return fail(BSGD_E_INVALID_ARG, "n_views must be in [1, 65535]");
+    if (!d->angles_rad) return fail(BSGD_E_INVALID_ARG, "angles_rad is NULL");
+    for (int m = 0; m < d->n_views; ++m)
+        if (!std::isfinite(d->angles_rad[m])) return fail(BSGD_E_INVALID_ARG, "angle %d is not finite", m);
+    if (d->nu < 1 || d->nv < 1) return fail(BSGD_E_INVALID_ARG, "detector sizes must be >= 1");
+    if ((int64_t)d->nu * d->nv > (int64_t)1 << 30) return fail(BSGD_E_INVALID_ARG, "detector too large");
+    if (!(d->du > 0 && d->dv > 0) || !std::isfinite(d->du) || !std::isfinite(d->dv))
+        return fail(BSGD_E_INVALID_ARG, "detector pitch must be positive and finite");
+    if ((int64_t)d->nx * d->ny * d->nz > ((int64_t)1 << 31) - 1) return fail(BSGD_E_INVALID_ARG, "volume too large");
+    if (d->bx < 1 || d->by < 1 || d->bz < 1 || d->bx > d->nx || d->by > d->ny || d->bz > d->nz)
+        return fail(BSGD_E_INVALID_ARG, "block tiling must satisfy 1 <= b <= n per axis");
+    if ((int64_t)d->bx * d->by * d->bz > 65535) return fail(BSGD_E_INVALID_ARG, "at most 65535 column blocks");
+    if (d->n_row_blocks < 1 || d->n_row_blocks > d->n_views)
+        return fail(BSGD_E_INVALID_ARG, "n_row_blocks must be in [1, n_views]");
+    if (d->su < 1 || d->sv < 1 || d->su > d->nu || d->sv > d->nv || d->su * d->sv > 16)
+        return fail(BSGD_E_INVALID_ARG, "sub-detectors: 1 <= su <= nu, 1 <= sv <= nv, su sv <= 16");
+    if (d->im_mode != BSGD_IM_NONE && d->im_mode != BSGD_IM_COLNORM && d->im_mode != BSGD_IM_UNIFORM)
+        return fail(d->im_mode == 2 ? BSGD_E_UNSUPPORTED : BSGD_E_INVALID_ARG, "unsupported im_mode %d", d->im_mode);
+    if (d->kind != BSGD_PARALLEL_2D) {
+        if (!(d->sod > 0 && d->sdd > d->sod) || !std::isfinite(d->sdd))
+            return fail(BSGD_E_INVALID_ARG, "need 0 < sod < sdd");
+        const double rx = 0.5 * d->nx * d->vx, ry = 0.5 * d->ny * d->vy;
+        const double R = std::sqrt(rx * rx + ry * ry);
+        if (!(R < d->sod) || !(R < d->sdd - d->sod))
+            return fail(BSGD_E_INVALID_ARG, "the volume must lie strictly between source and detector");
+    }
+    return BSGD_OK;
+}
+
+static void tile(int n, int b, int t, int& lo, int& hi)
+{
+    lo = (int)(((int64_t)t * n) / b);
+    hi = (int)(((int64_t)(t + 1) * n) / b);
+}
+
+static void build_tables(bsgd_geometry* g)
+{
+    const bsgd_geometry_desc& d = g->d;
+    const bool is3d = d.kind == BSGD_CONE_FLAT_3D;
+    const bool par = d.kind == BSGD_PARALLEL_2D;
+    g->dim = is3d ? 3 : 2;
+    g->N = d.bx * d.by * d.bz;
+    g->M = d.n_row_blocks;
+    g->S = d.su * d.sv;
+    g->n_rays = (int64_t)d.n_views * d.nu * d.nv;
+    g->n_vox = (int64_t)d.nx * d.ny * d.nz;
+
+    // row blocks: seeded Fisher-Yates permutation cut into M consecutive groups
+    std::vector<int32_t> perm(d.n_views);
+    for (int i = 0; i < d.n_views; ++i) perm[i] = i;
+    for (int t = 0; t + 1 < d.n_views; ++t) {
+        int jj = t + (int)bounded(hash_keys(d.partition_seed, STREAM_PARTITION, {(uint64_t)t}),
+                                  (uint64_t)(d.n_views - t));
+        std::swap(perm[t], perm[jj]);
+    }
+    const int base = d.n_views / g->M, extra = d.n_views % g->M;
+    g->view_order.clear();
+    g->group_start.assign(1, 0);
+    int pos = 0;
+    g->max_group = 0;
+    for (int i = 0; i < g->M; ++i) {
+        int size = base + (i < extra ? 1 : 0);
+        std::vector<int32_t> grp(perm.begin() + pos, perm.begin() + pos + size);
+        std::sort(grp.begin(), grp.end());
+        g->view_order.insert(g->view_order.end(), grp.begin(), grp.end());
+        pos += size;
+        g->group_start.push_back(pos);
+        g->max_group = std::max(g->max_group, size);
+    }
+
+    // column blocks
+    const double lox = -0.5 * d.nx * d.vx, loy = -0.5 * d.ny * d.vy, loz = -0.5 * d.nz * d.vz;
+    g->blocks.resize(g->N);
+    std::vector<double> cbx(g->N), cby(g->N), cbz(g->N), ex0(g->N), ex1(g->N), ey0(g->N), ey1(g->N), ez0(g->N),
+        ez1(g->N);
+    for (int tz = 0; tz < d.bz; ++tz)
+        for (int ty = 0; ty < d.by; ++ty)
+            for (int tx = 0; tx < d.bx; ++tx) {
+                const int j = (tz * d.by + ty) * d.bx + tx;
+                int x0, x1, y0, y1, z0, z1;
+                tile(d.nx, d.bx, tx, x0, x1);
+                tile(d.ny, d.by, ty, y0, y1);
+                tile(d.nz, d.bz, tz, z0, z1);
+                BlockInfo& B = g->blocks[j];
+                std::memset(&B, 0, sizeof B);
+                B.x0 = x0;
+                B.y0 = y0;
+                B.z0 = z0;
+                B.nbx = x1 - x0;
+                B.nby = y1 - y0;
+                B.nbz = z1 - z0;
+                B.hx = (float)(0.5 * B.nbx * d.vx);
+                B.hy = (float)(0.5 * B.nby * d.vy);
+                B.hz = (float)(0.5 * B.nbz * d.vz);
+                ex0[j] = lox + x0 * d.vx;
+                ex1[j] = lox + x1 * d.vx;
+                ey0[j] = loy + y0 * d.vy;
+                ey1[j] = loy + y1 * d.vy;
+                ez0[j] = loz + z0 * d.vz;
+                ez1[j] = loz + z1 * d.vz;
+                cbx[j] = 0.5 * (ex0[j] + ex1[j]);
+                cby[j] = 0.5 * (ey0[j] + ey1[j]);
+                cbz[j] = 0.5 * (ez0[j] + ez1[j]);
+            }
+
+    // per (view, block): detector footprint and block-local ray anchors
+    const double ku = 0.5 * (d.nu - 1), lv = 0.5 * (d.nv - 1);
+    const double margin = 1e-3;
+    g->pairs.resize((size_t)d.n_views * g->N);
+    int64_t zoff = 0;
+    for (int v = 0; v < d.n_views; ++v) {
+        const double c = std::cos(d.angles_rad[v]), s = std::sin(d.angles_rad[v]);
+        for (int j = 0; j < g->N; ++j) {
+            PairInfo& P = g->pairs[(size_t)v * g->N + j];
+            std::memset(&P, 0, sizeof P);
+            double kmin = INFINITY, kmax = -INFINITY, lmin = INFINITY, lmax = -INFINITY;
+            for (int q = 0; q < 8; ++q) {
+                const double X = (q & 1) ? ex1[j] : ex0[j];
+                const double Y = (q & 2) ? ey1[j] : ey0[j];
+                const double Z = (q & 4) ? ez1[j] : ez0[j];
+                const double w = -X * s + Y * c;
+                double kk, ll = 0.0;
+                if (par) {
+                    kk = w / d.du + ku;
+                } else {
+                    const double dep = d.sod - (X * c + Y * s);
+                    kk = d.sdd * w / dep / d.du + ku;
+                    if (is3d) ll = d.sdd * Z / dep / d.dv + lv;
+                }
+                kmin = std::min(kmin, kk);
+                kmax = std::max(kmax, kk);
+                lmin = std::min(lmin, ll);
+                lmax = std::max(lmax, ll);
+            }
+            int u0 = (int)std::max(0.0, std::ceil(kmin - margin));
+            int u1 = (int)std::min((double)d.nu, std::floor(kmax + margin) + 1.0);
+            int v0 = 0, v1 = 1;
+            if (is3d) {
+                v0 = (int)std::max(0.0, std::ceil(lmin - margin));
+                v1 = (int)std::min((double)d.nv, std::floor(lmax + margin) + 1.0);
+            }
+            if (u1 <= u0 || v1 <= v0) u0 = u1 = v0 = v1 = 0;
+            P.u0 = u0;
+            P.u1 = u1;
+            P.v0 = v0;
+            P.v1 = v1;
+            P.zoff = zoff;
+            zoff += (int64_t)(u1 - u0) * (v1 - v0);
+
+            const double cu = -cbx[j] * s + cby[j] * c;
+            const double ce = cbx[j] * c + cby[j] * s;
+            P.cu = (float)cu;
+            P.cz = (float)cbz[j];
+            if (par) {
+                const int kc = (int)std::lround(cu / d.du + ku);
+                P.kc = kc;
+                P.au = (float)d.du;
+                P.bu = (float)((kc - ku) * d.du - cu);
+                P.depth = 0.0f;
+            } else {
+                const double D = d.sod - ce;
+                const double A = D / d.sdd;
+                const int kc = (int)std::lround(cu / A / d.du + ku);
+                P.kc = kc;
+                P.au = (float)(A * d.du);
+                P.bu = (float)(A * (kc - ku) * d.du - cu);
+                P.depth = (float)D;
+                if (is3d) {
+                    const int lc = (int)std::lround(cbz[j] / A / d.dv + lv);
+                    P.lc = lc;
+                    P.av = (float)(A * d.dv);
+                    P.bv = (float)(A * (lc - lv) * d.dv - cbz[j]);
+                }
+            }
+        }
+    }
+    g->z_floats = zoff;
+}
+
+static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
+{
+    const bsgd_geometry_desc& d = g->d;
+    std::vector<float2> cs(d.n_views);
+    for (int v = 0; v < d.n_views; ++v)
+        cs[v] = make_float2((float)std::cos(d.angles_rad[v]), (float)std::sin(d.angles_rad[v]));
+    HIP_TRY(g->d_cs.alloc(cs.size() * sizeof(float2)));
+    HIP_TRY(g->d_pairs.alloc(g->pairs.size() * sizeof(PairInfo)));
+    HIP_TRY(g->d_blocks.alloc(g->blocks.size() * sizeof(BlockInfo)));
+    std::vector<int32_t> all(d.n_views);
+    for (int v = 0; v < d.n_views; ++v) all[v] = v;
+    HIP_TRY(g->d_all_views.alloc(all.size() * sizeof(int32_t)));
+    HIP_TRY(hipMemcpyAsync(g->d_cs.p, cs.data(), cs.size() * sizeof(float2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->d_pairs.p, g->pairs.data(), g->pairs.size() * sizeof(PairInfo), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(hipMemcpyAsync(g->d_blocks.p, g->blocks.data(), g->blocks.size() * sizeof(BlockInfo),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->d_all_views.p, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+
+    DevGeom& G = g->dg;
+    G.kind = d.kind;
+    G.dim = g->dim;
+    G.nx = d.nx;
+    G.ny = d.ny;
+    G.nz = d.nz;
+    G.vx = (float)d.vx;
+    G.vy = (float)d.vy;
+    G.vz = (float)d.vz;
+    G.n_views = d.n_views;
+    G.nu = d.nu;
+    G.nv = d.nv;
+    G.du = (float)d.du;
+    G.dv = (float)d.dv;
+    G.sod = (float)d.sod;
+    G.sdd = (float)d.sdd;
+    G.N = g->N;
+    G.bx = d.bx;
+    G.by = d.by;
+    G.bz = d.bz;
+    G.su = d.su;
+    G.sv = d.sv;
+    G.S = g->S;
+    G.cs = g->d_cs.as<float2>();
+    G.pairs = g->d_pairs.as<PairInfo>();
+    G.blocks = g->d_blocks.as<BlockInfo>();
+    return BSGD_OK;
+}
+
+static bsgd_status compute_im(bsgd_geometry* g, hipStream_t st)
+{
+    const size_t n = (size_t)g->d.n_views * g->S * g->N;
+    DevBuf dw, dn;
+    HIP_TRY(dw.alloc(n * sizeof(double)));
+    HIP_TRY(dn.alloc(n * sizeof(int64_t)));
+    HIP_TRY(launch_geom_stats(g->dg, dw.as<double>(), dn.as<int64_t>(), st));
+    g->im_w.resize(n);
+    g->im_nnz.resize(n);
+    HIP_TRY(hipMemcpyAsync(g->im_w.data(), dw.p, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(g->im_nnz.data(), dn.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    g->nnz_total = 0;
+    for (int64_t c : g->im_nnz) g->nnz_total += c;
+
+    g->im_q.assign(n, 0u);
+    const bsgd_geometry_desc& d = g->d;
+    if (d.im_table) {
+        std::memcpy(g->im_q.data(), d.im_table, n * sizeof(uint32_t));
+    } else if (d.im_mode == BSGD_IM_UNIFORM) {
+        std::fill(g->im_q.begin(), g->im_q.end(), 1u);
+    } else {
+        // q = round(2^20 w / sum_s w), at least 1 where w > 0
+        for (int v = 0; v < d.n_views; ++v)
+            for (int j = 0; j < g->N; ++j) {
+                double tot = 0.0;
+                for (int s = 0; s < g->S; ++s) tot += g->im_w[((size_t)v * g->S + s) * g->N + j];
+                for (int s = 0; s < g->S; ++s) {
+                    const size_t o = ((size_t)v * g->S + s) * g->N + j;
+                    const double w = g->im_w[o];
+                    uint32_t q = 0;
+                    if (tot > 0.0) q = (uint32_t)std::floor(w / tot * (double)(1u << 20) + 0.5);
+                    if (w > 0.0 && q == 0) q = 1;
+                    g->im_q[o] = q;
+                }
+            }
+    }
+    HIP_TRY(g->d_q.alloc(n * sizeof(uint32_t)));
+    HIP_TRY(hipMemcpyAsync(g->d_q.p, g->im_q.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_geometry_create(const bsgd_geometry_desc* desc, void* stream, bsgd_geometry** out)
+{
+    if (!out) return fail(BSGD_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    bsgd_status stt = validate(desc);
+    if (stt != BSGD_OK) return stt;
+    bsgd_geometry* g = new (std::nothrow) bsgd_geometry();
+    if (!g) return fail(BSGD_E_OUT_OF_MEMORY, "host allocation failed");
+    g->d = *desc;
+    g->angles.assign(desc->angles_rad, desc->angles_rad + desc->n_views);
+    g->d.angles_rad = g->angles.data();
+    g->d.im_table = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        build_tables(g);
+    } catch (...) {
+        delete g;
+        return fail(BSGD_E_OUT_OF_MEMORY, "host allocation failed while building tables");
+    }
+    stt = upload_tables(g, st);
+    if (stt == BSGD_OK) {
+        g->d.im_table = desc->im_table;
+        stt = compute_im(g, st);
+        g->d.im_table = nullptr;
+    }
+    if (stt != BSGD_OK) {
+        delete g;
+        return stt;
+    }
+    *out = g;
+    return BSGD_OK;
+}
+
+extern "C" void bsgd_geometry_destroy(bsgd_geometry* g) { delete g; }
+
+extern "C" bsgd_status bsgd_geometry_get_info(const bsgd_geometry* g, bsgd_geometry_info* out)
+{
+    if (!g || !out) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    out->n_rays = g->n_rays;
+    out->n_voxels = g->n_vox;
+    out->n_blocks = g->N;
+    out->n_row_blocks = g->M;
+    out->n_subdet = g->S;
+    out->max_group_views = g->max_group;
+    out->z_floats = g->z_floats;
+    out->nnz = g->nnz_total;
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_geometry_table(const bsgd_geometry* g, int32_t which, void* out, size_t bytes)
+{
+    if (!g || !out) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    const void* src = nullptr;
+    size_t need = 0;
+    std::vector<int32_t> rects;
+    switch (which) {
+    case BSGD_TABLE_VIEW_ORDER:
+        src = g->view_order.data();
+        need = g->view_order.size() * sizeof(int32_t);
+        break;
+    case BSGD_TABLE_GROUP_START:
+        src = g->group_start.data();
+        need = g->group_start.size() * sizeof(int32_t);
+        break;
+    case BSGD_TABLE_IM_WEIGHTS:
+        src = g->im_w.data();
+        need = g->im_w.size() * sizeof(double);
+        break;
+    case BSGD_TABLE_IM_TABLE:
+        src = g->im_q.data();
+        need = g->im_q.size() * sizeof(uint32_t);
+        break;
+    case BSGD_TABLE_NNZ:
+        src = g->im_nnz.data();
+        need = g->im_nnz.size() * sizeof(int64_t);
+        break;
+    case BSGD_TABLE_FOOTPRINT:
+        rects.resize(g->pairs.size() * 4);
+        for (size_t i = 0; i < g->pairs.size(); ++i) {
+            rects[4 * i] = g->pairs[i].u0;
+            rects[4 * i + 1] = g->pairs[i].u1;
+            rects[4 * i + 2] = g->pairs[i].v0;
+            rects[4 * i + 3] = g->pairs[i].v1;
+        }
+        src = rects.data();
+        need = rects.size() * sizeof(int32_t);
+        break;
+    default:
+        return fail(BSGD_E_INVALID_ARG, "unknown table %d", which);
+    }
+    if (bytes < need) return fail(BSGD_E_INVALID_ARG, "table needs %zu bytes, got %zu", need, bytes);
+    std::memcpy(out, src, need);
+    return BSGD_OK;
+}
+
+// Device view list for a standalone projector call.
+static bsgd_status view_list(bsgd_geometry* g, const int32_t* views, int32_t n, hipStream_t st, const int32_t** dev)
+{
+    if (!views) {
+        *dev = g->d_all_views.as<int32_t>();
+        return BSGD_OK;
+    }
+    for (int i = 0; i < n; ++i)
+        if (views[i] < 0 || views[i] >= g->d.n_views) return fail(BSGD_E_INVALID_ARG, "view index %d out of range", views[i]);
+    const size_t b = (size_t)n * sizeof(int32_t);
+    HIP_TRY(g->stage.reserve(b));
+    std::memcpy(g->stage.host, views, b);
+    if (g->d_views.bytes < b) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(g->d_views.alloc(std::max(b, (size_t)4096)));
+    }
+    HIP_TRY(g->stage.upload(g->d_views.p, b, st));
+    *dev = g->d_views.as<int32_t>();
+    return BSGD_OK;
+}
+
+static bsgd_status check_proj_args(const bsgd_geometry* g, const void* a, const void* b, const int32_t* views,
+                                   int32_t n_sel, int32_t block, uint32_t flags)
+{
+    if (!g || !a || !b) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    if (views && (n_sel < 0 || n_sel > 65535)) return fail(BSGD_E_INVALID_ARG, "n_views_sel must be in [0, 65535]");
+    if (block < -1 || block >= g->N) return fail(BSGD_E_INVALID_ARG, "block %d out of range", block);
+    if (flags & ~BSGD_ACCUMULATE) return fail(BSGD_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_forward_project(const bsgd_geometry* gc, const float* x, float* y, const int32_t* views,
+                                            int32_t n_sel, int32_t block, uint32_t flags, void* stream)
+{
+    bsgd_status stt = check_proj_args(gc, x, y, views, n_sel, block, flags);
+    if (stt != BSGD_OK) return stt;
+    bsgd_geometry* g = const_cast<bsgd_geometry*>(gc);
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t* dv = nullptr;
+    if (!views) n_sel = g->d.n_views;
+    stt = view_list(g, views, n_sel, st, &dv);
+    if (stt != BSGD_OK) return stt;
+    HIP_TRY(launch_fp_full(g->dg, dv, n_sel, block, x, y, (flags & BSGD_ACCUMULATE) ? 1 : 0, st));
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_back_project(const bsgd_geometry* gc, const float* y, float* x, const int32_t* views,
+                                         int32_t n_sel, int32_t block, float scale, uint32_t flags, void* stream)
+{
+    bsgd_status stt = check_proj_args(gc, y, x, views, n_sel, block, flags);
+    if (stt != BSGD_OK) return stt;
+    if (!std::isfinite(scale)) return fail(BSGD_E_INVALID_ARG, "scale must be finite");
+    bsgd_geometry* g = const_cast<bsgd_geometry*>(gc);
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t* dv = nullptr;
+    if (!views) n_sel = g->d.n_views;
+    stt = view_list(g, views, n_sel, st, &dv);
+    if (stt != BSGD_OK) return stt;
+    HIP_TRY(launch_bp_full(g->dg, dv, n_sel, block, y, x, scale, (flags & BSGD_ACCUMULATE) ? 1 : 0, st));
+    return BSGD_OK;
+}
+
+// ------------------------------------------------------------ solver
+
+enum { KID_FP = 0, KID_RESID = 1, KID_BP = 2, KID_TV = 3, KID_DRAW = 4, KID_COUNT = 5 };
+
+struct bsgd_solver {
+    const bsgd_geometry* g = nullptr;
+    const float* y = nullptr;
+    float* x = nullptr;
+    bsgd_options o{};
+    hipStream_t st = nullptr;
+    int R = 1, B = 1, T = 1, tv_every = 1, maxv = 1;
+    int64_t k = 0;
+    bool failed = false, im = false;
+    SchedLayout L{};
+    DevBuf z, ghat, gsum, r_sel, sched, draws, partials, norm_out, tv_p, tv_a, tv_b;
+    int sched_cap = 0;
+    Staging stage;
+    double* norm_host = nullptr;
+    // last call's schedule (host) for export
+    std::vector<int32_t> last_sched;
+    int last_n = 0;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double ms[KID_COUNT] = {0, 0, 0, 0, 0};
+    int64_t launches[KID_COUNT] = {0, 0, 0, 0, 0};
+
+    ~bsgd_solver()
+    {
+        if (st) (void)hipStreamSynchronize(st);
+        for (auto& p : pending) {
+            ev_pool.push_back(p.second.first);
+            ev_pool.push_back(p.second.second);
+        }
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        if (norm_host) (void)hipHostFree(norm_host);
+    }
+
+    hipError_t event(hipEvent_t* e)
+    {
+        if (!ev_pool.empty()) {
+            *e = ev_pool.back();
+            ev_pool.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreate(e);
+    }
+};
+
+// Launch helper recording a start/stop event pair around `fn` when profiling.
+template <class F>
+static hipError_t timed(bsgd_solver* s, int kid, F&& fn)
+{
+    if (!s->prof) return fn();
+    hipEvent_t a, b;
+    hipError_t e = s->event(&a);
+    if (e != hipSuccess) return e;
+    e = s->event(&b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(a, s->st);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s->st);
+    if (e != hipSuccess) return e;
+    s->pending.push_back({kid, {a, b}});
+    s->launches[kid] += 1;
+    return hipSuccess;
+}
+
+static bsgd_status resolve_counts(const bsgd_geometry* g, const bsgd_options* o, int& R, int& B)
+{
+    if (o->rows_per_iter == 0 && o->blocks_per_iter == 0) {
+        const int P = o->node_count;
+        if (P < 1) return fail(BSGD_E_INVALID_ARG, "give rows_per_iter and blocks_per_iter, or node_count >= 1");
+        B = std::min(P, g->N);  // gamma N = min(N, P)
+        if (P % B) return fail(BSGD_E_INVALID_ARG, "node_count %d gives a non-integer alpha M", P);
+        R = P / B;  // alpha M = P / (N gamma)
+        if (R > g->M) return fail(BSGD_E_INVALID_ARG, "node_count %d exceeds M N", P);
+        return BSGD_OK;
+    }
+    R = o->rows_per_iter;
+    B = o->blocks_per_iter;
+    if (R < 1 || R > g->M) return fail(BSGD_E_INVALID_ARG, "rows_per_iter must be in [1, M]");
+    if (B < 1 || B > g->N) return fail(BSGD_E_INVALID_ARG, "blocks_per_iter must be in [1, N]");
+    return BSGD_OK;
+}
+
+static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* x, const bsgd_options* o,
+                                 hipStream_t st, bsgd_solver** out)
+{
+    if (!g || !y || !x || !o || !out) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    int R, B;
+    bsgd_status stt = resolve_counts(g, o, R, B);
+    if (stt != BSGD_OK) return stt;
+    if (!std::isfinite(o->mu)) return fail(BSGD_E_INVALID_ARG, "mu must be finite");
+    if (!(o->tv_lambda >= 0.0) || !std::isfinite(o->tv_lambda)) return fail(BSGD_E_INVALID_ARG, "tv_lambda must be >= 0");
+    if (o->tv_lambda > 0 && o->tv_inner_iters < 1) return fail(BSGD_E_INVALID_ARG, "tv_inner_iters must be >= 1");
+    if (o->tv_every < 0 || o->max_effective_epochs < 0 || o->check_every < 0 || !(o->tol >= 0.0))
+        return fail(BSGD_E_INVALID_ARG, "negative option");
+    bsgd_solver* s = new (std::nothrow) bsgd_solver();
+    if (!s) return fail(BSGD_E_OUT_OF_MEMORY, "host allocation failed");
+    s->g = g;
+    s->y = y;
+    s->x = x;
+    s->o = *o;
+    s->st = st;
+    s->R = R;
+    s->B = B;
+    s->T = std::max(1, (int)std::lround((double)g->M * g->N / ((double)R * B)));
+    s->tv_every = o->tv_every > 0 ? o->tv_every : s->T;
+    s->maxv = R * g->max_group;
+    s->im = g->d.im_mode != BSGD_IM_NONE;
+    s->L.R = R;
+    s->L.B = B;
+    s->L.maxv = s->maxv;
+    s->L.stride = 2 + 2 * R + B + s->maxv;
+    const int64_t per_view = (int64_t)g->d.nu * g->d.nv;
+    auto cleanup = [&](bsgd_status e) {
+        delete s;
+        return e;
+    };
+#define S_TRY(expr)                                                                                \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return cleanup(fail(e_ == hipErrorOutOfMemory ? BSGD_E_OUT_OF_MEMORY : BSGD_E_DEVICE, "%s: %s", #expr, \
+                                hipGetErrorString(e_)));                                           \
+    } while (0)
+    S_TRY(s->z.alloc((size_t)g->z_floats * sizeof(float)));
+    S_TRY(s->ghat.alloc((size_t)g->M * g->n_vox * sizeof(float)));
+    S_TRY(s->gsum.alloc((size_t)g->n_vox * sizeof(float)));
+    S_TRY(s->r_sel.alloc((size_t)s->maxv * per_view * sizeof(float)));
+    const int n_part = (int)(((per_view + 255) / 256) * g->d.n_views);
+    S_TRY(s->partials.alloc((size_t)std::max(n_part, 4096) * sizeof(double)));
+    S_TRY(s->norm_out.alloc(sizeof(double)));
+    S_TRY(hipHostMalloc((void**)&s->norm_host, sizeof(double), hipHostMallocDefault));
+    if (o->tv_lambda > 0) {
+        const size_t nb = (size_t)g->dim * g->n_vox * sizeof(float);
+        S_TRY(s->tv_p.alloc(nb));
+        S_TRY(s->tv_a.alloc(nb));
+        S_TRY(s->tv_b.alloc(nb));
+    }
+    S_TRY(launch_fill(s->z.as<float>(), 0.0f, g->z_floats, st));
+    S_TRY(launch_fill(s->ghat.as<float>(), 0.0f, (int64_t)g->M * g->n_vox, st));
+    S_TRY(launch_fill(s->gsum.as<float>(), 0.0f, g->n_vox, st));
+#undef S_TRY
+    *out = s;
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solver_create(const bsgd_geometry* g, const float* y, float* x, const bsgd_options* o,
+                                          void* stream, bsgd_solver** out)
+{
+    return solver_create(g, y, x, o, (hipStream_t)stream, out);
+}
+
+extern "C" void bsgd_solver_destroy(bsgd_solver* s) { delete s; }
+
+static bsgd_status ensure_sched(bsgd_solver* s, int n)
+{
+    if (n <= s->sched_cap) return BSGD_OK;
+    HIP_TRY(hipStreamSynchronize(s->st));
+    const int cap = std::max(n, 64);
+    HIP_TRY(s->sched.alloc((size_t)cap * s->L.stride * sizeof(int32_t)));
+    if (s->im) HIP_TRY(s->draws.alloc((size_t)cap * s->maxv * s->B));
+    s->sched_cap = cap;
+    return BSGD_OK;
+}
+
+static void fill_schedule(bsgd_solver* s, int n, int32_t* out)
+{
+    const bsgd_geometry* g = s->g;
+    const SchedLayout& L = s->L;
+    std::vector<int32_t> scratch;
+    for (int it = 0; it < n; ++it) {
+        int32_t* rec = out + (size_t)it * L.stride;
+        std::fill(rec, rec + L.stride, 0);
+        const int64_t k = s->k + it;
+        choose(s->o.seed, STREAM_ROWS, k, g->M, L.R, rec + L.off_rows(), scratch);
+        choose(s->o.seed, STREAM_BLOCKS, k, g->N, L.B, rec + L.off_blocks(), scratch);
+        int nv = 0;
+        for (int ri = 0; ri < L.R; ++ri) {
+            const int i = rec[L.off_rows() + ri];
+            rec[L.off_gstart() + ri] = nv;
+            for (int p = g->group_start[i]; p < g->group_start[i + 1]; ++p) rec[L.off_views() + nv++] = g->view_order[p];
+        }
+        rec[L.off_gstart() + L.R] = nv;
+        rec[0] = nv;
+    }
+}
+
+static bsgd_status resid_norm(bsgd_solver* s, double* out)
+{
+    int np = 0;
+    HIP_TRY(launch_resid_sumsq(s->g->dg, s->y, s->z.as<float>(), s->partials.as<double>(), &np, s->st));
+    HIP_TRY(launch_sum_partials(s->partials.as<double>(), np, s->norm_out.as<double>(), s->st));
+    HIP_TRY(hipMemcpyAsync(s->norm_host, s->norm_out.p, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    *out = std::sqrt(*s->norm_host);
+    return BSGD_OK;
+}
+
+static bsgd_status step_impl(bsgd_solver* s, int n_iters)
+{
+    const bsgd_geometry* g = s->g;
+    bsgd_status stt = ensure_sched(s, n_iters);
+    if (stt != BSGD_OK) return stt;
+    const size_t sched_bytes = (size_t)n_iters * s->L.stride * sizeof(int32_t);
+    HIP_TRY(s->stage.reserve(sched_bytes));
+    int32_t* host = reinterpret_cast<int32_t*>(s->stage.host);
+    fill_schedule(s, n_iters, host);
+    s->last_sched.assign(host, host + (size_t)n_iters * s->L.stride);
+    s->last_n = n_iters;
+    HIP_TRY(s->stage.upload(s->sched.p, sched_bytes, s->st));
+    const int32_t* dsched = s->sched.as<int32_t>();
+    int8_t* ddraws = s->im ? s->draws.as<int8_t>() : nullptr;
+    if (s->im) {
+        HIP_TRY(timed(s, KID_DRAW, [&] {
+            return launch_draws(g->dg, dsched, s->L, n_iters, s->k, s->o.seed, g->d_q.as<uint32_t>(), ddraws, s->st);
+        }));
+    }
+    const int64_t per_it_draws = (int64_t)s->maxv * s->B;
+    for (int it = 0; it < n_iters; ++it) {
+        const int32_t* rec = dsched + (size_t)it * s->L.stride;
+        const int8_t* dr = ddraws ? ddraws + it * per_it_draws : nullptr;
+        HIP_TRY(timed(s, KID_FP, [&] { return launch_fp_pairs(g->dg, rec, s->L, dr, s->x, s->z.as<float>(), s->st); }));
+        HIP_TRY(timed(s, KID_RESID,
+                      [&] { return launch_resid(g->dg, rec, s->L, s->y, s->z.as<float>(), s->r_sel.as<float>(), s->st); }));
+        HIP_TRY(timed(s, KID_BP, [&] {
+            return launch_bp_step(g->dg, rec, s->L, dr, s->r_sel.as<float>(), s->ghat.as<float>(), s->gsum.as<float>(),
+                                  s->x, (float)s->o.mu, g->n_vox, s->st);
+        }));
+        s->k += 1;
+        if (s->o.tv_lambda > 0 && s->k % s->tv_every == 0) {
+            const float w = (float)(s->o.mu * s->o.tv_lambda);
+            HIP_TRY(timed(s, KID_TV, [&] {
+                return launch_tv_prox(g->dg, s->x, w, s->o.tv_inner_iters, s->tv_p.as<float>(), s->tv_a.as<float>(),
+                                      s->tv_b.as<float>(), s->st);
+            }));
+        }
+    }
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_norm_out)
+{
+    if (!s) return fail(BSGD_E_INVALID_ARG, "solver is NULL");
+    if (s->failed) return fail(BSGD_E_STATE, "solver is in a failed state");
+    if (n_iters < 0 || n_iters > (1 << 20)) return fail(BSGD_E_INVALID_ARG, "n_iters must be in [0, 2^20]");
+    if (n_iters > 0) {
+        bsgd_status stt = step_impl(s, n_iters);
+        if (stt != BSGD_OK) {
+            s->failed = true;
+            return stt;
+        }
+    }
+    if (resid_norm_out) {
+        bsgd_status stt = resid_norm(s, resid_norm_out);
+        if (stt != BSGD_OK) {
+            s->failed = true;
+            return stt;
+        }
+        if (!std::isfinite(*resid_norm_out)) return fail(BSGD_E_DIVERGED, "residual norm is not finite");
+    }
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solver_counts(const bsgd_solver* s, int64_t* iters_done, int32_t* rows, int32_t* blocks,
+                                          int32_t* epoch_iters)
+{
+    if (!s) return fail(BSGD_E_INVALID_ARG, "solver is NULL");
+    if (iters_done) *iters_done = s->k;
+    if (rows) *rows = s->R;
+    if (blocks) *blocks = s->B;
+    if (epoch_iters) *epoch_iters = s->T;
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solver_last_schedule(const bsgd_solver* sc, int32_t* n_out, int32_t* rows,
+                                                 int32_t* blocks, int16_t* draws, size_t draws_bytes)
+{
+    if (!sc) return fail(BSGD_E_INVALID_ARG, "solver is NULL");
+    bsgd_solver* s = const_cast<bsgd_solver*>(sc);
+    const int n = s->last_n;
+    if (n_out) *n_out = n;
+    const SchedLayout& L = s->L;
+    for (int it = 0; it < n; ++it) {
+        const int32_t* rec = s->last_sched.data() + (size_t)it * L.stride;
+        if (rows) std::copy(rec + L.off_rows(), rec + L.off_rows() + L.R, rows + (size_t)it * L.R);
+        if (blocks) std::copy(rec + L.off_blocks(), rec + L.off_blocks() + L.B, blocks + (size_t)it * L.B);
+    }
+    if (draws) {
+        const size_t cnt = (size_t)n * s->maxv * s->B;
+        if (draws_bytes < cnt * sizeof(int16_t)) return fail(BSGD_E_INVALID_ARG, "draws buffer too small");
+        if (!s->im) {
+            std::fill(draws, draws + cnt, (int16_t)-2);
+        } else {
+            std::vector<int8_t> tmp(cnt);
+            HIP_TRY(hipStreamSynchronize(s->st));
+            HIP_TRY(hipMemcpy(tmp.data(), s->draws.p, cnt, hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < cnt; ++i) draws[i] = tmp[i];
+        }
+    }
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solver_state(const bsgd_solver* s, int32_t which, float* out, size_t bytes)
+{
+    if (!s || !out) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    const DevBuf* src = nullptr;
+    size_t need = 0;
+    if (which == 0) {
+        src = &s->gsum;
+        need = (size_t)s->g->n_vox * sizeof(float);
+    } else if (which == 1) {
+        src = &s->ghat;
+        need = (size_t)s->g->M * s->g->n_vox * sizeof(float);
+    } else if (which == 2) {
+        src = &s->z;
+        need = (size_t)s->g->z_floats * sizeof(float);
+    } else {
+        return fail(BSGD_E_INVALID_ARG, "unknown state %d", which);
+    }
+    if (bytes < need) return fail(BSGD_E_INVALID_ARG, "state needs %zu bytes", need);
+    HIP_TRY(hipMemcpyAsync(out, src->p, need, hipMemcpyDeviceToDevice, s->st));
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solver_set_profiling(bsgd_solver* s, int32_t on)
+{
+    if (!s) return fail(BSGD_E_INVALID_ARG, "solver is NULL");
+    s->prof = on != 0;
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solver_kernel_times(bsgd_solver* s, double* ms_out, int64_t* launches_out)
+{
+    if (!s) return fail(BSGD_E_INVALID_ARG, "solver is NULL");
+    HIP_TRY(hipStreamSynchronize(s->st));
+    for (auto& p : s->pending) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        s->ms[p.first] += ms;
+        s->ev_pool.push_back(p.second.first);
+        s->ev_pool.push_back(p.second.second);
+    }
+    s->pending.clear();
+    for (int i = 0; i < KID_COUNT; ++i) {
+        if (ms_out) ms_out[i] = s->ms[i];
+        if (launches_out) launches_out[i] = s->launches[i];
+    }
+    return BSGD_OK;
+}
+
+// ||A^T (y - A x)|| with scratch buffers: ty [n_rays], tg [n_vox].
+static bsgd_status normal_residual(const bsgd_geometry* g, const float* y, const float* x, float* ty, float* tg,
+                                   double* partials, double* dout, double* host_out, hipStream_t st, double* out)
+{
+    HIP_TRY(launch_fp_full(g->dg, g->d_all_views.as<int32_t>(), g->d.n_views, -1, x, ty, 0, st));
+    HIP_TRY(launch_sub(y, ty, ty, g->n_rays, st));
+    HIP_TRY(launch_bp_full(g->dg, g->d_all_views.as<int32_t>(), g->d.n_views, -1, ty, tg, 1.0f, 0, st));
+    int np = 0;
+    HIP_TRY(launch_sumsq(tg, g->n_vox, partials, &np, st));
+    HIP_TRY(launch_sum_partials(partials, np, dout, st));
+    HIP_TRY(hipMemcpyAsync(host_out, dout, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = std::sqrt(*host_out);
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solve(const bsgd_geometry* g, const float* y, float* x, const bsgd_options* o, void* stream,
+                                  int32_t* iters_out, double* resid_norm_out)
+{
+    bsgd_solver* s = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    bsgd_status stt = solver_create(g, y, x, o, st, &s);
+    if (stt != BSGD_OK) return stt;
+    const int epochs = o->max_effective_epochs > 0 ? o->max_effective_epochs : 1;
+    const int check = o->check_every > 0 ? o->check_every : 1;
+    DevBuf ty, tg;
+    double ref = 0.0;
+    if (o->tol > 0) {
+        if (ty.alloc((size_t)g->n_rays * sizeof(float)) != hipSuccess ||
+            tg.alloc((size_t)g->n_vox * sizeof(float)) != hipSuccess) {
+            delete s;
+            return fail(BSGD_E_OUT_OF_MEMORY, "no memory for the stopping-rule scratch");
+        }
+        // ||A^T y||: the normal residual at x = 0
+        HIP_TRY(launch_fill(tg.as<float>(), 0.0f, g->n_vox, st));
+        HIP_TRY(launch_bp_full(g->dg, g->d_all_views.as<int32_t>(), g->d.n_views, -1, y, tg.as<float>(), 1.0f, 0, st));
+        int np = 0;
+        HIP_TRY(launch_sumsq(tg.as<float>(), g->n_vox, s->partials.as<double>(), &np, st));
+        HIP_TRY(launch_sum_partials(s->partials.as<double>(), np, s->norm_out.as<double>(), st));
+        HIP_TRY(hipMemcpyAsync(s->norm_host, s->norm_out.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        ref = std::sqrt(*s->norm_host);
+    }
+    for (int e = 0; e < epochs; ++e) {
+        stt = bsgd_step(s, s->T, nullptr);
+        if (stt != BSGD_OK) break;
+        if (o->tol > 0 && ((e + 1) % check == 0 || e + 1 == epochs)) {
+            double nr = 0.0;
+            stt = normal_residual(g, y, x, ty.as<float>(), tg.as<float>(), s->partials.as<double>(),
+                                  s->norm_out.as<double>(), s->norm_host, st, &nr);
+            if (stt != BSGD_OK) break;
+            if (!std::isfinite(nr)) {
+                stt = fail(BSGD_E_DIVERGED, "normal residual is not finite");
+                break;
+            }
+            if (ref > 0 && nr / ref <= o->tol) break;
+        }
+    }
+    double rn = 0.0;
+    if (stt == BSGD_OK) stt = bsgd_step(s, 0, &rn);
+    if (stt == BSGD_OK) {
+        if (iters_out) *iters_out = (int32_t)s->k;
+        if (resid_norm_out) *resid_norm_out = rn;
+    }
+    delete s;
+    return stt;
+}

@@ -1,0 +1,214 @@
+// Device-side geometry records and the per-(ray, voxel) arithmetic shared by all
+// kernels. The forward projector (ray-driven Siddon walk), the back projector
+// (voxel-driven slab test) and the importance-weight pass all evaluate a_ij with
+// the same formulas in the same block-local frame, so the back projection is the
+// exact transpose of the forward projection up to FP32 summation order.
+//
+// Frames and precision: every ray is re-anchored per column block. Its point is
+// taken on the plane through the block centre perpendicular to the central ray,
+// at lateral offset lambda = (k - kc) au + bu (and (l - lc) av + bv along z) from
+// the block centre; au, bu, kc are derived in FP64 on the host per (view, block).
+// The direction is the unnormalised source-to-pixel vector (a, b[, v]) with
+// |(a, b, v)| = sqrt(sdd^2 + u^2 + v^2) (fan / cone) or the unit vector (parallel).
+// The walk parameter t is in units of that length; a_ij = dt * |d|. All plane
+// positions are block-local, X_i = i v - h, exact in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bsgd {
+
+enum : int32_t { KIND_PARALLEL_2D = 0, KIND_FAN_2D = 1, KIND_CONE_3D = 2 };
+
+// One (view, column block) pair. 64 bytes.
+struct PairInfo {
+    int32_t u0, u1, v0, v1;  // detector footprint of the block, half-open pixel ranges
+    int64_t zoff;            // first float of this pair's z slot, laid out [l - v0][k - u0]
+    float au, bu, av, bv;    // lateral ray offsets at the block-centre plane (mm)
+    int32_t kc, lc;          // anchor pixel indices for the offsets
+    float cu;                // block centre . e_u (mm)
+    float depth;             // source to block-centre plane distance (mm); 0 for parallel
+    float cz;                // block centre z (mm)
+    int32_t pad;
+};
+
+// One column block. 48 bytes.
+struct BlockInfo {
+    int32_t x0, y0, z0;      // first voxel
+    int32_t nbx, nby, nbz;   // voxels per axis
+    float hx, hy, hz;        // half extents (mm)
+    float pad0, pad1, pad2;
+};
+
+struct DevGeom {
+    int32_t kind, dim;
+    int32_t nx, ny, nz;
+    float vx, vy, vz;
+    int32_t n_views, nu, nv;
+    float du, dv, sod, sdd;
+    int32_t N, bx, by, bz;
+    int32_t su, sv, S;
+    const float2* cs;          // [n_views] (cos, sin)
+    const PairInfo* pairs;     // [n_views][N]
+    const BlockInfo* blocks;   // [N]
+};
+
+// Sub-detector s covers u in [k0, k1), v in [l0, l1).
+__device__ __forceinline__ void subdet_range(const DevGeom& G, int s, int& k0, int& k1, int& l0, int& l1)
+{
+    int a = s % G.su, b = s / G.su;
+    k0 = (a * G.nu) / G.su;
+    k1 = ((a + 1) * G.nu) / G.su;
+    l0 = (b * G.nv) / G.sv;
+    l1 = ((b + 1) * G.nv) / G.sv;
+}
+
+// Ray (k, l) of a view, in the block-local frame of pair P.
+struct Ray {
+    float p[3];    // point on the block-centre plane, block-local (mm)
+    float d[3];    // direction, unnormalised
+    float inv[3];  // reciprocal of d (inf for a zero component)
+    float len;     // |d| (mm per unit t)
+};
+
+template <int DIM>
+__device__ __forceinline__ void make_ray(const DevGeom& G, float c, float s, const PairInfo& P, int k, int l,
+                                         Ray& R)
+{
+    float lu = fmaf((float)(k - P.kc), P.au, P.bu);
+    R.p[0] = -lu * s;
+    R.p[1] = lu * c;
+    if (G.kind == KIND_PARALLEL_2D) {
+        R.d[0] = c;
+        R.d[1] = s;
+        R.len = 1.0f;
+    } else {
+        float u = ((float)k - 0.5f * (float)(G.nu - 1)) * G.du;
+        R.d[0] = fmaf(-G.sdd, c, -(u * s));
+        R.d[1] = fmaf(-G.sdd, s, u * c);
+        float n2 = fmaf(u, u, G.sdd * G.sdd);
+        if (DIM == 3) {
+            float v = ((float)l - 0.5f * (float)(G.nv - 1)) * G.dv;
+            R.d[2] = v;
+            n2 = fmaf(v, v, n2);
+        }
+        R.len = sqrtf(n2);
+    }
+    if (DIM == 3) R.p[2] = fmaf((float)(l - P.lc), P.av, P.bv);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) R.inv[a] = 1.0f / R.d[a];
+}
+
+__device__ __forceinline__ float plane_pos(int i, float v, float h) { return fmaf((float)i, v, -h); }
+
+__device__ __forceinline__ float plane_t(int i, float v, float h, float p, float inv)
+{
+    return (plane_pos(i, v, h) - p) * inv;
+}
+
+// Ray-driven Siddon walk through one block. visit(ix, iy, iz, dt) is called for
+// every voxel the ray crosses, in order, with the parameter length dt >= 0
+// (dt = 0 at exact corner crossings).
+template <int DIM, class Visit>
+__device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], const float (&h)[3],
+                                           const float (&vs)[3], Visit&& visit)
+{
+    float tlo = -INFINITY, thi = INFINITY;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        float X0 = -h[a];
+        float Xn = plane_pos(nb[a], vs[a], h[a]);
+        if (R.d[a] != 0.0f) {
+            float t0 = (X0 - R.p[a]) * R.inv[a];
+            float t1 = (Xn - R.p[a]) * R.inv[a];
+            tlo = fmaxf(tlo, fminf(t0, t1));
+            thi = fminf(thi, fmaxf(t0, t1));
+        } else if (!(X0 <= R.p[a] && R.p[a] < Xn)) {
+            return;
+        }
+    }
+    if (!(tlo < thi)) return;
+
+    int idx[3] = {0, 0, 0};
+    int step[3] = {0, 0, 0};
+    float tn[3] = {INFINITY, INFINITY, INFINITY};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int n = nb[a];
+        float pos = (R.d[a] != 0.0f) ? fmaf(tlo, R.d[a], R.p[a]) : R.p[a];
+        float fi = floorf((pos + h[a]) / vs[a]);
+        fi = fminf(fmaxf(fi, 0.0f), (float)(n - 1));
+        int i = (int)fi;
+        if (R.d[a] > 0.0f) {
+            while (i < n - 1 && plane_t(i + 1, vs[a], h[a], R.p[a], R.inv[a]) <= tlo) ++i;
+            while (i > 0 && plane_t(i, vs[a], h[a], R.p[a], R.inv[a]) > tlo) --i;
+            step[a] = 1;
+            tn[a] = plane_t(i + 1, vs[a], h[a], R.p[a], R.inv[a]);
+        } else if (R.d[a] < 0.0f) {
+            while (i > 0 && plane_t(i, vs[a], h[a], R.p[a], R.inv[a]) <= tlo) --i;
+            while (i < n - 1 && plane_t(i + 1, vs[a], h[a], R.p[a], R.inv[a]) > tlo) ++i;
+            step[a] = -1;
+            tn[a] = plane_t(i, vs[a], h[a], R.p[a], R.inv[a]);
+        } else {
+            while (i < n - 1 && R.p[a] >= plane_pos(i + 1, vs[a], h[a])) ++i;
+            while (i > 0 && R.p[a] < plane_pos(i, vs[a], h[a])) --i;
+        }
+        idx[a] = i;
+    }
+
+    float t = tlo;
+    const int max_steps = nb[0] + (DIM > 1 ? nb[1] : 0) + (DIM > 2 ? nb[2] : 0) + 2;
+    for (int it = 0; it < max_steps; ++it) {
+        float tm = tn[0];
+        int ax = 0;
+        if (DIM > 1 && tn[1] < tm) { tm = tn[1]; ax = 1; }
+        if (DIM > 2 && tn[2] < tm) { tm = tn[2]; ax = 2; }
+        visit(idx[0], idx[1], idx[2], tm - t);
+        t = tm;
+        int ni = idx[ax] + step[ax];
+        if (step[ax] == 0 || ni < 0 || ni >= nb[ax]) break;
+        idx[ax] = ni;
+        tn[ax] = plane_t(step[ax] > 0 ? ni + 1 : ni, vs[ax], h[ax], R.p[ax], R.inv[ax]);
+    }
+}
+
+// Length parameter of ray R inside block-local voxel (ix, iy, iz): the slab test
+// with the same plane formula as walk_block. Returns dt (0 when the ray misses).
+template <int DIM>
+__device__ __forceinline__ float voxel_dt(const Ray& R, const int (&ix)[3], const float (&h)[3], const float (&vs)[3])
+{
+    float te = -INFINITY, tx = INFINITY;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (R.d[a] != 0.0f) {
+            float t0 = plane_t(ix[a], vs[a], h[a], R.p[a], R.inv[a]);
+            float t1 = plane_t(ix[a] + 1, vs[a], h[a], R.p[a], R.inv[a]);
+            te = fmaxf(te, fminf(t0, t1));
+            tx = fminf(tx, fmaxf(t0, t1));
+        } else {
+            if (!(plane_pos(ix[a], vs[a], h[a]) <= R.p[a] && R.p[a] < plane_pos(ix[a] + 1, vs[a], h[a])))
+                return 0.0f;
+        }
+    }
+    return fmaxf(tx - te, 0.0f);
+}
+
+// SplitMix64 output function and the counter-based draws (same definition as the
+// host runtime's selection streams).
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t hash3(uint64_t seed, uint64_t stream, uint64_t k1, uint64_t k2, uint64_t k3)
+{
+    uint64_t h = mix64(seed + 0x9E3779B97F4A7C15ull * (1ull + stream));
+    h = mix64(h ^ k1);
+    h = mix64(h ^ k2);
+    return mix64(h ^ k3);
+}
+
+}  // namespace bsgd

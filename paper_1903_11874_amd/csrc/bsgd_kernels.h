@@ -1,0 +1,66 @@
+// Host-callable launchers of the HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bsgd_device.h"
+
+namespace bsgd {
+
+// Per-iteration schedule record, int32, `stride` entries:
+//   [0]                    number of views in this iteration
+//   [1, 1+R)               selected row blocks (ascending)
+//   [1+R, 2+2R)            offsets of each selected row block's views into the view list
+//   [2+2R, 2+2R+B)         selected column blocks (ascending)
+//   [2+2R+B, +maxv)        view list (row blocks in order, views ascending in each)
+struct SchedLayout {
+    int32_t R, B, maxv, stride;
+    __host__ __device__ int off_rows() const { return 1; }
+    __host__ __device__ int off_gstart() const { return 1 + R; }
+    __host__ __device__ int off_blocks() const { return 2 + 2 * R; }
+    __host__ __device__ int off_views() const { return 2 + 2 * R + B; }
+};
+
+// Draws: int8 per (iteration, view slot, block slot); -1 = skip view, >= 0 sub-detector.
+constexpr int8_t DRAW_SKIP = -1;
+
+hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStream_t st);
+
+hipError_t launch_draws(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
+                        uint64_t seed, const uint32_t* q, int8_t* draws, hipStream_t st);
+
+hipError_t launch_fp_pairs(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+                           const float* x, float* z, hipStream_t st);
+
+hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const float* y,
+                        const float* z, float* r_sel, hipStream_t st);
+
+hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+                          const float* r_sel, float* ghat, float* gsum, float* x, float mu, int64_t n_vox,
+                          hipStream_t st);
+
+// Standalone projectors over a device view list (views[n_sel]); block < 0 = all blocks.
+hipError_t launch_fp_full(const DevGeom& G, const int32_t* views, int n_sel, int block, const float* x,
+                          float* y, int accumulate, hipStream_t st);
+hipError_t launch_bp_full(const DevGeom& G, const int32_t* views, int n_sel, int block, const float* y,
+                          float* x, float scale, int accumulate, hipStream_t st);
+
+// ||y - sum_j z^j||^2 over all rays into partials; returns number of partials written.
+hipError_t launch_resid_sumsq(const DevGeom& G, const float* y, const float* z, double* partials,
+                              int* n_partials, hipStream_t st);
+// sum of squares of a float array into partials.
+hipError_t launch_sumsq(const float* a, int64_t n, double* partials, int* n_partials, hipStream_t st);
+// out[0] = sum of partials[0..n) in index order.
+hipError_t launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
+
+// a[i] = b[i] - c[i]
+hipError_t launch_sub(const float* b, const float* c, float* a, int64_t n, hipStream_t st);
+hipError_t launch_fill(float* a, float v, int64_t n, hipStream_t st);
+
+// TV proximal step of BSGD-TV on x (in place): iters fast-gradient-projection steps.
+// p, ra, rb: device [dim][n_vox] scratch.
+hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float* p, float* ra, float* rb,
+                          hipStream_t st);
+
+}  // namespace bsgd

@@ -1,0 +1,753 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the BSGD hot path:
+//   forward projection of sampled (view, block) pairs      Algorithm 1/2, z refresh
+//   residual rebuild r = y - sum_j z^j on the sampled rows  Algorithm 1, residual line
+//   matched back projection fused with the block step      Algorithm 1, g_hat / g / x lines
+//   sub-detector draws and importance weights              Algorithm 2, Sec. II-A
+//   TV proximal step                                        Algorithm 4
+//   deterministic wave64 reductions for residual norms      Algorithm 3 (norm of r)
+// Projection is a sparse gather, not a dense contraction, so nothing here uses
+// MFMA. No kernel uses global atomics; every sum has a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "bsgd_device.h"
+#include "bsgd_kernels.h"
+
+namespace bsgd {
+
+namespace {
+
+constexpr int WG = 256;
+constexpr float SHADOW_EPS = 1e-3f;  // candidate-range margin of the voxel shadow, in pixels
+
+__device__ __forceinline__ void block_dims(const DevGeom& G, const BlockInfo& B, int (&nb)[3], float (&h)[3],
+                                           float (&vs)[3])
+{
+    nb[0] = B.nbx;
+    nb[1] = B.nby;
+    nb[2] = B.nbz;
+    h[0] = B.hx;
+    h[1] = B.hy;
+    h[2] = B.hz;
+    vs[0] = G.vx;
+    vs[1] = G.vy;
+    vs[2] = G.vz;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide (256 threads) double sum in a fixed order; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = ((lds[0] + lds[1]) + (lds[2] + lds[3]));
+    __syncthreads();
+    return r;
+}
+
+// Rectangle of pixels processed for one (view, block) pair: footprint, intersected
+// with the drawn sub-detector when s >= 0.
+__device__ __forceinline__ void pair_range(const DevGeom& G, const PairInfo& P, int s, int& k0, int& k1, int& l0,
+                                           int& l1)
+{
+    k0 = P.u0;
+    k1 = P.u1;
+    l0 = P.v0;
+    l1 = P.v1;
+    if (s >= 0) {
+        int a0, a1, b0, b1;
+        subdet_range(G, s, a0, a1, b0, b1);
+        k0 = max(k0, a0);
+        k1 = min(k1, a1);
+        l0 = max(l0, b0);
+        l1 = min(l1, b1);
+    }
+}
+
+// Forward projection of ray (k, l) through block j of view v: sum_i a_i x_i (mm * x).
+template <int DIM>
+__device__ __forceinline__ float fp_ray_block(const DevGeom& G, float c, float s, const PairInfo& P,
+                                              const BlockInfo& B, int k, int l, const float* __restrict__ x)
+{
+    Ray R;
+    make_ray<DIM>(G, c, s, P, k, l, R);
+    int nb[3];
+    float h[3], vs[3];
+    block_dims(G, B, nb, h, vs);
+    const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
+    const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
+    float acc = 0.0f;
+    walk_block<DIM>(R, nb, h, vs, [&](int ix, int iy, int iz, float dt) {
+        acc = fmaf(dt, xb[iz * sz + iy * sy + ix], acc);
+    });
+    return acc * R.len;
+}
+
+// Back projection of one view into one voxel: sum over candidate rays of a_ij r_i.
+// Candidates are the pixels inside the voxel's shadow (corner projections plus a
+// margin), clipped to [k0, k1) x [l0, l1).
+template <int DIM>
+__device__ __forceinline__ float bp_voxel_view(const DevGeom& G, float c, float s, const PairInfo& P,
+                                               const int (&li)[3], const float (&h)[3], const float (&vs)[3],
+                                               int k0, int k1, int l0, int l1, const float* __restrict__ rview)
+{
+    const float hvx = 0.5f * vs[0], hvy = 0.5f * vs[1];
+    const float qx = plane_pos(li[0], vs[0], h[0]) + hvx;
+    const float qy = plane_pos(li[1], vs[1], h[1]) + hvy;
+    const float w0 = fmaf(qy, c, -(qx * s));
+    const float d0 = -fmaf(qx, c, qy * s);
+    const float dwx = -hvx * s, dwy = hvy * c;
+    const float ddx = -hvx * c, ddy = -hvy * s;
+    const float ku = 0.5f * (float)(G.nu - 1);
+    const float inv_du = 1.0f / G.du;
+    const bool par = (G.kind == KIND_PARALLEL_2D);
+    float kmin = INFINITY, kmax = -INFINITY;
+    float rdep[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float sx = (q & 1) ? 1.0f : -1.0f, sy = (q & 2) ? 1.0f : -1.0f;
+        const float w = fmaf(sy, dwy, fmaf(sx, dwx, w0)) + P.cu;
+        float kk;
+        if (par) {
+            kk = fmaf(w, inv_du, ku);
+            rdep[q] = 0.0f;
+        } else {
+            const float dep = fmaf(sy, ddy, fmaf(sx, ddx, d0)) + P.depth;
+            rdep[q] = G.sdd / dep;
+            kk = fmaf(w * rdep[q], inv_du, ku);
+        }
+        kmin = fminf(kmin, kk);
+        kmax = fmaxf(kmax, kk);
+    }
+    // clamp in the float domain before converting (the range may be empty)
+    const int klo = max(k0, (int)ceilf(fminf(fmaxf(kmin - SHADOW_EPS, (float)k0), (float)k1)));
+    const int khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kmax + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
+    int llo = l0, lhi = l1 - 1;
+    if (DIM == 3) {
+        const float hvz = 0.5f * vs[2];
+        const float qz = plane_pos(li[2], vs[2], h[2]) + hvz;
+        const float lv = 0.5f * (float)(G.nv - 1);
+        const float inv_dv = 1.0f / G.dv;
+        float lmin = INFINITY, lmax = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const float zabs = P.cz + qz + (e ? hvz : -hvz);
+                const float ll = fmaf(zabs * rdep[q], inv_dv, lv);
+                lmin = fminf(lmin, ll);
+                lmax = fmaxf(lmax, ll);
+            }
+        }
+        llo = max(l0, (int)ceilf(fminf(fmaxf(lmin - SHADOW_EPS, (float)l0), (float)l1)));
+        lhi = min(l1 - 1, (int)floorf(fmaxf(fminf(lmax + SHADOW_EPS, (float)l1), (float)l0 - 1.0f)));
+    }
+    float acc = 0.0f;
+    for (int l = llo; l <= lhi; ++l) {
+        for (int k = klo; k <= khi; ++k) {
+            Ray R;
+            make_ray<DIM>(G, c, s, P, k, l, R);
+            const float dt = voxel_dt<DIM>(R, li, h, vs);
+            if (dt > 0.0f) acc = fmaf(dt * R.len, rview[(int64_t)l * G.nu + k], acc);
+        }
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------ geometry statistics
+
+// One wave per (view, block) pair: for every sub-detector s, w = sum over its rays
+// of sum_i a_i^2 and the number of positive-length segments.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict__ w, long long* __restrict__ nnz)
+{
+    const int wave = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int n_pairs = G.n_views * G.N;
+    if (wave >= n_pairs) return;
+    const int v = wave / G.N, j = wave % G.N;
+    const PairInfo P = G.pairs[wave];
+    const BlockInfo B = G.blocks[j];
+    const float2 cs = G.cs[v];
+    int nb[3];
+    float h[3], vs[3];
+    block_dims(G, B, nb, h, vs);
+    for (int sd = 0; sd < G.S; ++sd) {
+        int k0, k1, l0, l1;
+        pair_range(G, P, sd, k0, k1, l0, l1);
+        const int wk = k1 - k0, wl = l1 - l0;
+        const int n = (wk > 0 && wl > 0) ? wk * wl : 0;
+        double acc = 0.0;
+        long long cnt = 0;
+        for (int q = lane; q < n; q += 64) {
+            const int k = k0 + q % wk, l = l0 + q / wk;
+            Ray R;
+            make_ray<DIM>(G, cs.x, cs.y, P, k, l, R);
+            float s2 = 0.0f;
+            int ns = 0;
+            walk_block<DIM>(R, nb, h, vs, [&](int, int, int, float dt) {
+                s2 = fmaf(dt, dt, s2);
+                ns += dt > 0.0f;
+            });
+            acc += (double)s2 * (double)R.len * (double)R.len;
+            cnt += ns;
+        }
+        acc = wave_sum(acc);
+        cnt = wave_sum_ll(cnt);
+        if (lane == 0) {
+            const int64_t o = ((int64_t)v * G.S + sd) * G.N + j;
+            w[o] = acc;
+            nnz[o] = cnt;
+        }
+    }
+}
+
+// ------------------------------------------------------------ sampling draws
+
+__global__ __launch_bounds__(WG) void k_draws(DevGeom G, const int32_t* __restrict__ sched, SchedLayout L,
+                                              int n_iters, long long k0, unsigned long long seed,
+                                              const uint32_t* __restrict__ q, int8_t* __restrict__ draws)
+{
+    const int64_t per_it = (int64_t)L.maxv * L.B;
+    const int64_t gid = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (gid >= per_it * n_iters) return;
+    const int it = (int)(gid / per_it);
+    const int rem = (int)(gid % per_it);
+    const int a = rem / L.B, b = rem % L.B;
+    const int32_t* S_ = sched + (int64_t)it * L.stride;
+    int8_t out = DRAW_SKIP;
+    if (a < S_[0]) {
+        const int v = S_[L.off_views() + a];
+        const int j = S_[L.off_blocks() + b];
+        unsigned long long total = 0;
+        for (int s = 0; s < G.S; ++s) total += q[((int64_t)v * G.S + s) * G.N + j];
+        if (total > 0) {
+            const uint64_t hsh = hash3(seed, 4ull, (uint64_t)(k0 + it), (uint64_t)v, (uint64_t)j);
+            const uint64_t u = __umul64hi(hsh, total);
+            unsigned long long accq = 0;
+            int pick = G.S - 1;
+            for (int s = 0; s < G.S; ++s) {
+                accq += q[((int64_t)v * G.S + s) * G.N + j];
+                if (accq > u) {
+                    pick = s;
+                    break;
+                }
+            }
+            out = (int8_t)pick;
+        }
+    }
+    draws[gid] = out;
+}
+
+// ------------------------------------------------------------ solver: forward projection
+
+// One wave per (view slot, block slot) pair of the iteration: z^j = A_{rows}^{J_j} x_{J_j}
+// on the pair's footprint (restricted to the drawn sub-detector). Lanes walk
+// consecutive detector pixels, so z stores are contiguous.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
+                                                 const int8_t* __restrict__ draws, const float* __restrict__ x,
+                                                 float* __restrict__ z)
+{
+    const int wave = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int a = wave / L.B, b = wave % L.B;
+    if (a >= S_[0]) return;
+    int sd = -2;
+    if (draws) {
+        sd = draws[a * L.B + b];
+        if (sd == DRAW_SKIP) return;
+    }
+    const int v = S_[L.off_views() + a];
+    const int j = S_[L.off_blocks() + b];
+    const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+    const BlockInfo B = G.blocks[j];
+    const float2 cs = G.cs[v];
+    int k0, k1, l0, l1;
+    pair_range(G, P, sd, k0, k1, l0, l1);
+    const int wk = k1 - k0, wl = l1 - l0;
+    if (wk <= 0 || wl <= 0) return;
+    const int n = wk * wl;
+    const int W = P.u1 - P.u0;
+    for (int q = lane; q < n; q += 64) {
+        const int k = k0 + q % wk, l = l0 + q / wk;
+        const float val = fp_ray_block<DIM>(G, cs.x, cs.y, P, B, k, l, x);
+        z[P.zoff + (int64_t)(l - P.v0) * W + (k - P.u0)] = val;
+    }
+}
+
+// ------------------------------------------------------------ solver: residual rebuild
+
+// r = y - sum_j z^j for every ray of the iteration's views (j ascending).
+__global__ __launch_bounds__(WG) void k_resid(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
+                                              const float* __restrict__ y, const float* __restrict__ z,
+                                              float* __restrict__ r_sel)
+{
+    const int a = blockIdx.y;
+    if (a >= S_[0]) return;
+    const int per_view = G.nu * G.nv;
+    const int ray = blockIdx.x * WG + threadIdx.x;
+    if (ray >= per_view) return;
+    const int v = S_[L.off_views() + a];
+    const int k = ray % G.nu, l = ray / G.nu;
+    float acc = y[(int64_t)v * per_view + ray];
+    const PairInfo* pv = G.pairs + (int64_t)v * G.N;
+    for (int j = 0; j < G.N; ++j) {
+        const int4 rc = *reinterpret_cast<const int4*>(&pv[j].u0);
+        if (k >= rc.x && k < rc.y && l >= rc.z && l < rc.w)
+            acc -= z[pv[j].zoff + (int64_t)(l - rc.z) * (rc.y - rc.x) + (k - rc.x)];
+    }
+    r_sel[(int64_t)a * per_view + ray] = acc;
+}
+
+// ------------------------------------------------------------ solver: back projection + step
+
+template <int DIM>
+struct Tile;
+template <>
+struct Tile<2> {
+    static constexpr int X = 16, Y = 16, Z = 1;
+};
+template <>
+struct Tile<3> {
+    static constexpr int X = 8, Y = 8, Z = 4;
+};
+
+// One thread per voxel of a selected block: for each selected row block i,
+// g_hat^i_new = 2 (A_{rows(i,j)}^{J_j})^T r; g += sum_i (g_hat^i_new - g_hat^i_old);
+// g_hat^i = g_hat^i_new; then x += mu g. The voxel's update reads only r, so it
+// is independent of every other voxel (no atomics).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
+                                                const int8_t* __restrict__ draws, const float* __restrict__ r_sel,
+                                                float* __restrict__ ghat, float* __restrict__ gsum,
+                                                float* __restrict__ x, float mu, long long n_vox)
+{
+    const int b = blockIdx.y;
+    const int j = S_[L.off_blocks() + b];
+    const BlockInfo B = G.blocks[j];
+    int nb[3];
+    float h[3], vs[3];
+    block_dims(G, B, nb, h, vs);
+    const int tx_n = (nb[0] + Tile<DIM>::X - 1) / Tile<DIM>::X;
+    const int ty_n = (nb[1] + Tile<DIM>::Y - 1) / Tile<DIM>::Y;
+    const int tz_n = (nb[2] + Tile<DIM>::Z - 1) / Tile<DIM>::Z;
+    const int tile = blockIdx.x;
+    if (tile >= tx_n * ty_n * tz_n) return;
+    const int t_x = tile % tx_n, t_y = (tile / tx_n) % ty_n, t_z = tile / (tx_n * ty_n);
+    const int lx = threadIdx.x % Tile<DIM>::X;
+    const int ly = (threadIdx.x / Tile<DIM>::X) % Tile<DIM>::Y;
+    const int lz = threadIdx.x / (Tile<DIM>::X * Tile<DIM>::Y);
+    int li[3] = {t_x * Tile<DIM>::X + lx, t_y * Tile<DIM>::Y + ly, t_z * Tile<DIM>::Z + lz};
+    if (li[0] >= nb[0] || li[1] >= nb[1] || li[2] >= nb[2]) return;
+    const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
+    const int per_view = G.nu * G.nv;
+    const int nvs = S_[0];
+    (void)nvs;
+    float dg = 0.0f;
+    for (int ri = 0; ri < L.R; ++ri) {
+        const int i = S_[L.off_rows() + ri];
+        const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
+        float acc = 0.0f;
+        for (int a = a0; a < a1; ++a) {
+            int sd = -2;
+            if (draws) {
+                sd = draws[a * L.B + b];
+                if (sd == DRAW_SKIP) continue;
+            }
+            const int v = S_[L.off_views() + a];
+            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+            int k0, k1, l0, l1;
+            pair_range(G, P, sd, k0, k1, l0, l1);
+            if (k1 <= k0 || l1 <= l0) continue;
+            const float2 cs = G.cs[v];
+            acc += bp_voxel_view<DIM>(G, cs.x, cs.y, P, li, h, vs, k0, k1, l0, l1,
+                                      r_sel + (int64_t)a * per_view);
+        }
+        const float gnew = 2.0f * acc;
+        float* gp = ghat + (int64_t)i * n_vox + vox;
+        dg += gnew - *gp;
+        *gp = gnew;
+    }
+    const float gv = gsum[vox] + dg;
+    gsum[vox] = gv;
+    x[vox] = fmaf(mu, gv, x[vox]);
+}
+
+// ------------------------------------------------------------ standalone projectors
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fp_full(DevGeom G, const int32_t* __restrict__ views, int n_sel,
+                                                int j0, int j1, const float* __restrict__ x,
+                                                float* __restrict__ y, int accumulate)
+{
+    const int a = blockIdx.y;
+    const int per_view = G.nu * G.nv;
+    const int ray = blockIdx.x * WG + threadIdx.x;
+    if (a >= n_sel || ray >= per_view) return;
+    const int v = views[a];
+    const int k = ray % G.nu, l = ray / G.nu;
+    const float2 cs = G.cs[v];
+    float acc = 0.0f;
+    for (int j = j0; j < j1; ++j) {
+        const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+        if (k >= P.u0 && k < P.u1 && l >= P.v0 && l < P.v1)
+            acc += fp_ray_block<DIM>(G, cs.x, cs.y, P, G.blocks[j], k, l, x);
+    }
+    float* dst = y + (int64_t)a * per_view + ray;
+    *dst = accumulate ? *dst + acc : acc;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __restrict__ views, int n_sel, int j0,
+                                                const float* __restrict__ y, float* __restrict__ x, float scale,
+                                                int accumulate)
+{
+    const int j = j0 + blockIdx.y;
+    const BlockInfo B = G.blocks[j];
+    int nb[3];
+    float h[3], vs[3];
+    block_dims(G, B, nb, h, vs);
+    const int tx_n = (nb[0] + Tile<DIM>::X - 1) / Tile<DIM>::X;
+    const int ty_n = (nb[1] + Tile<DIM>::Y - 1) / Tile<DIM>::Y;
+    const int tz_n = (nb[2] + Tile<DIM>::Z - 1) / Tile<DIM>::Z;
+    const int tile = blockIdx.x;
+    if (tile >= tx_n * ty_n * tz_n) return;
+    const int t_x = tile % tx_n, t_y = (tile / tx_n) % ty_n, t_z = tile / (tx_n * ty_n);
+    const int lx = threadIdx.x % Tile<DIM>::X;
+    const int ly = (threadIdx.x / Tile<DIM>::X) % Tile<DIM>::Y;
+    const int lz = threadIdx.x / (Tile<DIM>::X * Tile<DIM>::Y);
+    int li[3] = {t_x * Tile<DIM>::X + lx, t_y * Tile<DIM>::Y + ly, t_z * Tile<DIM>::Z + lz};
+    if (li[0] >= nb[0] || li[1] >= nb[1] || li[2] >= nb[2]) return;
+    const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
+    const int per_view = G.nu * G.nv;
+    float acc = 0.0f;
+    for (int a = 0; a < n_sel; ++a) {
+        const int v = views[a];
+        const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+        if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
+        const float2 cs = G.cs[v];
+        acc += bp_voxel_view<DIM>(G, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
+                                  y + (int64_t)a * per_view);
+    }
+    const float val = scale * acc;
+    x[vox] = accumulate ? x[vox] + val : val;
+}
+
+// ------------------------------------------------------------ reductions
+
+__global__ __launch_bounds__(WG) void k_resid_sumsq(DevGeom G, const float* __restrict__ y,
+                                                    const float* __restrict__ z, double* __restrict__ partials)
+{
+    __shared__ double lds[4];
+    const int v = blockIdx.y;
+    const int per_view = G.nu * G.nv;
+    const int ray = blockIdx.x * WG + threadIdx.x;
+    double val = 0.0;
+    if (ray < per_view) {
+        const int k = ray % G.nu, l = ray / G.nu;
+        float acc = y[(int64_t)v * per_view + ray];
+        const PairInfo* pv = G.pairs + (int64_t)v * G.N;
+        for (int j = 0; j < G.N; ++j) {
+            const int4 rc = *reinterpret_cast<const int4*>(&pv[j].u0);
+            if (k >= rc.x && k < rc.y && l >= rc.z && l < rc.w)
+                acc -= z[pv[j].zoff + (int64_t)(l - rc.z) * (rc.y - rc.x) + (k - rc.x)];
+        }
+        val = (double)acc * (double)acc;
+    }
+    const double s = block_sum(val, lds);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(WG) void k_sumsq(const float* __restrict__ a, long long n, double* __restrict__ partials)
+{
+    __shared__ double lds[4];
+    double val = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) val += (double)a[i] * (double)a[i];
+    const double s = block_sum(val, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(WG) void k_sum_partials(const double* __restrict__ p, int n, double* __restrict__ out)
+{
+    __shared__ double lds[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += WG) v += p[i];
+    const double s = block_sum(v, lds);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ __launch_bounds__(WG) void k_sub(const float* __restrict__ b, const float* __restrict__ c,
+                                            float* __restrict__ a, long long n)
+{
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) a[i] = b[i] - c[i];
+}
+
+__global__ __launch_bounds__(WG) void k_fill(float* __restrict__ a, float v, long long n)
+{
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// ------------------------------------------------------------ TV proximal step (FGP)
+
+// D^T q at voxel (x, y, z) for the backward-difference gradient with zero
+// differences across the low boundary: sum_a [q_a(c) (c_a >= 1) - q_a(c + e_a) (c_a + 1 < n_a)].
+template <int DIM>
+__device__ __forceinline__ float div_adj(const float* __restrict__ q, int64_t nvox, int X, int Y, int Z, int nx,
+                                         int ny, int nz)
+{
+    const int64_t o = ((int64_t)Z * ny + Y) * nx + X;
+    float r = 0.0f;
+    if (X >= 1) r += q[o];
+    if (X + 1 < nx) r -= q[o + 1];
+    if (Y >= 1) r += q[nvox + o];
+    if (Y + 1 < ny) r -= q[nvox + o + nx];
+    if (DIM == 3) {
+        if (Z >= 1) r += q[2 * nvox + o];
+        if (Z + 1 < nz) r -= q[2 * nvox + o + (int64_t)nx * ny];
+    }
+    return r;
+}
+
+// One FGP step on the dual: p_new = P_ball(r + step D(b - w D^T r)); r_out = p_new + coef (p_new - p).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fgp_iter(const float* __restrict__ b, const float* __restrict__ rin,
+                                                 float* __restrict__ rout, float* __restrict__ p, int nx, int ny,
+                                                 int nz, float w, float step, float coef)
+{
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (o >= nvox) return;
+    const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
+    const float uc = b[o] - w * div_adj<DIM>(rin, nvox, X, Y, Z, nx, ny, nz);
+    float g[3] = {0.0f, 0.0f, 0.0f};
+    if (X >= 1) g[0] = uc - (b[o - 1] - w * div_adj<DIM>(rin, nvox, X - 1, Y, Z, nx, ny, nz));
+    if (Y >= 1) g[1] = uc - (b[o - nx] - w * div_adj<DIM>(rin, nvox, X, Y - 1, Z, nx, ny, nz));
+    if (DIM == 3 && Z >= 1)
+        g[2] = uc - (b[o - (int64_t)nx * ny] - w * div_adj<DIM>(rin, nvox, X, Y, Z - 1, nx, ny, nz));
+    float q[3];
+    float n2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        q[a] = fmaf(step, g[a], rin[a * nvox + o]);
+        n2 = fmaf(q[a], q[a], n2);
+    }
+    const float sc = 1.0f / fmaxf(1.0f, sqrtf(n2));
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const float pn = q[a] * sc;
+        const float po = p[a * nvox + o];
+        rout[a * nvox + o] = fmaf(coef, pn - po, pn);
+        p[a * nvox + o] = pn;
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fgp_final(float* __restrict__ x, const float* __restrict__ p, int nx, int ny,
+                                                  int nz, float w)
+{
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (o >= nvox) return;
+    const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
+    x[o] = x[o] - w * div_adj<DIM>(p, nvox, X, Y, Z, nx, ny, nz);
+}
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStream_t st)
+{
+    const int64_t waves = (int64_t)G.n_views * G.N;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (G.dim == 3)
+        hipLaunchKernelGGL(k_geom_stats<3>, dim3(blocks), dim3(WG), 0, st, G, w, (long long*)nnz);
+    else
+        hipLaunchKernelGGL(k_geom_stats<2>, dim3(blocks), dim3(WG), 0, st, G, w, (long long*)nnz);
+    return hipGetLastError();
+}
+
+hipError_t launch_draws(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
+                        uint64_t seed, const uint32_t* q, int8_t* draws, hipStream_t st)
+{
+    const int64_t n = (int64_t)n_iters * L.maxv * L.B;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_draws, dim3(grid1(n)), dim3(WG), 0, st, G, sched, L, n_iters, (long long)k0,
+                       (unsigned long long)seed, q, draws);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp_pairs(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+                           const float* x, float* z, hipStream_t st)
+{
+    const int64_t waves = (int64_t)L.maxv * L.B;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (G.dim == 3)
+        hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, sched_it, L, draws_it, x, z);
+    else
+        hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, sched_it, L, draws_it, x, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const float* y, const float* z,
+                        float* r_sel, hipStream_t st)
+{
+    const int per_view = G.nu * G.nv;
+    hipLaunchKernelGGL(k_resid, dim3(grid1(per_view), L.maxv), dim3(WG), 0, st, G, sched_it, L, y, z, r_sel);
+    return hipGetLastError();
+}
+
+static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int dim)
+{
+    (void)host_blocks_unused;
+    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by, mbz = (G.nz + G.bz - 1) / G.bz;
+    if (dim == 3)
+        return ((mbx + Tile<3>::X - 1) / Tile<3>::X) * ((mby + Tile<3>::Y - 1) / Tile<3>::Y) *
+               ((mbz + Tile<3>::Z - 1) / Tile<3>::Z);
+    return ((mbx + Tile<2>::X - 1) / Tile<2>::X) * ((mby + Tile<2>::Y - 1) / Tile<2>::Y);
+}
+
+hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+                          const float* r_sel, float* ghat, float* gsum, float* x, float mu, int64_t n_vox,
+                          hipStream_t st)
+{
+    const int tiles = max_tiles(G, nullptr, G.dim);
+    if (G.dim == 3)
+        hipLaunchKernelGGL(k_bp_step<3>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, L, draws_it, r_sel, ghat,
+                           gsum, x, mu, (long long)n_vox);
+    else
+        hipLaunchKernelGGL(k_bp_step<2>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, L, draws_it, r_sel, ghat,
+                           gsum, x, mu, (long long)n_vox);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp_full(const DevGeom& G, const int32_t* views, int n_sel, int block, const float* x, float* y,
+                          int accumulate, hipStream_t st)
+{
+    if (n_sel == 0) return hipSuccess;
+    const int per_view = G.nu * G.nv;
+    const int j0 = block < 0 ? 0 : block, j1 = block < 0 ? G.N : block + 1;
+    if (G.dim == 3)
+        hipLaunchKernelGGL(k_fp_full<3>, dim3(grid1(per_view), n_sel), dim3(WG), 0, st, G, views, n_sel, j0, j1, x,
+                           y, accumulate);
+    else
+        hipLaunchKernelGGL(k_fp_full<2>, dim3(grid1(per_view), n_sel), dim3(WG), 0, st, G, views, n_sel, j0, j1, x,
+                           y, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_full(const DevGeom& G, const int32_t* views, int n_sel, int block, const float* y, float* x,
+                          float scale, int accumulate, hipStream_t st)
+{
+    const int tiles = max_tiles(G, nullptr, G.dim);
+    const int j0 = block < 0 ? 0 : block, nj = block < 0 ? G.N : 1;
+    if (G.dim == 3)
+        hipLaunchKernelGGL(k_bp_full<3>, dim3(tiles, nj), dim3(WG), 0, st, G, views, n_sel, j0, y, x, scale,
+                           accumulate);
+    else
+        hipLaunchKernelGGL(k_bp_full<2>, dim3(tiles, nj), dim3(WG), 0, st, G, views, n_sel, j0, y, x, scale,
+                           accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_sumsq(const DevGeom& G, const float* y, const float* z, double* partials, int* n_partials,
+                              hipStream_t st)
+{
+    const int per_view = G.nu * G.nv;
+    const unsigned gx = grid1(per_view);
+    hipLaunchKernelGGL(k_resid_sumsq, dim3(gx, G.n_views), dim3(WG), 0, st, G, y, z, partials);
+    *n_partials = (int)(gx * G.n_views);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const float* a, int64_t n, double* partials, int* n_partials, hipStream_t st)
+{
+    int64_t blocks = (n + WG - 1) / WG;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_sumsq, dim3((unsigned)blocks), dim3(WG), 0, st, a, (long long)n, partials);
+    *n_partials = (int)blocks;
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* partials, int n, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(WG), 0, st, partials, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(const float* b, const float* c, float* a, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sub, dim3(grid1(n)), dim3(WG), 0, st, b, c, a, (long long)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* a, float v, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(WG), 0, st, a, v, (long long)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float* p, float* ra, float* rb,
+                          hipStream_t st)
+{
+    if (w <= 0.0f || iters <= 0) return hipSuccess;
+    const int64_t nvox = (int64_t)G.nx * G.ny * G.nz;
+    const int dim = G.dim;
+    hipError_t e = launch_fill(p, 0.0f, dim * nvox, st);
+    if (e != hipSuccess) return e;
+    e = launch_fill(ra, 0.0f, dim * nvox, st);
+    if (e != hipSuccess) return e;
+    const float step = (float)(1.0 / (4.0 * dim * (double)w));
+    double tk = 1.0;
+    float* rin = ra;
+    float* rout = rb;
+    for (int it = 0; it < iters; ++it) {
+        const double tn = (1.0 + sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
+        const float coef = (float)((tk - 1.0) / tn);
+        if (dim == 3)
+            hipLaunchKernelGGL(k_fgp_iter<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, rout, p, G.nx, G.ny, G.nz,
+                               w, step, coef);
+        else
+            hipLaunchKernelGGL(k_fgp_iter<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, rout, p, G.nx, G.ny, G.nz,
+                               w, step, coef);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        tk = tn;
+        float* t = rin;
+        rin = rout;
+        rout = t;
+    }
+    if (dim == 3)
+        hipLaunchKernelGGL(k_fgp_final<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, w);
+    else
+        hipLaunchKernelGGL(k_fgp_final<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, w);
+    return hipGetLastError();
+}
+
+}  // namespace bsgd

@@ -1,0 +1,56 @@
+"""Shared test utilities: small parity geometries, oracle caches, error metrics."""
+from __future__ import annotations
+
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from bsgd_inputs.configs import GeometrySpec
+
+
+def log(msg: str):
+    """Name the case on stdout before a GPU step (flushed, so a crash still shows it)."""
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def require_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# Small geometries: several column blocks with uneven tiles, view counts not divisible
+# by M, no ray lying exactly on a grid plane.
+PARALLEL_SMALL = GeometrySpec(kind="parallel2d", nx=37, ny=29, nz=1, vx=1.0, vy=1.0, vz=1.0, n_views=31,
+                              angle_span=math.pi, nu=48, nv=1, du=0.9, dv=1.0, bx=3, by=2, bz=1,
+                              n_row_blocks=4, partition_seed=21)
+FAN_SMALL = GeometrySpec(kind="fan2d", nx=41, ny=35, nz=1, vx=0.8, vy=0.8, vz=0.8, n_views=40,
+                         angle_span=2 * math.pi, nu=64, nv=1, du=1.1, dv=1.0, sod=60.0, sdd=130.0,
+                         bx=3, by=3, bz=1, n_row_blocks=5, partition_seed=22, su=3, sv=1)
+CONE_SMALL = GeometrySpec(kind="cone3d", nx=20, ny=18, nz=14, vx=1.0, vy=1.0, vz=1.0, n_views=24,
+                          angle_span=2 * math.pi, nu=28, nv=22, du=1.3, dv=1.3, sod=40.0, sdd=90.0,
+                          bx=2, by=3, bz=2, n_row_blocks=4, partition_seed=23, su=2, sv=2)
+SMALL = {"parallel": PARALLEL_SMALL, "fan": FAN_SMALL, "cone": CONE_SMALL}
+
+
+@functools.lru_cache(maxsize=16)
+def oracle_matrix(g: GeometrySpec):
+    from oracle.system import matrix
+    return matrix(g)
+
+
+@functools.lru_cache(maxsize=16)
+def oracle_problem(g: GeometrySpec):
+    from oracle.bsgd import Problem
+    return Problem.build(g, oracle_matrix(g))

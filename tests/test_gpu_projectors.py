@@ -1,0 +1,174 @@
+"""GPU parity of the forward / back projectors and geometry tables against the FP64 oracle.
+
+Bar: relative l2 error <= 1e-5 per output vector (FP32 device arithmetic vs FP64);
+integer tables (partitions, nonzero counts) exact.
+"""
+import numpy as np
+import pytest
+
+from bsgd_inputs.configs import workload
+from bsgd_inputs.phantoms import phantom_for, random_image
+from oracle import geometry as ogeo
+from oracle.bsgd import im_weights, quantise
+from oracle.cfast import Projector
+
+from helpers import SMALL, log, oracle_matrix, oracle_problem, rel_l2, require_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _geom(g, **kw):
+    from paper_1903_11874_amd import Geometry
+    return Geometry(g, **kw)
+
+
+@pytest.mark.parametrize("name", ["parallel", "fan", "cone"])
+def test_fp_bp_match_oracle_small(name):
+    import torch
+    dev = require_gpu()
+    g = SMALL[name]
+    log(f"projectors small {name}")
+    A = oracle_matrix(g)
+    geom = _geom(g)
+    x = random_image(A.shape[1], 11)
+    r = random_image(A.shape[0], 12, -1.0, 1.0)
+    xd = torch.tensor(x, dtype=torch.float32, device=dev)
+    rd = torch.tensor(r, dtype=torch.float32, device=dev)
+    x32 = xd.double().cpu().numpy()
+    r32 = rd.double().cpu().numpy()
+    y = geom.forward_project(xd).double().cpu().numpy()
+    assert rel_l2(y, A @ x32) <= TOL
+    b = geom.back_project(rd).double().cpu().numpy()
+    assert rel_l2(b, A.T @ r32) <= TOL
+    # one column block at a time, and a subset of views
+    views = [3, 0, 7, 12]
+    rows = np.concatenate([ogeo.rays_of_view(g, v) for v in views])
+    blocks = ogeo.column_blocks(g)
+    for j in (0, len(blocks) - 1, len(blocks) // 2):
+        J = blocks[j]
+        yj = geom.forward_project(xd, views=views, block=j).double().cpu().numpy()
+        ref = A[rows][:, J] @ x32[J]
+        assert rel_l2(yj, ref) <= TOL
+        rs = torch.tensor(r[: rows.size], dtype=torch.float32, device=dev)
+        out = torch.full((A.shape[1],), 7.0, dtype=torch.float32, device=dev)
+        geom.back_project(rs, views=views, block=j, scale=2.0, out=out)
+        o = out.double().cpu().numpy()
+        ref = 2.0 * (A[rows][:, J].T @ rs.double().cpu().numpy())
+        assert rel_l2(o[J], ref) <= TOL
+        mask = np.ones(A.shape[1], bool)
+        mask[J] = False
+        assert np.all(o[mask] == 7.0)
+    # accumulate flag
+    y2 = geom.forward_project(xd, out=torch.ones(A.shape[0], device=dev), accumulate=True)
+    assert rel_l2(y2.double().cpu().numpy(), A @ x32 + 1.0) <= TOL
+
+
+@pytest.mark.parametrize("name", ["parallel", "fan", "cone"])
+def test_tables_match_oracle(name):
+    require_gpu()
+    g = SMALL[name]
+    log(f"tables {name}")
+    p = oracle_problem(g)
+    geom = _geom(g)
+    assert geom.groups() == p.groups
+    # nonzero counts per (view, sub-detector, block)
+    nnz = geom.table("nnz")
+    A = p.A
+    for v in range(0, g.n_views, 5):
+        for s in range(g.su * g.sv):
+            rows = ogeo.subdetector_rays(g, v, s)
+            for j, J in enumerate(p.blocks):
+                ref = A[rows][:, J].nnz
+                assert abs(int(nnz[v, s, j]) - ref) <= max(1, ref // 5000), (v, s, j)
+    assert abs(geom.info["nnz"] - A.nnz) <= A.nnz * 1e-4
+    # importance weights and their quantisation
+    w_ref = im_weights(p)
+    w = geom.table("im_weights")
+    assert rel_l2(w, w_ref) <= TOL
+    q_ref = quantise(w_ref).astype(np.int64)
+    q = quantise(w).astype(np.int64)
+    assert np.max(np.abs(q - q_ref)) <= 1
+    # footprints contain every ray with a nonzero entry in the block
+    fp = geom.table("footprint")
+    for v in range(0, g.n_views, 7):
+        rows = ogeo.rays_of_view(g, v)
+        for j, J in enumerate(p.blocks):
+            hit = np.flatnonzero(np.asarray(A[rows][:, J].sum(axis=1)).ravel() > 1e-9)
+            k, l = hit % g.nu, hit // g.nu
+            u0, u1, v0, v1 = fp[v, j]
+            assert np.all((k >= u0) & (k < u1) & (l >= v0) & (l < v1))
+
+
+def test_colnorm_table_in_use():
+    require_gpu()
+    g = SMALL["fan"].with_(im_mode="colnorm")
+    geom = _geom(g)
+    q = geom.table("im_table").astype(np.int64)
+    q_ref = quantise(im_weights(oracle_problem(SMALL["fan"]))).astype(np.int64)
+    assert np.max(np.abs(q - q_ref)) <= 1
+    supplied = _geom(g, im_table=q_ref.astype(np.uint32))
+    assert np.array_equal(supplied.table("im_table").astype(np.int64), q_ref)
+
+
+@pytest.mark.parametrize("cfg", ["c2_fan512_im", "c3_cone256_tv"])
+def test_full_size_sampled_rays(cfg):
+    import torch
+    dev = require_gpu()
+    g = workload(cfg).geometry
+    log(f"full-size sampled FP {cfg}")
+    geom = _geom(g)
+    x = phantom_for(g, 8, 5)
+    xd = torch.tensor(x, dtype=torch.float32, device=dev)
+    y = geom.forward_project(xd).double().cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(9))
+    sample = np.sort(rng.choice(y.size, size=3000, replace=False))
+    P = Projector(g, rays=sample)
+    ref = P.fp(xd.double().cpu().numpy())
+    assert rel_l2(y[sample], ref) <= TOL
+
+
+def test_full_size_fan_back_projection():
+    import torch
+    dev = require_gpu()
+    g = workload("c2_fan512_im").geometry
+    log("full-size BP c2")
+    geom = _geom(g)
+    n_rays = g.n_views * g.nu
+    r = random_image(n_rays, 31, -1.0, 1.0)
+    rd = torch.tensor(r, dtype=torch.float32, device=dev)
+    b = geom.back_project(rd).double().cpu().numpy()
+    ref = Projector(g).bp(rd.double().cpu().numpy())
+    assert rel_l2(b, ref) <= TOL
+
+
+def test_full_size_cone_back_projection_view_subset():
+    import torch
+    dev = require_gpu()
+    g = workload("c3_cone256_tv").geometry
+    log("full-size BP c3 (6 views)")
+    geom = _geom(g)
+    views = [0, 61, 122, 183, 244, 305]
+    rows = np.concatenate([ogeo.rays_of_view(g, v) for v in views])
+    r = random_image(rows.size, 32, -1.0, 1.0)
+    rd = torch.tensor(r, dtype=torch.float32, device=dev)
+    b = geom.back_project(rd, views=views).double().cpu().numpy()
+    ref = Projector(g, rays=rows).bp(rd.double().cpu().numpy())
+    assert rel_l2(b, ref) <= TOL
+
+
+@pytest.mark.parametrize("cfg", ["c2_fan512_im", "c3_cone256_tv"])
+def test_adjoint_identity_full_size(cfg):
+    import torch
+    dev = require_gpu()
+    g = workload(cfg).geometry
+    log(f"adjoint {cfg}")
+    geom = _geom(g)
+    x = torch.tensor(random_image(g.nx * g.ny * g.nz, 41), dtype=torch.float32, device=dev)
+    r = torch.tensor(random_image(g.n_views * g.nu * g.nv, 42, -1, 1), dtype=torch.float32, device=dev)
+    ax = geom.forward_project(x).double()
+    atr = geom.back_project(r).double()
+    lhs = float(torch.dot(ax, r.double()))
+    rhs = float(torch.dot(x.double(), atr))
+    scale = float(torch.linalg.norm(ax) * torch.linalg.norm(r.double()))
+    assert abs(lhs - rhs) <= 1e-6 * scale
