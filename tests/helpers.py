@@ -38,8 +38,8 @@ PARALLEL_SMALL = GeometrySpec(kind="parallel2d", nx=37, ny=29, nz=1, vx=1.0, vy=
 FAN_SMALL = GeometrySpec(kind="fan2d", nx=41, ny=35, nz=1, vx=0.8, vy=0.8, vz=0.8, n_views=40,
                          angle_span=2 * math.pi, nu=64, nv=1, du=1.1, dv=1.0, sod=60.0, sdd=130.0,
                          bx=3, by=3, bz=1, n_row_blocks=5, partition_seed=22, su=3, sv=1)
-CONE_SMALL = GeometrySpec(kind="cone3d", nx=20, ny=18, nz=14, vx=1.0, vy=1.0, vz=1.0, n_views=24,
-                          angle_span=2 * math.pi, nu=28, nv=22, du=1.3, dv=1.3, sod=40.0, sdd=90.0,
+CONE_SMALL = GeometrySpec(kind="cone3d", nx=20, ny=18, nz=14, vx=1.0, vy=1.0, vz=0.947, n_views=24,
+                          angle_span=2 * math.pi, nu=28, nv=22, du=1.3, dv=1.2373, sod=40.0, sdd=90.0,
                           bx=2, by=3, bz=2, n_row_blocks=4, partition_seed=23, su=2, sv=2)
 SMALL = {"parallel": PARALLEL_SMALL, "fan": FAN_SMALL, "cone": CONE_SMALL}
 
