@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="untimed extra steps with per-kernel events (0 = events on in the timed region)")
     args = ap.parse_args()
@@ -111,6 +113,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = (1 << 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return
     from bsgd_inputs.configs import workload
     from bsgd_inputs.phantoms import phantom_for, poisson_log_noise
     from paper_1903_11874_amd import Geometry, Solver
