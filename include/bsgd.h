@@ -76,7 +76,7 @@ typedef struct {
     int32_t nu, nv;               /* detector pixels (nv = 1 in 2D) */
     double du, dv;                /* detector pitch, mm */
     double sod, sdd;              /* source-to-centre, source-to-detector, mm (fan/cone) */
-    int32_t bx, by, bz;           /* column-block tiling, N = bx by bz (bz = 1 in 2D) */
+    int32_t bx, by, bz;           /* column-block tiling, N = bx by bz <= 1024 (bz = 1 in 2D) */
     int32_t n_row_blocks;         /* M */
     uint64_t partition_seed;      /* seed of the view-to-row-block permutation */
     int32_t su, sv;               /* sub-detectors per view (IM), S = su sv <= 16 */
@@ -149,7 +149,8 @@ bsgd_status bsgd_back_project(const bsgd_geometry* geom, const float* y, float* 
  *   node_count P gives them through Eq. 1: gamma = min(1, P/N), alpha = P/(M N gamma)
  *   (non-integer results are rejected).
  * mu: the paper's step length; the update is g = 2 A^T r, x += mu g (Eq. (SGDITE)).
- * seed: selection and importance-sampling streams (counter-based, see DESIGN notes).
+ * seed: selection and importance-sampling streams. Every draw is a pure function of
+ *   (seed, stream, counters): SplitMix64 output function, keys folded one by one.
  * tv_lambda > 0 enables Algorithm 4: every tv_every iterations (0 = round(1/(alpha gamma)))
  *   x <- argmin_t ||t - x||^2 + 2 mu lambda TV(t) by tv_inner_iters fast-gradient-projection
  *   steps (isotropic TV, backward differences, zero difference across the low boundary).

@@ -162,7 +162,9 @@ struct bsgd_geometry {
     std::vector<double> im_w;
     std::vector<int64_t> im_nnz;
     std::vector<uint32_t> im_q;
-    DevBuf d_cs, d_pairs, d_blocks, d_q, d_all_views, d_views;
+    std::vector<float4> raydir;
+    std::vector<float2> rayv;
+    DevBuf d_cs, d_pairs, d_blocks, d_q, d_all_views, d_views, d_raydir, d_rayv;
     Staging stage;
     DevGeom dg{};
 };
@@ -189,7 +191,8 @@ static bsgd_status validate(const bsgd_geometry_desc* d)
     if ((int64_t)d->nx * d->ny * d->nz > ((int64_t)1 << 31) - 1) return fail(BSGD_E_INVALID_ARG, "volume too large");
     if (d->bx < 1 || d->by < 1 || d->bz < 1 || d->bx > d->nx || d->by > d->ny || d->bz > d->nz)
         return fail(BSGD_E_INVALID_ARG, "block tiling must satisfy 1 <= b <= n per axis");
-    if ((int64_t)d->bx * d->by * d->bz > 65535) return fail(BSGD_E_INVALID_ARG, "at most 65535 column blocks");
+    if ((int64_t)d->bx * d->by * d->bz > MAX_BLOCKS)
+        return fail(BSGD_E_INVALID_ARG, "at most %d column blocks", MAX_BLOCKS);
     if (d->n_row_blocks < 1 || d->n_row_blocks > d->n_views)
         return fail(BSGD_E_INVALID_ARG, "n_row_blocks must be in [1, n_views]");
     if (d->su < 1 || d->sv < 1 || d->su > d->nu || d->sv > d->nv || d->su * d->sv > 16)
@@ -355,6 +358,30 @@ static void build_tables(bsgd_geometry* g)
         }
     }
     g->z_floats = zoff;
+
+    // ray tables: reciprocal direction components and lengths, FP64 rounded once
+    auto recip = [](double a) { return a == 0.0 ? INFINITY : (float)(1.0 / a); };
+    g->raydir.resize((size_t)d.n_views * d.nu);
+    for (int v = 0; v < d.n_views; ++v) {
+        const double c = std::cos(d.angles_rad[v]), s = std::sin(d.angles_rad[v]);
+        for (int k = 0; k < d.nu; ++k) {
+            float4 T;
+            if (par) {
+                T = make_float4(recip(c), recip(s), 1.0f, 0.0f);
+            } else {
+                const double u = (k - ku) * d.du;
+                const double a = -d.sdd * c - u * s, b = -d.sdd * s + u * c;
+                const double n2 = d.sdd * d.sdd + u * u;
+                T = make_float4(recip(a), recip(b), is3d ? (float)n2 : (float)std::sqrt(n2), 0.0f);
+            }
+            g->raydir[(size_t)v * d.nu + k] = T;
+        }
+    }
+    g->rayv.resize(d.nv);
+    for (int l = 0; l < d.nv; ++l) {
+        const double vv = (l - lv) * d.dv;
+        g->rayv[l] = make_float2(recip(vv), (float)(vv * vv));
+    }
 }
 
 static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
@@ -369,6 +396,11 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     std::vector<int32_t> all(d.n_views);
     for (int v = 0; v < d.n_views; ++v) all[v] = v;
     HIP_TRY(g->d_all_views.alloc(all.size() * sizeof(int32_t)));
+    HIP_TRY(g->d_raydir.alloc(g->raydir.size() * sizeof(float4)));
+    HIP_TRY(g->d_rayv.alloc(g->rayv.size() * sizeof(float2)));
+    HIP_TRY(hipMemcpyAsync(g->d_raydir.p, g->raydir.data(), g->raydir.size() * sizeof(float4), hipMemcpyHostToDevice,
+                           st));
+    HIP_TRY(hipMemcpyAsync(g->d_rayv.p, g->rayv.data(), g->rayv.size() * sizeof(float2), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(g->d_cs.p, cs.data(), cs.size() * sizeof(float2), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(g->d_pairs.p, g->pairs.data(), g->pairs.size() * sizeof(PairInfo), hipMemcpyHostToDevice,
                            st));
@@ -403,6 +435,8 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.cs = g->d_cs.as<float2>();
     G.pairs = g->d_pairs.as<PairInfo>();
     G.blocks = g->d_blocks.as<BlockInfo>();
+    G.raydir = g->d_raydir.as<float4>();
+    G.rayv = g->d_rayv.as<float2>();
     return BSGD_OK;
 }
 
@@ -620,7 +654,7 @@ struct bsgd_solver {
     int64_t k = 0;
     bool failed = false, im = false;
     SchedLayout L{};
-    DevBuf z, ghat, gsum, r_sel, sched, draws, partials, norm_out, tv_p, tv_a, tv_b;
+    DevBuf z, ghat, gsum, r_sel, sched, draws, work, partials, norm_out, tv_p, tv_a, tv_b;
     int sched_cap = 0;
     Staging stage;
     double* norm_host = nullptr;
@@ -773,6 +807,7 @@ static bsgd_status ensure_sched(bsgd_solver* s, int n)
     HIP_TRY(hipStreamSynchronize(s->st));
     const int cap = std::max(n, 64);
     HIP_TRY(s->sched.alloc((size_t)cap * s->L.stride * sizeof(int32_t)));
+    HIP_TRY(s->work.alloc((size_t)cap * s->maxv * s->B * sizeof(PairWork)));
     if (s->im) HIP_TRY(s->draws.alloc((size_t)cap * s->maxv * s->B));
     s->sched_cap = cap;
     return BSGD_OK;
@@ -825,20 +860,22 @@ static bsgd_status step_impl(bsgd_solver* s, int n_iters)
     HIP_TRY(s->stage.upload(s->sched.p, sched_bytes, s->st));
     const int32_t* dsched = s->sched.as<int32_t>();
     int8_t* ddraws = s->im ? s->draws.as<int8_t>() : nullptr;
-    if (s->im) {
-        HIP_TRY(timed(s, KID_DRAW, [&] {
-            return launch_draws(g->dg, dsched, s->L, n_iters, s->k, s->o.seed, g->d_q.as<uint32_t>(), ddraws, s->st);
-        }));
-    }
-    const int64_t per_it_draws = (int64_t)s->maxv * s->B;
+    PairWork* dwork = s->work.as<PairWork>();
+    HIP_TRY(timed(s, KID_DRAW, [&] {
+        return launch_plan(g->dg, dsched, s->L, n_iters, s->k, s->o.seed, s->im ? g->d_q.as<uint32_t>() : nullptr,
+                           ddraws, dwork, s->st);
+    }));
+    const int64_t per_it_work = (int64_t)s->maxv * s->B;
     for (int it = 0; it < n_iters; ++it) {
         const int32_t* rec = dsched + (size_t)it * s->L.stride;
-        const int8_t* dr = ddraws ? ddraws + it * per_it_draws : nullptr;
-        HIP_TRY(timed(s, KID_FP, [&] { return launch_fp_pairs(g->dg, rec, s->L, dr, s->x, s->z.as<float>(), s->st); }));
+        const PairWork* wk = dwork + it * per_it_work;
+        HIP_TRY(timed(s, KID_FP, [&] {
+            return launch_fp_pairs(g->dg, wk, s->L, rec + s->L.off_blocks(), s->x, s->z.as<float>(), s->st);
+        }));
         HIP_TRY(timed(s, KID_RESID,
                       [&] { return launch_resid(g->dg, rec, s->L, s->y, s->z.as<float>(), s->r_sel.as<float>(), s->st); }));
         HIP_TRY(timed(s, KID_BP, [&] {
-            return launch_bp_step(g->dg, rec, s->L, dr, s->r_sel.as<float>(), s->ghat.as<float>(), s->gsum.as<float>(),
+            return launch_bp_step(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->ghat.as<float>(), s->gsum.as<float>(),
                                   s->x, (float)s->o.mu, g->n_vox, s->st);
         }));
         s->k += 1;

@@ -10,8 +10,11 @@
 // the block centre; au, bu, kc are derived in FP64 on the host per (view, block).
 // The direction is the unnormalised source-to-pixel vector (a, b[, v]) with
 // |(a, b, v)| = sqrt(sdd^2 + u^2 + v^2) (fan / cone) or the unit vector (parallel).
-// The walk parameter t is in units of that length; a_ij = dt * |d|. All plane
-// positions are block-local, X_i = i v - h, exact in FP32.
+// Its reciprocals and length are precomputed in FP64 per (view, pixel column) and
+// per pixel row (ray tables), so every kernel reads identical values. The walk
+// parameter t is in units of that length; a_ij = dt * |d|. All plane positions are
+// block-local, X_i = i v - h, exact in FP32. A direction component that is exactly
+// zero is stored as an infinite reciprocal; such an axis is never crossed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,6 +33,21 @@ struct PairInfo {
     float cu;                // block centre . e_u (mm)
     float depth;             // source to block-centre plane distance (mm); 0 for parallel
     float cz;                // block centre z (mm)
+    int32_t pad;
+};
+
+// Work record of one (view slot, block slot) pair of one iteration, written by the
+// plan kernel: the pixel range to process (footprint, restricted to the drawn
+// sub-detector), the z addressing and the ray anchors of the pair. 80 bytes.
+struct PairWork {
+    int32_t k0, k1, l0, l1;  // half-open pixel ranges; empty when k1 <= k0
+    int64_t zbase;           // z index of pixel (k, l) is zbase + l * zw + k
+    int32_t zw;              // footprint width (row stride of the z slot)
+    int32_t view;
+    float au, bu, av, bv;    // as in PairInfo
+    int32_t kc, lc;
+    float cu, depth, cz;
+    float c, s;              // cos, sin of the view angle
     int32_t pad;
 };
 
@@ -52,6 +70,8 @@ struct DevGeom {
     const float2* cs;          // [n_views] (cos, sin)
     const PairInfo* pairs;     // [n_views][N]
     const BlockInfo* blocks;   // [N]
+    const float4* raydir;      // [n_views][nu]: 1/a, 1/b, |(a,b)|^2 (cone) or |d| (2D), unused
+    const float2* rayv;        // [nv]: 1/v, v^2 (cone only)
 };
 
 // Sub-detector s covers u in [k0, k1), v in [l0, l1).
@@ -67,37 +87,31 @@ __device__ __forceinline__ void subdet_range(const DevGeom& G, int s, int& k0, i
 // Ray (k, l) of a view, in the block-local frame of pair P.
 struct Ray {
     float p[3];    // point on the block-centre plane, block-local (mm)
-    float d[3];    // direction, unnormalised
-    float inv[3];  // reciprocal of d (inf for a zero component)
+    float inv[3];  // reciprocal of the direction (inf for a zero component)
     float len;     // |d| (mm per unit t)
 };
 
-template <int DIM>
-__device__ __forceinline__ void make_ray(const DevGeom& G, float c, float s, const PairInfo& P, int k, int l,
-                                         Ray& R)
+__device__ __forceinline__ bool axis_fixed(float inv) { return __builtin_isinf(inv); }
+
+// P is a PairInfo or a PairWork (same anchor fields).
+template <int DIM, class Anchor>
+__device__ __forceinline__ void make_ray(const DevGeom& G, int view, float c, float s, const Anchor& P, int k,
+                                         int l, Ray& R)
 {
-    float lu = fmaf((float)(k - P.kc), P.au, P.bu);
+    const float lu = fmaf((float)(k - P.kc), P.au, P.bu);
     R.p[0] = -lu * s;
     R.p[1] = lu * c;
-    if (G.kind == KIND_PARALLEL_2D) {
-        R.d[0] = c;
-        R.d[1] = s;
-        R.len = 1.0f;
+    const float4 T = G.raydir[(int64_t)view * G.nu + k];
+    R.inv[0] = T.x;
+    R.inv[1] = T.y;
+    if (DIM == 3) {
+        R.p[2] = fmaf((float)(l - P.lc), P.av, P.bv);
+        const float2 V = G.rayv[l];
+        R.inv[2] = V.x;
+        R.len = __builtin_amdgcn_sqrtf(T.z + V.y);
     } else {
-        float u = ((float)k - 0.5f * (float)(G.nu - 1)) * G.du;
-        R.d[0] = fmaf(-G.sdd, c, -(u * s));
-        R.d[1] = fmaf(-G.sdd, s, u * c);
-        float n2 = fmaf(u, u, G.sdd * G.sdd);
-        if (DIM == 3) {
-            float v = ((float)l - 0.5f * (float)(G.nv - 1)) * G.dv;
-            R.d[2] = v;
-            n2 = fmaf(v, v, n2);
-        }
-        R.len = sqrtf(n2);
+        R.len = T.z;
     }
-    if (DIM == 3) R.p[2] = fmaf((float)(l - P.lc), P.av, P.bv);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) R.inv[a] = 1.0f / R.d[a];
 }
 
 __device__ __forceinline__ float plane_pos(int i, float v, float h) { return fmaf((float)i, v, -h); }
@@ -107,9 +121,50 @@ __device__ __forceinline__ float plane_t(int i, float v, float h, float p, float
     return (plane_pos(i, v, h) - p) * inv;
 }
 
+// Entry voxel index along one axis at parameter tlo, exact with respect to plane_t,
+// the next crossing parameter and the step direction.
+__device__ __forceinline__ void walk_axis_init(const Ray& R, int a, int n, float h, float vs, float tlo, int& idx,
+                                               int& step, float& tn)
+{
+    const bool fixed = axis_fixed(R.inv[a]);
+    // estimate only: the loops below make the index exact with respect to plane_t
+    const float pos = fixed ? R.p[a] : fmaf(tlo, __builtin_amdgcn_rcpf(R.inv[a]), R.p[a]);
+    float fi = floorf((pos + h) * __builtin_amdgcn_rcpf(vs));
+    fi = fminf(fmaxf(fi, 0.0f), (float)(n - 1));
+    int i = (int)fi;
+    step = 0;
+    tn = INFINITY;
+    if (fixed) {
+        while (i < n - 1 && R.p[a] >= plane_pos(i + 1, vs, h)) ++i;
+        while (i > 0 && R.p[a] < plane_pos(i, vs, h)) --i;
+    } else if (R.inv[a] > 0.0f) {
+        while (i < n - 1 && plane_t(i + 1, vs, h, R.p[a], R.inv[a]) <= tlo) ++i;
+        while (i > 0 && plane_t(i, vs, h, R.p[a], R.inv[a]) > tlo) --i;
+        step = 1;
+        tn = plane_t(i + 1, vs, h, R.p[a], R.inv[a]);
+    } else {
+        while (i > 0 && plane_t(i, vs, h, R.p[a], R.inv[a]) <= tlo) --i;
+        while (i < n - 1 && plane_t(i + 1, vs, h, R.p[a], R.inv[a]) > tlo) ++i;
+        step = -1;
+        tn = plane_t(i, vs, h, R.p[a], R.inv[a]);
+    }
+    idx = i;
+}
+
+// Cross the next plane of one axis: returns false when the walk leaves the block.
+__device__ __forceinline__ bool walk_axis_step(const Ray& R, int a, int n, float h, float vs, int& idx, int step,
+                                               float& tn)
+{
+    const int ni = idx + step;
+    if (step == 0 || ni < 0 || ni >= n) return false;
+    idx = ni;
+    tn = plane_t(step > 0 ? ni + 1 : ni, vs, h, R.p[a], R.inv[a]);
+    return true;
+}
+
 // Ray-driven Siddon walk through one block. visit(ix, iy, iz, dt) is called for
 // every voxel the ray crosses, in order, with the parameter length dt >= 0
-// (dt = 0 at exact corner crossings).
+// (dt = 0 at exact corner crossings; ties cross the lowest axis first).
 template <int DIM, class Visit>
 __device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], const float (&h)[3],
                                            const float (&vs)[3], Visit&& visit)
@@ -119,7 +174,7 @@ __device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], con
     for (int a = 0; a < DIM; ++a) {
         float X0 = -h[a];
         float Xn = plane_pos(nb[a], vs[a], h[a]);
-        if (R.d[a] != 0.0f) {
+        if (!axis_fixed(R.inv[a])) {
             float t0 = (X0 - R.p[a]) * R.inv[a];
             float t1 = (Xn - R.p[a]) * R.inv[a];
             tlo = fmaxf(tlo, fminf(t0, t1));
@@ -130,46 +185,28 @@ __device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], con
     }
     if (!(tlo < thi)) return;
 
-    int idx[3] = {0, 0, 0};
-    int step[3] = {0, 0, 0};
-    float tn[3] = {INFINITY, INFINITY, INFINITY};
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const int n = nb[a];
-        float pos = (R.d[a] != 0.0f) ? fmaf(tlo, R.d[a], R.p[a]) : R.p[a];
-        float fi = floorf((pos + h[a]) / vs[a]);
-        fi = fminf(fmaxf(fi, 0.0f), (float)(n - 1));
-        int i = (int)fi;
-        if (R.d[a] > 0.0f) {
-            while (i < n - 1 && plane_t(i + 1, vs[a], h[a], R.p[a], R.inv[a]) <= tlo) ++i;
-            while (i > 0 && plane_t(i, vs[a], h[a], R.p[a], R.inv[a]) > tlo) --i;
-            step[a] = 1;
-            tn[a] = plane_t(i + 1, vs[a], h[a], R.p[a], R.inv[a]);
-        } else if (R.d[a] < 0.0f) {
-            while (i > 0 && plane_t(i, vs[a], h[a], R.p[a], R.inv[a]) <= tlo) --i;
-            while (i < n - 1 && plane_t(i + 1, vs[a], h[a], R.p[a], R.inv[a]) > tlo) ++i;
-            step[a] = -1;
-            tn[a] = plane_t(i, vs[a], h[a], R.p[a], R.inv[a]);
-        } else {
-            while (i < n - 1 && R.p[a] >= plane_pos(i + 1, vs[a], h[a])) ++i;
-            while (i > 0 && R.p[a] < plane_pos(i, vs[a], h[a])) --i;
-        }
-        idx[a] = i;
-    }
+    int ix, iy, iz = 0, sx, sy, sz = 0;
+    float tx, ty, tz = INFINITY;
+    walk_axis_init(R, 0, nb[0], h[0], vs[0], tlo, ix, sx, tx);
+    walk_axis_init(R, 1, nb[1], h[1], vs[1], tlo, iy, sy, ty);
+    if (DIM == 3) walk_axis_init(R, 2, nb[2], h[2], vs[2], tlo, iz, sz, tz);
 
     float t = tlo;
-    const int max_steps = nb[0] + (DIM > 1 ? nb[1] : 0) + (DIM > 2 ? nb[2] : 0) + 2;
+    const int max_steps = nb[0] + nb[1] + (DIM == 3 ? nb[2] : 0) + 2;
     for (int it = 0; it < max_steps; ++it) {
-        float tm = tn[0];
-        int ax = 0;
-        if (DIM > 1 && tn[1] < tm) { tm = tn[1]; ax = 1; }
-        if (DIM > 2 && tn[2] < tm) { tm = tn[2]; ax = 2; }
-        visit(idx[0], idx[1], idx[2], tm - t);
-        t = tm;
-        int ni = idx[ax] + step[ax];
-        if (step[ax] == 0 || ni < 0 || ni >= nb[ax]) break;
-        idx[ax] = ni;
-        tn[ax] = plane_t(step[ax] > 0 ? ni + 1 : ni, vs[ax], h[ax], R.p[ax], R.inv[ax]);
+        if (tx <= ty && (DIM == 2 || tx <= tz)) {
+            visit(ix, iy, iz, tx - t);
+            t = tx;
+            if (!walk_axis_step(R, 0, nb[0], h[0], vs[0], ix, sx, tx)) break;
+        } else if (DIM == 2 || ty <= tz) {
+            visit(ix, iy, iz, ty - t);
+            t = ty;
+            if (!walk_axis_step(R, 1, nb[1], h[1], vs[1], iy, sy, ty)) break;
+        } else {
+            visit(ix, iy, iz, tz - t);
+            t = tz;
+            if (!walk_axis_step(R, 2, nb[2], h[2], vs[2], iz, sz, tz)) break;
+        }
     }
 }
 
@@ -181,7 +218,7 @@ __device__ __forceinline__ float voxel_dt(const Ray& R, const int (&ix)[3], cons
     float te = -INFINITY, tx = INFINITY;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        if (R.d[a] != 0.0f) {
+        if (!axis_fixed(R.inv[a])) {
             float t0 = plane_t(ix[a], vs[a], h[a], R.p[a], R.inv[a]);
             float t1 = plane_t(ix[a] + 1, vs[a], h[a], R.p[a], R.inv[a]);
             te = fmaxf(te, fminf(t0, t1));

@@ -25,18 +25,27 @@ struct SchedLayout {
 // Draws: int8 per (iteration, view slot, block slot); -1 = skip view, >= 0 sub-detector.
 constexpr int8_t DRAW_SKIP = -1;
 
+// Maximum column blocks per geometry (the residual kernels stage one view's
+// footprint rectangles in LDS).
+constexpr int MAX_BLOCKS = 1024;
+// Views per workgroup of the LDS-staged forward projector (tunable).
+extern int fp_chunk_views;
+
 hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStream_t st);
 
-hipError_t launch_draws(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
-                        uint64_t seed, const uint32_t* q, int8_t* draws, hipStream_t st);
+// Draws (when q != NULL) and per-(block slot, view slot) work records for n_iters
+// iterations: draws [n][maxv][B] (may be NULL), work [n][B][maxv].
+hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
+                       uint64_t seed, const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st);
 
-hipError_t launch_fp_pairs(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+// blocks_sel: the iteration's selected blocks (device, inside its schedule record).
+hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,
                            const float* x, float* z, hipStream_t st);
 
 hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const float* y,
                         const float* z, float* r_sel, hipStream_t st);
 
-hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
                           const float* r_sel, float* ghat, float* gsum, float* x, float mu, int64_t n_vox,
                           hipStream_t st);
 

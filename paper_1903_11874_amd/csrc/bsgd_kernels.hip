@@ -11,6 +11,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "bsgd_device.h"
 #include "bsgd_kernels.h"
 
@@ -82,17 +84,17 @@ __device__ __forceinline__ void pair_range(const DevGeom& G, const PairInfo& P, 
 }
 
 // Forward projection of ray (k, l) through block j of view v: sum_i a_i x_i (mm * x).
-template <int DIM>
-__device__ __forceinline__ float fp_ray_block(const DevGeom& G, float c, float s, const PairInfo& P,
-                                              const BlockInfo& B, int k, int l, const float* __restrict__ x)
+// xb points at the block's first voxel with row stride sy and slice stride sz (global
+// memory or an LDS copy of the block).
+template <int DIM, class Anchor, class Ptr>
+__device__ __forceinline__ float fp_ray_block(const DevGeom& G, int view, float c, float s, const Anchor& P,
+                                              const BlockInfo& B, int k, int l, Ptr xb, int64_t sy, int64_t sz)
 {
     Ray R;
-    make_ray<DIM>(G, c, s, P, k, l, R);
+    make_ray<DIM>(G, view, c, s, P, k, l, R);
     int nb[3];
     float h[3], vs[3];
     block_dims(G, B, nb, h, vs);
-    const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
-    const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
     float acc = 0.0f;
     walk_block<DIM>(R, nb, h, vs, [&](int ix, int iy, int iz, float dt) {
         acc = fmaf(dt, xb[iz * sz + iy * sy + ix], acc);
@@ -103,8 +105,8 @@ __device__ __forceinline__ float fp_ray_block(const DevGeom& G, float c, float s
 // Back projection of one view into one voxel: sum over candidate rays of a_ij r_i.
 // Candidates are the pixels inside the voxel's shadow (corner projections plus a
 // margin), clipped to [k0, k1) x [l0, l1).
-template <int DIM>
-__device__ __forceinline__ float bp_voxel_view(const DevGeom& G, float c, float s, const PairInfo& P,
+template <int DIM, class Anchor>
+__device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float c, float s, const Anchor& P,
                                                const int (&li)[3], const float (&h)[3], const float (&vs)[3],
                                                int k0, int k1, int l0, int l1, const float* __restrict__ rview)
 {
@@ -116,7 +118,7 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, float c, float 
     const float dwx = -hvx * s, dwy = hvy * c;
     const float ddx = -hvx * c, ddy = -hvy * s;
     const float ku = 0.5f * (float)(G.nu - 1);
-    const float inv_du = 1.0f / G.du;
+    const float inv_du = __builtin_amdgcn_rcpf(G.du);
     const bool par = (G.kind == KIND_PARALLEL_2D);
     float kmin = INFINITY, kmax = -INFINITY;
     float rdep[4];
@@ -130,7 +132,7 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, float c, float 
             rdep[q] = 0.0f;
         } else {
             const float dep = fmaf(sy, ddy, fmaf(sx, ddx, d0)) + P.depth;
-            rdep[q] = G.sdd / dep;
+            rdep[q] = G.sdd * __builtin_amdgcn_rcpf(dep);
             kk = fmaf(w * rdep[q], inv_du, ku);
         }
         kmin = fminf(kmin, kk);
@@ -144,7 +146,7 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, float c, float 
         const float hvz = 0.5f * vs[2];
         const float qz = plane_pos(li[2], vs[2], h[2]) + hvz;
         const float lv = 0.5f * (float)(G.nv - 1);
-        const float inv_dv = 1.0f / G.dv;
+        const float inv_dv = __builtin_amdgcn_rcpf(G.dv);
         float lmin = INFINITY, lmax = -INFINITY;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -163,7 +165,7 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, float c, float 
     for (int l = llo; l <= lhi; ++l) {
         for (int k = klo; k <= khi; ++k) {
             Ray R;
-            make_ray<DIM>(G, c, s, P, k, l, R);
+            make_ray<DIM>(G, view, c, s, P, k, l, R);
             const float dt = voxel_dt<DIM>(R, li, h, vs);
             if (dt > 0.0f) acc = fmaf(dt * R.len, rview[(int64_t)l * G.nu + k], acc);
         }
@@ -178,7 +180,7 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, float c, float 
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict__ w, long long* __restrict__ nnz)
 {
-    const int wave = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (WG / 64) + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int n_pairs = G.n_views * G.N;
     if (wave >= n_pairs) return;
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict
         for (int q = lane; q < n; q += 64) {
             const int k = k0 + q % wk, l = l0 + q / wk;
             Ray R;
-            make_ray<DIM>(G, cs.x, cs.y, P, k, l, R);
+            make_ray<DIM>(G, v, cs.x, cs.y, P, k, l, R);
             float s2 = 0.0f;
             int ns = 0;
             walk_block<DIM>(R, nb, h, vs, [&](int, int, int, float dt) {
@@ -219,176 +221,298 @@ __global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict
     }
 }
 
-// ------------------------------------------------------------ sampling draws
+// ------------------------------------------------------------ iteration plan (draws + work records)
 
-__global__ __launch_bounds__(WG) void k_draws(DevGeom G, const int32_t* __restrict__ sched, SchedLayout L,
-                                              int n_iters, long long k0, unsigned long long seed,
-                                              const uint32_t* __restrict__ q, int8_t* __restrict__ draws)
+// One thread per (iteration, block slot, view slot): draw the sub-detector of
+// Algorithm 2 when sampling is on (counter-based: hash of (seed, IM stream, k,
+// view, block), first s whose running sum of q exceeds bounded(hash, sum q)), and
+// write the pair's work record. Draws are stored [it][view slot][block slot] for
+// export; records [it][block slot][view slot] so that a block's views are contiguous.
+__global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restrict__ sched, SchedLayout L,
+                                             int n_iters, long long k0, unsigned long long seed,
+                                             const uint32_t* __restrict__ q, int8_t* __restrict__ draws,
+                                             PairWork* __restrict__ work)
 {
     const int64_t per_it = (int64_t)L.maxv * L.B;
     const int64_t gid = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (gid >= per_it * n_iters) return;
     const int it = (int)(gid / per_it);
     const int rem = (int)(gid % per_it);
-    const int a = rem / L.B, b = rem % L.B;
+    const int b = rem / L.maxv, a = rem % L.maxv;
     const int32_t* S_ = sched + (int64_t)it * L.stride;
-    int8_t out = DRAW_SKIP;
+    PairWork W;
+    W.k0 = W.k1 = W.l0 = W.l1 = 0;
+    W.zbase = 0;
+    W.zw = 0;
+    W.view = 0;
+    W.au = W.bu = W.av = W.bv = 0.0f;
+    W.kc = W.lc = 0;
+    W.cu = W.depth = W.cz = 0.0f;
+    W.c = W.s = 0.0f;
+    W.pad = 0;
+    int8_t dr = DRAW_SKIP;
     if (a < S_[0]) {
         const int v = S_[L.off_views() + a];
         const int j = S_[L.off_blocks() + b];
-        unsigned long long total = 0;
-        for (int s = 0; s < G.S; ++s) total += q[((int64_t)v * G.S + s) * G.N + j];
-        if (total > 0) {
-            const uint64_t hsh = hash3(seed, 4ull, (uint64_t)(k0 + it), (uint64_t)v, (uint64_t)j);
-            const uint64_t u = __umul64hi(hsh, total);
-            unsigned long long accq = 0;
-            int pick = G.S - 1;
-            for (int s = 0; s < G.S; ++s) {
-                accq += q[((int64_t)v * G.S + s) * G.N + j];
-                if (accq > u) {
-                    pick = s;
-                    break;
+        int sd = -2;
+        if (q) {
+            unsigned long long total = 0;
+            for (int t = 0; t < G.S; ++t) total += q[((int64_t)v * G.S + t) * G.N + j];
+            sd = DRAW_SKIP;
+            if (total > 0) {
+                const uint64_t hsh = hash3(seed, 4ull, (uint64_t)(k0 + it), (uint64_t)v, (uint64_t)j);
+                const uint64_t u = __umul64hi(hsh, total);
+                unsigned long long accq = 0;
+                sd = G.S - 1;
+                for (int t = 0; t < G.S; ++t) {
+                    accq += q[((int64_t)v * G.S + t) * G.N + j];
+                    if (accq > u) {
+                        sd = t;
+                        break;
+                    }
                 }
             }
-            out = (int8_t)pick;
+            dr = (int8_t)sd;
+        }
+        if (sd != DRAW_SKIP) {
+            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+            pair_range(G, P, sd, W.k0, W.k1, W.l0, W.l1);
+            if (W.k1 <= W.k0 || W.l1 <= W.l0) W.k0 = W.k1 = W.l0 = W.l1 = 0;
+            W.zw = P.u1 - P.u0;
+            W.zbase = P.zoff - (int64_t)P.v0 * W.zw - P.u0;
+            W.view = v;
+            W.au = P.au;
+            W.bu = P.bu;
+            W.av = P.av;
+            W.bv = P.bv;
+            W.kc = P.kc;
+            W.lc = P.lc;
+            W.cu = P.cu;
+            W.depth = P.depth;
+            W.cz = P.cz;
+            const float2 cs = G.cs[v];
+            W.c = cs.x;
+            W.s = cs.y;
         }
     }
-    draws[gid] = out;
+    if (draws) draws[(int64_t)it * per_it + (int64_t)a * L.B + b] = dr;
+    work[gid] = W;
 }
 
 // ------------------------------------------------------------ solver: forward projection
 
-// One wave per (view slot, block slot) pair of the iteration: z^j = A_{rows}^{J_j} x_{J_j}
-// on the pair's footprint (restricted to the drawn sub-detector). Lanes walk
-// consecutive detector pixels, so z stores are contiguous.
+// One wave per (view slot, block slot) pair: z^j = A_{rows}^{J_j} x_{J_j} on the
+// pair's range. Lanes walk consecutive detector pixels, so z stores are contiguous.
+// x is gathered from global memory (blocks too large for LDS).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
-                                                 const int8_t* __restrict__ draws, const float* __restrict__ x,
+__global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
+                                                 const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
                                                  float* __restrict__ z)
 {
-    const int wave = blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (WG / 64) + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int a = wave / L.B, b = wave % L.B;
-    if (a >= S_[0]) return;
-    int sd = -2;
-    if (draws) {
-        sd = draws[a * L.B + b];
-        if (sd == DRAW_SKIP) return;
-    }
-    const int v = S_[L.off_views() + a];
-    const int j = S_[L.off_blocks() + b];
-    const PairInfo P = G.pairs[(int64_t)v * G.N + j];
-    const BlockInfo B = G.blocks[j];
-    const float2 cs = G.cs[v];
-    int k0, k1, l0, l1;
-    pair_range(G, P, sd, k0, k1, l0, l1);
-    const int wk = k1 - k0, wl = l1 - l0;
+    if (wave >= L.maxv * L.B) return;
+    const int b = wave / L.maxv;
+    const PairWork W = work[wave];
+    const int wk = W.k1 - W.k0, wl = W.l1 - W.l0;
     if (wk <= 0 || wl <= 0) return;
+    const BlockInfo B = G.blocks[blocks_sel[b]];
+    const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
+    const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
     const int n = wk * wl;
-    const int W = P.u1 - P.u0;
     for (int q = lane; q < n; q += 64) {
-        const int k = k0 + q % wk, l = l0 + q / wk;
-        const float val = fp_ray_block<DIM>(G, cs.x, cs.y, P, B, k, l, x);
-        z[P.zoff + (int64_t)(l - P.v0) * W + (k - P.u0)] = val;
+        const int k = W.k0 + q % wk, l = W.l0 + q / wk;
+        z[W.zbase + (int64_t)l * W.zw + k] = fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xb, sy, sz);
+    }
+}
+
+constexpr int FP_MAX_CHUNK = 16;
+constexpr int FP_LDS_MAX_FLOATS = 16384;  // blocks up to 64 KB are staged in LDS
+
+// Workgroup per (view chunk, block slot): the block's image tile is copied to LDS
+// once and every ray of the chunk's pairs walks it there. Work items are the rays
+// of all pairs of the chunk, flattened.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
+                                                     const int32_t* __restrict__ blocks_sel,
+                                                     const float* __restrict__ x, float* __restrict__ z, int chunk)
+{
+    extern __shared__ float xs[];
+    __shared__ PairWork pw[FP_MAX_CHUNK];
+    __shared__ int s_off[FP_MAX_CHUNK + 1];
+    const int b = blockIdx.y;
+    const int a_begin = blockIdx.x * chunk;
+    if (a_begin >= L.maxv) return;
+    const int nch = min(chunk, L.maxv - a_begin);
+    const PairWork* wb = work + (int64_t)b * L.maxv + a_begin;
+    if (threadIdx.x < nch) pw[threadIdx.x] = wb[threadIdx.x];
+    const BlockInfo B = G.blocks[blocks_sel[b]];
+    const int plane = B.nbx * B.nby;
+    const int nvox_b = plane * B.nbz;
+    for (int i = threadIdx.x; i < nvox_b; i += WG) {
+        const int ix = i % B.nbx, iy = (i / B.nbx) % B.nby, iz = i / plane;
+        xs[i] = x[((int64_t)(B.z0 + iz) * G.ny + (B.y0 + iy)) * (int64_t)G.nx + (B.x0 + ix)];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int q = 0; q < nch; ++q) {
+            s_off[q] = off;
+            off += max(0, pw[q].k1 - pw[q].k0) * max(0, pw[q].l1 - pw[q].l0);
+        }
+        s_off[nch] = off;
+    }
+    __syncthreads();
+    const int total = s_off[nch];
+    for (int item = threadIdx.x; item < total; item += WG) {
+        int q = 0;
+        while (s_off[q + 1] <= item) ++q;
+        const PairWork& W = pw[q];
+        const int wk = W.k1 - W.k0;
+        const int r = item - s_off[q];
+        const int k = W.k0 + r % wk, l = W.l0 + r / wk;
+        z[W.zbase + (int64_t)l * W.zw + k] =
+            fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xs, (int64_t)B.nbx, (int64_t)plane);
     }
 }
 
 // ------------------------------------------------------------ solver: residual rebuild
 
-// r = y - sum_j z^j for every ray of the iteration's views (j ascending).
-__global__ __launch_bounds__(WG) void k_resid(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
-                                              const float* __restrict__ y, const float* __restrict__ z,
-                                              float* __restrict__ r_sel)
+constexpr int RES_WG = 64;
+
+// r = y - sum_j z^j for every ray of one view (j ascending); the view's footprint
+// rectangles are staged in LDS.
+__device__ __forceinline__ float resid_ray(const DevGeom& G, int v, int k, int l, const float* __restrict__ y,
+                                           const float* __restrict__ z, const int4* rc, const long long* zo,
+                                           int per_view, int ray)
 {
+    float acc = y[(int64_t)v * per_view + ray];
+    for (int j = 0; j < G.N; ++j) {
+        const int4 r4 = rc[j];
+        if (k >= r4.x && k < r4.y && l >= r4.z && l < r4.w)
+            acc -= z[zo[j] + (int64_t)(l - r4.z) * (r4.y - r4.x) + (k - r4.x)];
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void stage_rects(const DevGeom& G, int v, int4* rc, long long* zo)
+{
+    const PairInfo* pv = G.pairs + (int64_t)v * G.N;
+    for (int j = threadIdx.x; j < G.N; j += blockDim.x) {
+        rc[j] = *reinterpret_cast<const int4*>(&pv[j].u0);
+        zo[j] = pv[j].zoff;
+    }
+    __syncthreads();
+}
+
+// Dynamic LDS of the residual kernels: N int4 rectangles, then N 64-bit offsets.
+__host__ __device__ constexpr size_t resid_lds_bytes(int N) { return (size_t)N * (sizeof(int4) + sizeof(long long)); }
+
+__global__ __launch_bounds__(RES_WG) void k_resid(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
+                                                  const float* __restrict__ y, const float* __restrict__ z,
+                                                  float* __restrict__ r_sel)
+{
+    extern __shared__ int4 rc[];
+    long long* zo = reinterpret_cast<long long*>(rc + G.N);
     const int a = blockIdx.y;
     if (a >= S_[0]) return;
-    const int per_view = G.nu * G.nv;
-    const int ray = blockIdx.x * WG + threadIdx.x;
-    if (ray >= per_view) return;
     const int v = S_[L.off_views() + a];
+    stage_rects(G, v, rc, zo);
+    const int per_view = G.nu * G.nv;
+    const int ray = blockIdx.x * RES_WG + threadIdx.x;
+    if (ray >= per_view) return;
     const int k = ray % G.nu, l = ray / G.nu;
-    float acc = y[(int64_t)v * per_view + ray];
-    const PairInfo* pv = G.pairs + (int64_t)v * G.N;
-    for (int j = 0; j < G.N; ++j) {
-        const int4 rc = *reinterpret_cast<const int4*>(&pv[j].u0);
-        if (k >= rc.x && k < rc.y && l >= rc.z && l < rc.w)
-            acc -= z[pv[j].zoff + (int64_t)(l - rc.z) * (rc.y - rc.x) + (k - rc.x)];
-    }
-    r_sel[(int64_t)a * per_view + ray] = acc;
+    r_sel[(int64_t)a * per_view + ray] = resid_ray(G, v, k, l, y, z, rc, zo, per_view, ray);
 }
 
 // ------------------------------------------------------------ solver: back projection + step
+
+// 64 voxels per workgroup, each voxel's views interleaved over BP_SPLIT threads and
+// summed in a fixed order through LDS.
+constexpr int BP_VOX = 64;
+constexpr int BP_SPLIT = WG / BP_VOX;
 
 template <int DIM>
 struct Tile;
 template <>
 struct Tile<2> {
-    static constexpr int X = 16, Y = 16, Z = 1;
+    static constexpr int X = 8, Y = 8, Z = 1;
 };
 template <>
 struct Tile<3> {
-    static constexpr int X = 8, Y = 8, Z = 4;
+    static constexpr int X = 4, Y = 4, Z = 4;
 };
 
-// One thread per voxel of a selected block: for each selected row block i,
-// g_hat^i_new = 2 (A_{rows(i,j)}^{J_j})^T r; g += sum_i (g_hat^i_new - g_hat^i_old);
-// g_hat^i = g_hat^i_new; then x += mu g. The voxel's update reads only r, so it
-// is independent of every other voxel (no atomics).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
-                                                const int8_t* __restrict__ draws, const float* __restrict__ r_sel,
+__device__ __forceinline__ bool tile_voxel(const BlockInfo& B, int tile, int vl, int (&li)[3], bool& tile_ok)
+{
+    const int tx_n = (B.nbx + Tile<DIM>::X - 1) / Tile<DIM>::X;
+    const int ty_n = (B.nby + Tile<DIM>::Y - 1) / Tile<DIM>::Y;
+    const int tz_n = (B.nbz + Tile<DIM>::Z - 1) / Tile<DIM>::Z;
+    tile_ok = tile < tx_n * ty_n * tz_n;
+    const int t_x = tile % tx_n, t_y = (tile / tx_n) % ty_n, t_z = tile / (tx_n * ty_n);
+    li[0] = t_x * Tile<DIM>::X + vl % Tile<DIM>::X;
+    li[1] = t_y * Tile<DIM>::Y + (vl / Tile<DIM>::X) % Tile<DIM>::Y;
+    li[2] = t_z * Tile<DIM>::Z + vl / (Tile<DIM>::X * Tile<DIM>::Y);
+    return tile_ok && li[0] < B.nbx && li[1] < B.nby && li[2] < B.nbz;
+}
+
+// For each selected row block i: g_hat^i_new = 2 (A_{rows(i,j)}^{J_j})^T r;
+// g += sum_i (g_hat^i_new - g_hat^i_old); g_hat^i = g_hat^i_new; then x += mu g.
+// A voxel's update reads only r, so voxels are independent (no atomics).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
+                                                SchedLayout L, const float* __restrict__ r_sel,
                                                 float* __restrict__ ghat, float* __restrict__ gsum,
                                                 float* __restrict__ x, float mu, long long n_vox)
 {
+    __shared__ float part[BP_SPLIT][BP_VOX];
     const int b = blockIdx.y;
     const int j = S_[L.off_blocks() + b];
     const BlockInfo B = G.blocks[j];
     int nb[3];
     float h[3], vs[3];
     block_dims(G, B, nb, h, vs);
-    const int tx_n = (nb[0] + Tile<DIM>::X - 1) / Tile<DIM>::X;
-    const int ty_n = (nb[1] + Tile<DIM>::Y - 1) / Tile<DIM>::Y;
-    const int tz_n = (nb[2] + Tile<DIM>::Z - 1) / Tile<DIM>::Z;
-    const int tile = blockIdx.x;
-    if (tile >= tx_n * ty_n * tz_n) return;
-    const int t_x = tile % tx_n, t_y = (tile / tx_n) % ty_n, t_z = tile / (tx_n * ty_n);
-    const int lx = threadIdx.x % Tile<DIM>::X;
-    const int ly = (threadIdx.x / Tile<DIM>::X) % Tile<DIM>::Y;
-    const int lz = threadIdx.x / (Tile<DIM>::X * Tile<DIM>::Y);
-    int li[3] = {t_x * Tile<DIM>::X + lx, t_y * Tile<DIM>::Y + ly, t_z * Tile<DIM>::Z + lz};
-    if (li[0] >= nb[0] || li[1] >= nb[1] || li[2] >= nb[2]) return;
+    const int vl = threadIdx.x % BP_VOX;
+    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
+    int li[3];
+    bool tile_ok;
+    const bool valid = tile_voxel<DIM>(B, blockIdx.x, vl, li, tile_ok);
+    if (!tile_ok) return;  // uniform over the workgroup
     const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
     const int per_view = G.nu * G.nv;
-    const int nvs = S_[0];
-    (void)nvs;
+    const PairWork* wb = work + (int64_t)b * L.maxv;
     float dg = 0.0f;
     for (int ri = 0; ri < L.R; ++ri) {
-        const int i = S_[L.off_rows() + ri];
         const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
         float acc = 0.0f;
-        for (int a = a0; a < a1; ++a) {
-            int sd = -2;
-            if (draws) {
-                sd = draws[a * L.B + b];
-                if (sd == DRAW_SKIP) continue;
+        if (valid) {
+            for (int a = a0 + grp; a < a1; a += BP_SPLIT) {
+                const PairWork W = wb[a];
+                if (W.k1 <= W.k0) continue;
+                acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
+                                          r_sel + (int64_t)a * per_view);
             }
-            const int v = S_[L.off_views() + a];
-            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
-            int k0, k1, l0, l1;
-            pair_range(G, P, sd, k0, k1, l0, l1);
-            if (k1 <= k0 || l1 <= l0) continue;
-            const float2 cs = G.cs[v];
-            acc += bp_voxel_view<DIM>(G, cs.x, cs.y, P, li, h, vs, k0, k1, l0, l1,
-                                      r_sel + (int64_t)a * per_view);
         }
-        const float gnew = 2.0f * acc;
-        float* gp = ghat + (int64_t)i * n_vox + vox;
-        dg += gnew - *gp;
-        *gp = gnew;
+        part[grp][vl] = acc;
+        __syncthreads();
+        if (grp == 0 && valid) {
+            float sum = part[0][vl];
+#pragma unroll
+            for (int q = 1; q < BP_SPLIT; ++q) sum += part[q][vl];
+            const int i = S_[L.off_rows() + ri];
+            const float gnew = 2.0f * sum;
+            float* gp = ghat + (int64_t)i * n_vox + vox;
+            dg += gnew - *gp;
+            *gp = gnew;
+        }
+        __syncthreads();
     }
-    const float gv = gsum[vox] + dg;
-    gsum[vox] = gv;
-    x[vox] = fmaf(mu, gv, x[vox]);
+    if (grp == 0 && valid) {
+        const float gv = gsum[vox] + dg;
+        gsum[vox] = gv;
+        x[vox] = fmaf(mu, gv, x[vox]);
+    }
 }
 
 // ------------------------------------------------------------ standalone projectors
@@ -405,11 +529,15 @@ __global__ __launch_bounds__(WG) void k_fp_full(DevGeom G, const int32_t* __rest
     const int v = views[a];
     const int k = ray % G.nu, l = ray / G.nu;
     const float2 cs = G.cs[v];
+    const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
     float acc = 0.0f;
     for (int j = j0; j < j1; ++j) {
         const PairInfo P = G.pairs[(int64_t)v * G.N + j];
-        if (k >= P.u0 && k < P.u1 && l >= P.v0 && l < P.v1)
-            acc += fp_ray_block<DIM>(G, cs.x, cs.y, P, G.blocks[j], k, l, x);
+        if (k >= P.u0 && k < P.u1 && l >= P.v0 && l < P.v1) {
+            const BlockInfo B = G.blocks[j];
+            const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
+            acc += fp_ray_block<DIM>(G, v, cs.x, cs.y, P, B, k, l, xb, sy, sz);
+        }
     }
     float* dst = y + (int64_t)a * per_view + ray;
     *dst = accumulate ? *dst + acc : acc;
@@ -420,35 +548,40 @@ __global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __rest
                                                 const float* __restrict__ y, float* __restrict__ x, float scale,
                                                 int accumulate)
 {
+    __shared__ float part[BP_SPLIT][BP_VOX];
     const int j = j0 + blockIdx.y;
     const BlockInfo B = G.blocks[j];
     int nb[3];
     float h[3], vs[3];
     block_dims(G, B, nb, h, vs);
-    const int tx_n = (nb[0] + Tile<DIM>::X - 1) / Tile<DIM>::X;
-    const int ty_n = (nb[1] + Tile<DIM>::Y - 1) / Tile<DIM>::Y;
-    const int tz_n = (nb[2] + Tile<DIM>::Z - 1) / Tile<DIM>::Z;
-    const int tile = blockIdx.x;
-    if (tile >= tx_n * ty_n * tz_n) return;
-    const int t_x = tile % tx_n, t_y = (tile / tx_n) % ty_n, t_z = tile / (tx_n * ty_n);
-    const int lx = threadIdx.x % Tile<DIM>::X;
-    const int ly = (threadIdx.x / Tile<DIM>::X) % Tile<DIM>::Y;
-    const int lz = threadIdx.x / (Tile<DIM>::X * Tile<DIM>::Y);
-    int li[3] = {t_x * Tile<DIM>::X + lx, t_y * Tile<DIM>::Y + ly, t_z * Tile<DIM>::Z + lz};
-    if (li[0] >= nb[0] || li[1] >= nb[1] || li[2] >= nb[2]) return;
-    const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
+    const int vl = threadIdx.x % BP_VOX;
+    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
+    int li[3];
+    bool tile_ok;
+    const bool valid = tile_voxel<DIM>(B, blockIdx.x, vl, li, tile_ok);
+    if (!tile_ok) return;
     const int per_view = G.nu * G.nv;
     float acc = 0.0f;
-    for (int a = 0; a < n_sel; ++a) {
-        const int v = views[a];
-        const PairInfo P = G.pairs[(int64_t)v * G.N + j];
-        if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
-        const float2 cs = G.cs[v];
-        acc += bp_voxel_view<DIM>(G, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
-                                  y + (int64_t)a * per_view);
+    if (valid) {
+        for (int a = grp; a < n_sel; a += BP_SPLIT) {
+            const int v = views[a];
+            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+            if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
+            const float2 cs = G.cs[v];
+            acc += bp_voxel_view<DIM>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
+                                      y + (int64_t)a * per_view);
+        }
     }
-    const float val = scale * acc;
-    x[vox] = accumulate ? x[vox] + val : val;
+    part[grp][vl] = acc;
+    __syncthreads();
+    if (grp == 0 && valid) {
+        float sum = part[0][vl];
+#pragma unroll
+        for (int q = 1; q < BP_SPLIT; ++q) sum += part[q][vl];
+        const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
+        const float val = scale * sum;
+        x[vox] = accumulate ? x[vox] + val : val;
+    }
 }
 
 // ------------------------------------------------------------ reductions
@@ -457,20 +590,16 @@ __global__ __launch_bounds__(WG) void k_resid_sumsq(DevGeom G, const float* __re
                                                     const float* __restrict__ z, double* __restrict__ partials)
 {
     __shared__ double lds[4];
+    extern __shared__ int4 rc[];
+    long long* zo = reinterpret_cast<long long*>(rc + G.N);
     const int v = blockIdx.y;
+    stage_rects(G, v, rc, zo);
     const int per_view = G.nu * G.nv;
     const int ray = blockIdx.x * WG + threadIdx.x;
     double val = 0.0;
     if (ray < per_view) {
-        const int k = ray % G.nu, l = ray / G.nu;
-        float acc = y[(int64_t)v * per_view + ray];
-        const PairInfo* pv = G.pairs + (int64_t)v * G.N;
-        for (int j = 0; j < G.N; ++j) {
-            const int4 rc = *reinterpret_cast<const int4*>(&pv[j].u0);
-            if (k >= rc.x && k < rc.y && l >= rc.z && l < rc.w)
-                acc -= z[pv[j].zoff + (int64_t)(l - rc.z) * (rc.y - rc.x) + (k - rc.x)];
-        }
-        val = (double)acc * (double)acc;
+        const float r = resid_ray(G, v, ray % G.nu, ray / G.nu, y, z, rc, zo, per_view, ray);
+        val = (double)r * (double)r;
     }
     const double s = block_sum(val, lds);
     if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
@@ -590,25 +719,45 @@ hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_draws(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
-                        uint64_t seed, const uint32_t* q, int8_t* draws, hipStream_t st)
+hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
+                       uint64_t seed, const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st)
 {
     const int64_t n = (int64_t)n_iters * L.maxv * L.B;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_draws, dim3(grid1(n)), dim3(WG), 0, st, G, sched, L, n_iters, (long long)k0,
-                       (unsigned long long)seed, q, draws);
+    hipLaunchKernelGGL(k_plan, dim3(grid1(n)), dim3(WG), 0, st, G, sched, L, n_iters, (long long)k0,
+                       (unsigned long long)seed, q, draws, work);
     return hipGetLastError();
 }
 
-hipError_t launch_fp_pairs(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+static int max_block_voxels(const DevGeom& G)
+{
+    return ((G.nx + G.bx - 1) / G.bx) * ((G.ny + G.by - 1) / G.by) * ((G.nz + G.bz - 1) / G.bz);
+}
+
+int fp_chunk_views = 3;  // views per workgroup of the LDS forward projector
+
+hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,
                            const float* x, float* z, hipStream_t st)
 {
+    const int maxvox = max_block_voxels(G);
+    if (maxvox <= FP_LDS_MAX_FLOATS) {
+        const int chunk = std::max(1, std::min(FP_MAX_CHUNK, fp_chunk_views));
+        const unsigned gx = (unsigned)((L.maxv + chunk - 1) / chunk);
+        const size_t lds = (size_t)maxvox * sizeof(float);
+        if (G.dim == 3)
+            hipLaunchKernelGGL(k_fp_pairs_lds<3>, dim3(gx, L.B), dim3(WG), lds, st, G, work_it, L, blocks_sel, x, z,
+                               chunk);
+        else
+            hipLaunchKernelGGL(k_fp_pairs_lds<2>, dim3(gx, L.B), dim3(WG), lds, st, G, work_it, L, blocks_sel, x, z,
+                               chunk);
+        return hipGetLastError();
+    }
     const int64_t waves = (int64_t)L.maxv * L.B;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     if (G.dim == 3)
-        hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, sched_it, L, draws_it, x, z);
+        hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, z);
     else
-        hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, sched_it, L, draws_it, x, z);
+        hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, z);
     return hipGetLastError();
 }
 
@@ -616,7 +765,9 @@ hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L
                         float* r_sel, hipStream_t st)
 {
     const int per_view = G.nu * G.nv;
-    hipLaunchKernelGGL(k_resid, dim3(grid1(per_view), L.maxv), dim3(WG), 0, st, G, sched_it, L, y, z, r_sel);
+    const unsigned gx = (unsigned)((per_view + RES_WG - 1) / RES_WG);
+    hipLaunchKernelGGL(k_resid, dim3(gx, L.maxv), dim3(RES_WG), resid_lds_bytes(G.N), st, G, sched_it, L, y, z,
+                       r_sel);
     return hipGetLastError();
 }
 
@@ -630,16 +781,16 @@ static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int 
     return ((mbx + Tile<2>::X - 1) / Tile<2>::X) * ((mby + Tile<2>::Y - 1) / Tile<2>::Y);
 }
 
-hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const int8_t* draws_it,
+hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
                           const float* r_sel, float* ghat, float* gsum, float* x, float mu, int64_t n_vox,
                           hipStream_t st)
 {
     const int tiles = max_tiles(G, nullptr, G.dim);
     if (G.dim == 3)
-        hipLaunchKernelGGL(k_bp_step<3>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, L, draws_it, r_sel, ghat,
+        hipLaunchKernelGGL(k_bp_step<3>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, work_it, L, r_sel, ghat,
                            gsum, x, mu, (long long)n_vox);
     else
-        hipLaunchKernelGGL(k_bp_step<2>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, L, draws_it, r_sel, ghat,
+        hipLaunchKernelGGL(k_bp_step<2>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, work_it, L, r_sel, ghat,
                            gsum, x, mu, (long long)n_vox);
     return hipGetLastError();
 }
@@ -678,7 +829,7 @@ hipError_t launch_resid_sumsq(const DevGeom& G, const float* y, const float* z, 
 {
     const int per_view = G.nu * G.nv;
     const unsigned gx = grid1(per_view);
-    hipLaunchKernelGGL(k_resid_sumsq, dim3(gx, G.n_views), dim3(WG), 0, st, G, y, z, partials);
+    hipLaunchKernelGGL(k_resid_sumsq, dim3(gx, G.n_views), dim3(WG), resid_lds_bytes(G.N), st, G, y, z, partials);
     *n_partials = (int)(gx * G.n_views);
     return hipGetLastError();
 }
