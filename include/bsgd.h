@@ -157,7 +157,8 @@ bsgd_status bsgd_back_project(const bsgd_geometry* geom, const float* y, float* 
  * max_effective_epochs, tol: bsgd_solve stops after max_effective_epochs effective epochs
  *   (one epoch = round(1/(alpha gamma)) iterations), or earlier when tol > 0 and the
  *   relative normal-equation residual ||A^T(y - A x)|| / ||A^T y|| <= tol, checked
- *   every check_every epochs (0 = every epoch). */
+ *   every check_every epochs (0 = every epoch).
+ * flags: BSGD_FLAG_EAGER (below). */
 typedef struct {
     int32_t rows_per_iter;
     int32_t blocks_per_iter;
@@ -170,8 +171,13 @@ typedef struct {
     int32_t max_effective_epochs;
     double tol;
     int32_t check_every;
-    int32_t reserved;
+    int32_t flags;                /* BSGD_FLAG_* */
 } bsgd_options;
+
+/* Launch every kernel directly instead of replaying a captured HIP graph of one
+ * effective epoch (graphs are used when a bsgd_step call covers whole epochs from an
+ * epoch boundary and per-kernel profiling is off). Results are identical. */
+#define BSGD_FLAG_EAGER 1
 
 /* Create a solver for y (device [n_views][nv][nu], must stay valid and unchanged while
  * the solver lives) and x (device [nz][ny][nx], the initial image, updated in place by

@@ -60,7 +60,7 @@ class Options(ctypes.Structure):
         ("rows_per_iter", ctypes.c_int32), ("blocks_per_iter", ctypes.c_int32), ("node_count", ctypes.c_int32),
         ("tv_inner_iters", ctypes.c_int32), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("tv_lambda", ctypes.c_double), ("tv_every", ctypes.c_int32), ("max_effective_epochs", ctypes.c_int32),
-        ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
     ]
 
 
@@ -241,12 +241,17 @@ class Geometry:
         return out
 
 
+FLAG_EAGER = 1
+
+
 def make_options(rows_per_iter=0, blocks_per_iter=0, node_count=0, mu=0.0, seed=0, tv_lambda=0.0,
-                 tv_inner_iters=20, tv_every=0, max_effective_epochs=0, tol=0.0, check_every=0) -> Options:
+                 tv_inner_iters=20, tv_every=0, max_effective_epochs=0, tol=0.0, check_every=0,
+                 eager=False) -> Options:
     o = Options()
     o.rows_per_iter, o.blocks_per_iter, o.node_count = rows_per_iter, blocks_per_iter, node_count
     o.tv_inner_iters, o.mu, o.seed, o.tv_lambda, o.tv_every = tv_inner_iters, mu, seed, tv_lambda, tv_every
-    o.max_effective_epochs, o.tol, o.check_every, o.reserved = max_effective_epochs, tol, check_every, 0
+    o.max_effective_epochs, o.tol, o.check_every = max_effective_epochs, tol, check_every
+    o.flags = FLAG_EAGER if eager else 0
     return o
 
 

@@ -657,6 +657,12 @@ struct bsgd_solver {
     DevBuf z, ghat, gsum, r_sel, sched, draws, work, partials, norm_out, tv_p, tv_a, tv_b;
     int sched_cap = 0;
     Staging stage;
+    // one captured epoch (T iterations) replayed per epoch
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    DevBuf g_sched, g_work, g_draws;
     double* norm_host = nullptr;
     // last call's schedule (host) for export
     std::vector<int32_t> last_sched;
@@ -677,6 +683,9 @@ struct bsgd_solver {
         }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         if (norm_host) (void)hipHostFree(norm_host);
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 
     hipError_t event(hipEvent_t* e)
@@ -758,7 +767,8 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     s->L.R = R;
     s->L.B = B;
     s->L.maxv = s->maxv;
-    s->L.stride = 2 + 2 * R + B + s->maxv;
+    s->L.stride = SchedLayout::stride_for(R, B, s->maxv);
+    s->graphs = (o->flags & BSGD_FLAG_EAGER) == 0;
     const int64_t per_view = (int64_t)g->d.nu * g->d.nv;
     auto cleanup = [&](bsgd_status e) {
         delete s;
@@ -832,6 +842,8 @@ static void fill_schedule(bsgd_solver* s, int n, int32_t* out)
         }
         rec[L.off_gstart() + L.R] = nv;
         rec[0] = nv;
+        rec[L.off_k()] = (int32_t)(uint32_t)((uint64_t)k & 0xffffffffu);
+        rec[L.off_k() + 1] = (int32_t)(uint32_t)((uint64_t)k >> 32);
     }
 }
 
@@ -846,9 +858,75 @@ static bsgd_status resid_norm(bsgd_solver* s, double* out)
     return BSGD_OK;
 }
 
-static bsgd_status step_impl(bsgd_solver* s, int n_iters)
+// Enqueue n_iters iterations reading schedule records `dsched` and writing work
+// records / draws into `dwork` / `ddraws`; k_first is the counter of the first one
+// (used only to place the TV steps).
+static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32_t* dsched, PairWork* dwork,
+                                     int8_t* ddraws, int n_iters, int64_t k_first)
 {
     const bsgd_geometry* g = s->g;
+    hipError_t e = timed(s, KID_DRAW, [&] {
+        return launch_plan(g->dg, dsched, s->L, n_iters, s->o.seed, s->im ? g->d_q.as<uint32_t>() : nullptr, ddraws,
+                           dwork, st);
+    });
+    if (e != hipSuccess) return e;
+    const int64_t per_it_work = (int64_t)s->maxv * s->B;
+    for (int it = 0; it < n_iters; ++it) {
+        const int32_t* rec = dsched + (size_t)it * s->L.stride;
+        const PairWork* wk = dwork + it * per_it_work;
+        e = timed(s, KID_FP, [&] {
+            return launch_fp_pairs(g->dg, wk, s->L, rec + s->L.off_blocks(), s->x, s->z.as<float>(), st);
+        });
+        if (e != hipSuccess) return e;
+        e = timed(s, KID_RESID,
+                  [&] { return launch_resid(g->dg, rec, s->L, s->y, s->z.as<float>(), s->r_sel.as<float>(), st); });
+        if (e != hipSuccess) return e;
+        e = timed(s, KID_BP, [&] {
+            return launch_bp_step(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->ghat.as<float>(), s->gsum.as<float>(),
+                                  s->x, (float)s->o.mu, g->n_vox, st);
+        });
+        if (e != hipSuccess) return e;
+        if (s->o.tv_lambda > 0 && (k_first + it + 1) % s->tv_every == 0) {
+            const float w = (float)(s->o.mu * s->o.tv_lambda);
+            e = timed(s, KID_TV, [&] {
+                return launch_tv_prox(g->dg, s->x, w, s->o.tv_inner_iters, s->tv_p.as<float>(), s->tv_a.as<float>(),
+                                      s->tv_b.as<float>(), st);
+            });
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// Capture one epoch (T iterations starting at a multiple of T) on a private stream.
+static bsgd_status build_graph(bsgd_solver* s)
+{
+    const int T = s->T;
+    HIP_TRY(s->g_sched.alloc((size_t)T * s->L.stride * sizeof(int32_t)));
+    HIP_TRY(s->g_work.alloc((size_t)T * s->maxv * s->B * sizeof(PairWork)));
+    if (s->im) HIP_TRY(s->g_draws.alloc((size_t)T * s->maxv * s->B));
+    HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_iterations(s, s->cap_stream, s->g_sched.as<int32_t>(), s->g_work.as<PairWork>(),
+                                      s->im ? s->g_draws.as<int8_t>() : nullptr, T, 0);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->cap_stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(BSGD_E_DEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    s->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&s->graph_exec, graph, nullptr, nullptr, 0));
+    return BSGD_OK;
+}
+
+static bsgd_status step_impl(bsgd_solver* s, int n_iters)
+{
+    const int T = s->T;
+    const bool tv_aligned = !(s->o.tv_lambda > 0) || (T % s->tv_every == 0);
+    const bool use_graph =
+        s->graphs && !s->prof && n_iters % T == 0 && s->k % T == 0 && tv_aligned && n_iters > 0;
     bsgd_status stt = ensure_sched(s, n_iters);
     if (stt != BSGD_OK) return stt;
     const size_t sched_bytes = (size_t)n_iters * s->L.stride * sizeof(int32_t);
@@ -857,36 +935,30 @@ static bsgd_status step_impl(bsgd_solver* s, int n_iters)
     fill_schedule(s, n_iters, host);
     s->last_sched.assign(host, host + (size_t)n_iters * s->L.stride);
     s->last_n = n_iters;
-    HIP_TRY(s->stage.upload(s->sched.p, sched_bytes, s->st));
-    const int32_t* dsched = s->sched.as<int32_t>();
-    int8_t* ddraws = s->im ? s->draws.as<int8_t>() : nullptr;
-    PairWork* dwork = s->work.as<PairWork>();
-    HIP_TRY(timed(s, KID_DRAW, [&] {
-        return launch_plan(g->dg, dsched, s->L, n_iters, s->k, s->o.seed, s->im ? g->d_q.as<uint32_t>() : nullptr,
-                           ddraws, dwork, s->st);
-    }));
-    const int64_t per_it_work = (int64_t)s->maxv * s->B;
-    for (int it = 0; it < n_iters; ++it) {
-        const int32_t* rec = dsched + (size_t)it * s->L.stride;
-        const PairWork* wk = dwork + it * per_it_work;
-        HIP_TRY(timed(s, KID_FP, [&] {
-            return launch_fp_pairs(g->dg, wk, s->L, rec + s->L.off_blocks(), s->x, s->z.as<float>(), s->st);
-        }));
-        HIP_TRY(timed(s, KID_RESID,
-                      [&] { return launch_resid(g->dg, rec, s->L, s->y, s->z.as<float>(), s->r_sel.as<float>(), s->st); }));
-        HIP_TRY(timed(s, KID_BP, [&] {
-            return launch_bp_step(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->ghat.as<float>(), s->gsum.as<float>(),
-                                  s->x, (float)s->o.mu, g->n_vox, s->st);
-        }));
-        s->k += 1;
-        if (s->o.tv_lambda > 0 && s->k % s->tv_every == 0) {
-            const float w = (float)(s->o.mu * s->o.tv_lambda);
-            HIP_TRY(timed(s, KID_TV, [&] {
-                return launch_tv_prox(g->dg, s->x, w, s->o.tv_inner_iters, s->tv_p.as<float>(), s->tv_a.as<float>(),
-                                      s->tv_b.as<float>(), s->st);
-            }));
-        }
+    if (!use_graph) {
+        HIP_TRY(s->stage.upload(s->sched.p, sched_bytes, s->st));
+        HIP_TRY(enqueue_iterations(s, s->st, s->sched.as<int32_t>(), s->work.as<PairWork>(),
+                                   s->im ? s->draws.as<int8_t>() : nullptr, n_iters, s->k));
+        s->k += n_iters;
+        return BSGD_OK;
     }
+    if (!s->graph_exec) {
+        stt = build_graph(s);
+        if (stt != BSGD_OK) return stt;
+    }
+    const size_t epoch_sched = (size_t)T * s->L.stride * sizeof(int32_t);
+    const size_t epoch_draws = (size_t)T * s->maxv * s->B;
+    for (int e = 0; e < n_iters / T; ++e) {
+        HIP_TRY(hipMemcpyAsync(s->g_sched.p, reinterpret_cast<char*>(s->stage.host) + e * epoch_sched, epoch_sched,
+                               hipMemcpyHostToDevice, s->st));
+        HIP_TRY(hipGraphLaunch(s->graph_exec, s->st));
+        if (s->im)
+            HIP_TRY(hipMemcpyAsync(s->draws.as<int8_t>() + e * epoch_draws, s->g_draws.p, epoch_draws,
+                                   hipMemcpyDeviceToDevice, s->st));
+    }
+    HIP_TRY(hipEventRecord(s->stage.done, s->st));
+    s->stage.pending = true;
+    s->k += n_iters;
     return BSGD_OK;
 }
 

@@ -151,23 +151,15 @@ __device__ __forceinline__ void walk_axis_init(const Ray& R, int a, int n, float
     idx = i;
 }
 
-// Cross the next plane of one axis: returns false when the walk leaves the block.
-__device__ __forceinline__ bool walk_axis_step(const Ray& R, int a, int n, float h, float vs, int& idx, int step,
-                                               float& tn)
-{
-    const int ni = idx + step;
-    if (step == 0 || ni < 0 || ni >= n) return false;
-    idx = ni;
-    tn = plane_t(step > 0 ? ni + 1 : ni, vs, h, R.p[a], R.inv[a]);
-    return true;
-}
-
-// Ray-driven Siddon walk through one block. visit(ix, iy, iz, dt) is called for
-// every voxel the ray crosses, in order, with the parameter length dt >= 0
-// (dt = 0 at exact corner crossings; ties cross the lowest axis first).
+// Ray-driven Siddon walk through one block. visit(off, dt) is called for every
+// voxel the ray crosses, in order, with the voxel's offset off = iz sz + iy sy + ix
+// in the block's storage and the parameter length dt >= 0 (dt = 0 at exact corner
+// crossings; ties cross the lowest axis first). The step is branch free: the
+// crossed axis' operands are selected and its next plane parameter is computed
+// with the same plane_t formula the back projector's slab test uses.
 template <int DIM, class Visit>
 __device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], const float (&h)[3],
-                                           const float (&vs)[3], Visit&& visit)
+                                           const float (&vs)[3], int sy, int sz, Visit&& visit)
 {
     float tlo = -INFINITY, thi = INFINITY;
 #pragma unroll
@@ -185,27 +177,59 @@ __device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], con
     }
     if (!(tlo < thi)) return;
 
-    int ix, iy, iz = 0, sx, sy, sz = 0;
+    int ix, iy, iz = 0, sx, sy_, sz_ = 0;
     float tx, ty, tz = INFINITY;
     walk_axis_init(R, 0, nb[0], h[0], vs[0], tlo, ix, sx, tx);
-    walk_axis_init(R, 1, nb[1], h[1], vs[1], tlo, iy, sy, ty);
-    if (DIM == 3) walk_axis_init(R, 2, nb[2], h[2], vs[2], tlo, iz, sz, tz);
+    walk_axis_init(R, 1, nb[1], h[1], vs[1], tlo, iy, sy_, ty);
+    if (DIM == 3) walk_axis_init(R, 2, nb[2], h[2], vs[2], tlo, iz, sz_, tz);
+    // next plane index per axis (the exit plane of the current voxel)
+    int px = ix + (sx > 0), py = iy + (sy_ > 0), pz = iz + (sz_ > 0);
+    int off = iz * sz + iy * sy + ix;
 
     float t = tlo;
     const int max_steps = nb[0] + nb[1] + (DIM == 3 ? nb[2] : 0) + 2;
     for (int it = 0; it < max_steps; ++it) {
-        if (tx <= ty && (DIM == 2 || tx <= tz)) {
-            visit(ix, iy, iz, tx - t);
-            t = tx;
-            if (!walk_axis_step(R, 0, nb[0], h[0], vs[0], ix, sx, tx)) break;
-        } else if (DIM == 2 || ty <= tz) {
-            visit(ix, iy, iz, ty - t);
-            t = ty;
-            if (!walk_axis_step(R, 1, nb[1], h[1], vs[1], iy, sy, ty)) break;
+        const bool cx = (tx <= ty) && (DIM == 2 || tx <= tz);
+        const bool cy = !cx && (DIM == 2 || ty <= tz);
+        const float tm = cx ? tx : (cy ? ty : tz);
+        visit(off, tm - t);
+        t = tm;
+        // advance the crossed axis
+        const int st = cx ? sx : (cy ? sy_ : sz_);
+            if (DIM == 2) {
+            ix += cx ? sx : 0;
+            iy += cx ? 0 : sy_;
+            px += cx ? sx : 0;
+            py += cx ? 0 : sy_;
+            off += cx ? sx : sy_ * sy;
+            const bool out = cx ? (ix < 0 || ix >= nb[0]) : (iy < 0 || iy >= nb[1]);
+            if (st == 0 || out) break;
+            const int kk = cx ? px : py;
+            const float pv = cx ? vs[0] : vs[1], ph = cx ? h[0] : h[1];
+            const float pp = cx ? R.p[0] : R.p[1], pi = cx ? R.inv[0] : R.inv[1];
+            const float tnew = plane_t(kk, pv, ph, pp, pi);
+            tx = cx ? tnew : tx;
+            ty = cx ? ty : tnew;
         } else {
-            visit(ix, iy, iz, tz - t);
-            t = tz;
-            if (!walk_axis_step(R, 2, nb[2], h[2], vs[2], iz, sz, tz)) break;
+            const bool cz = !cx && !cy;
+            ix += cx ? sx : 0;
+            iy += cy ? sy_ : 0;
+            iz += cz ? sz_ : 0;
+            px += cx ? sx : 0;
+            py += cy ? sy_ : 0;
+            pz += cz ? sz_ : 0;
+            off += cx ? sx : (cy ? sy_ * sy : sz_ * sz);
+            const bool out = cx ? (ix < 0 || ix >= nb[0]) : (cy ? (iy < 0 || iy >= nb[1]) : (iz < 0 || iz >= nb[2]));
+            if (st == 0 || out) break;
+            const int kk = cx ? px : (cy ? py : pz);
+            const float pv = cx ? vs[0] : (cy ? vs[1] : vs[2]);
+            const float ph = cx ? h[0] : (cy ? h[1] : h[2]);
+            const float pp = cx ? R.p[0] : (cy ? R.p[1] : R.p[2]);
+            const float pi = cx ? R.inv[0] : (cy ? R.inv[1] : R.inv[2]);
+            const float tnew = plane_t(kk, pv, ph, pp, pi);
+            tx = cx ? tnew : tx;
+            ty = cy ? tnew : ty;
+            tz = cz ? tnew : tz;
         }
     }
 }

@@ -14,12 +14,15 @@ namespace bsgd {
 //   [1+R, 2+2R)            offsets of each selected row block's views into the view list
 //   [2+2R, 2+2R+B)         selected column blocks (ascending)
 //   [2+2R+B, +maxv)        view list (row blocks in order, views ascending in each)
+//   [2+2R+B+maxv, +2)      iteration counter k (low, high 32 bits)
 struct SchedLayout {
     int32_t R, B, maxv, stride;
     __host__ __device__ int off_rows() const { return 1; }
     __host__ __device__ int off_gstart() const { return 1 + R; }
     __host__ __device__ int off_blocks() const { return 2 + 2 * R; }
     __host__ __device__ int off_views() const { return 2 + 2 * R + B; }
+    __host__ __device__ int off_k() const { return 2 + 2 * R + B + maxv; }
+    static __host__ __device__ int stride_for(int R, int B, int maxv) { return 4 + 2 * R + B + maxv; }
 };
 
 // Draws: int8 per (iteration, view slot, block slot); -1 = skip view, >= 0 sub-detector.
@@ -34,9 +37,10 @@ extern int fp_chunk_views;
 hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStream_t st);
 
 // Draws (when q != NULL) and per-(block slot, view slot) work records for n_iters
-// iterations: draws [n][maxv][B] (may be NULL), work [n][B][maxv].
-hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
-                       uint64_t seed, const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st);
+// iterations: draws [n][maxv][B] (may be NULL), work [n][B][maxv]. The iteration
+// counter of each record is read from the schedule.
+hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, uint64_t seed,
+                       const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st);
 
 // blocks_sel: the iteration's selected blocks (device, inside its schedule record).
 hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,

@@ -96,9 +96,7 @@ __device__ __forceinline__ float fp_ray_block(const DevGeom& G, int view, float 
     float h[3], vs[3];
     block_dims(G, B, nb, h, vs);
     float acc = 0.0f;
-    walk_block<DIM>(R, nb, h, vs, [&](int ix, int iy, int iz, float dt) {
-        acc = fmaf(dt, xb[iz * sz + iy * sy + ix], acc);
-    });
+    walk_block<DIM>(R, nb, h, vs, (int)sy, (int)sz, [&](int off, float dt) { acc = fmaf(dt, xb[off], acc); });
     return acc * R.len;
 }
 
@@ -204,7 +202,7 @@ __global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict
             make_ray<DIM>(G, v, cs.x, cs.y, P, k, l, R);
             float s2 = 0.0f;
             int ns = 0;
-            walk_block<DIM>(R, nb, h, vs, [&](int, int, int, float dt) {
+            walk_block<DIM>(R, nb, h, vs, 0, 0, [&](int, float dt) {
                 s2 = fmaf(dt, dt, s2);
                 ns += dt > 0.0f;
             });
@@ -229,7 +227,7 @@ __global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict
 // write the pair's work record. Draws are stored [it][view slot][block slot] for
 // export; records [it][block slot][view slot] so that a block's views are contiguous.
 __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restrict__ sched, SchedLayout L,
-                                             int n_iters, long long k0, unsigned long long seed,
+                                             int n_iters, unsigned long long seed,
                                              const uint32_t* __restrict__ q, int8_t* __restrict__ draws,
                                              PairWork* __restrict__ work)
 {
@@ -260,7 +258,8 @@ __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restric
             for (int t = 0; t < G.S; ++t) total += q[((int64_t)v * G.S + t) * G.N + j];
             sd = DRAW_SKIP;
             if (total > 0) {
-                const uint64_t hsh = hash3(seed, 4ull, (uint64_t)(k0 + it), (uint64_t)v, (uint64_t)j);
+                const uint64_t kk = (uint64_t)(uint32_t)S_[L.off_k()] | ((uint64_t)(uint32_t)S_[L.off_k() + 1] << 32);
+                const uint64_t hsh = hash3(seed, 4ull, kk, (uint64_t)v, (uint64_t)j);
                 const uint64_t u = __umul64hi(hsh, total);
                 unsigned long long accq = 0;
                 sd = G.S - 1;
@@ -320,9 +319,17 @@ __global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __re
     const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
     const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
     const int n = wk * wl;
+    int l = W.l0 + lane / wk;
+    int k = W.k0 + lane % wk;
+    const int dl = 64 / wk, dk = 64 % wk;
     for (int q = lane; q < n; q += 64) {
-        const int k = W.k0 + q % wk, l = W.l0 + q / wk;
         z[W.zbase + (int64_t)l * W.zw + k] = fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xb, sy, sz);
+        k += dk;
+        l += dl;
+        if (k >= W.k1) {
+            k -= wk;
+            ++l;
+        }
     }
 }
 
@@ -368,9 +375,16 @@ __global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* 
         int q = 0;
         while (s_off[q + 1] <= item) ++q;
         const PairWork& W = pw[q];
-        const int wk = W.k1 - W.k0;
         const int r = item - s_off[q];
-        const int k = W.k0 + r % wk, l = W.l0 + r / wk;
+        int k, l;
+        if (DIM == 2) {
+            k = W.k0 + r;
+            l = W.l0;
+        } else {
+            const int wk = W.k1 - W.k0;
+            l = W.l0 + r / wk;
+            k = W.k0 + (r - (l - W.l0) * wk);
+        }
         z[W.zbase + (int64_t)l * W.zw + k] =
             fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xs, (int64_t)B.nbx, (int64_t)plane);
     }
@@ -381,16 +395,38 @@ __global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* 
 constexpr int RES_WG = 64;
 
 // r = y - sum_j z^j for every ray of one view (j ascending); the view's footprint
-// rectangles are staged in LDS.
+// rectangles are staged in LDS. The z offsets of the blocks containing the ray are
+// first collected (per thread, in LDS) and then loaded back to back, so the
+// gathers overlap instead of waiting one by one; subtraction order stays ascending j.
+constexpr int RES_BATCH = 16;
+
 __device__ __forceinline__ float resid_ray(const DevGeom& G, int v, int k, int l, const float* __restrict__ y,
                                            const float* __restrict__ z, const int4* rc, const long long* zo,
-                                           int per_view, int ray)
+                                           long long* cand, int per_view, int ray)
 {
     float acc = y[(int64_t)v * per_view + ray];
+    int cnt = 0;
     for (int j = 0; j < G.N; ++j) {
         const int4 r4 = rc[j];
-        if (k >= r4.x && k < r4.y && l >= r4.z && l < r4.w)
-            acc -= z[zo[j] + (int64_t)(l - r4.z) * (r4.y - r4.x) + (k - r4.x)];
+        if (k >= r4.x && k < r4.y && l >= r4.z && l < r4.w) {
+            cand[cnt++] = zo[j] + (int64_t)(l - r4.z) * (r4.y - r4.x) + (k - r4.x);
+            if (cnt == RES_BATCH) {
+                float vals[RES_BATCH];
+#pragma unroll
+                for (int c = 0; c < RES_BATCH; ++c) vals[c] = z[cand[c]];
+#pragma unroll
+                for (int c = 0; c < RES_BATCH; ++c) acc -= vals[c];
+                cnt = 0;
+            }
+        }
+    }
+    for (int c0 = 0; c0 < cnt; c0 += 4) {
+        float vals[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) vals[c] = (c0 + c < cnt) ? z[cand[c0 + c]] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c0 + c < cnt) acc -= vals[c];
     }
     return acc;
 }
@@ -406,7 +442,10 @@ __device__ __forceinline__ void stage_rects(const DevGeom& G, int v, int4* rc, l
 }
 
 // Dynamic LDS of the residual kernels: N int4 rectangles, then N 64-bit offsets.
-__host__ __device__ constexpr size_t resid_lds_bytes(int N) { return (size_t)N * (sizeof(int4) + sizeof(long long)); }
+__host__ __device__ constexpr size_t resid_lds_bytes(int N, int threads)
+{
+    return (size_t)N * (sizeof(int4) + sizeof(long long)) + (size_t)threads * RES_BATCH * sizeof(long long);
+}
 
 __global__ __launch_bounds__(RES_WG) void k_resid(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
                                                   const float* __restrict__ y, const float* __restrict__ z,
@@ -414,6 +453,7 @@ __global__ __launch_bounds__(RES_WG) void k_resid(DevGeom G, const int32_t* __re
 {
     extern __shared__ int4 rc[];
     long long* zo = reinterpret_cast<long long*>(rc + G.N);
+    long long* cand = zo + G.N + threadIdx.x * RES_BATCH;
     const int a = blockIdx.y;
     if (a >= S_[0]) return;
     const int v = S_[L.off_views() + a];
@@ -422,7 +462,7 @@ __global__ __launch_bounds__(RES_WG) void k_resid(DevGeom G, const int32_t* __re
     const int ray = blockIdx.x * RES_WG + threadIdx.x;
     if (ray >= per_view) return;
     const int k = ray % G.nu, l = ray / G.nu;
-    r_sel[(int64_t)a * per_view + ray] = resid_ray(G, v, k, l, y, z, rc, zo, per_view, ray);
+    r_sel[(int64_t)a * per_view + ray] = resid_ray(G, v, k, l, y, z, rc, zo, cand, per_view, ray);
 }
 
 // ------------------------------------------------------------ solver: back projection + step
@@ -592,13 +632,14 @@ __global__ __launch_bounds__(WG) void k_resid_sumsq(DevGeom G, const float* __re
     __shared__ double lds[4];
     extern __shared__ int4 rc[];
     long long* zo = reinterpret_cast<long long*>(rc + G.N);
+    long long* cand = zo + G.N + threadIdx.x * RES_BATCH;
     const int v = blockIdx.y;
     stage_rects(G, v, rc, zo);
     const int per_view = G.nu * G.nv;
     const int ray = blockIdx.x * WG + threadIdx.x;
     double val = 0.0;
     if (ray < per_view) {
-        const float r = resid_ray(G, v, ray % G.nu, ray / G.nu, y, z, rc, zo, per_view, ray);
+        const float r = resid_ray(G, v, ray % G.nu, ray / G.nu, y, z, rc, zo, cand, per_view, ray);
         val = (double)r * (double)r;
     }
     const double s = block_sum(val, lds);
@@ -719,13 +760,13 @@ hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, int64_t k0,
-                       uint64_t seed, const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st)
+hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, uint64_t seed,
+                       const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st)
 {
     const int64_t n = (int64_t)n_iters * L.maxv * L.B;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plan, dim3(grid1(n)), dim3(WG), 0, st, G, sched, L, n_iters, (long long)k0,
-                       (unsigned long long)seed, q, draws, work);
+    hipLaunchKernelGGL(k_plan, dim3(grid1(n)), dim3(WG), 0, st, G, sched, L, n_iters, (unsigned long long)seed, q,
+                       draws, work);
     return hipGetLastError();
 }
 
@@ -766,7 +807,7 @@ hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L
 {
     const int per_view = G.nu * G.nv;
     const unsigned gx = (unsigned)((per_view + RES_WG - 1) / RES_WG);
-    hipLaunchKernelGGL(k_resid, dim3(gx, L.maxv), dim3(RES_WG), resid_lds_bytes(G.N), st, G, sched_it, L, y, z,
+    hipLaunchKernelGGL(k_resid, dim3(gx, L.maxv), dim3(RES_WG), resid_lds_bytes(G.N, RES_WG), st, G, sched_it, L, y, z,
                        r_sel);
     return hipGetLastError();
 }
@@ -829,7 +870,7 @@ hipError_t launch_resid_sumsq(const DevGeom& G, const float* y, const float* z, 
 {
     const int per_view = G.nu * G.nv;
     const unsigned gx = grid1(per_view);
-    hipLaunchKernelGGL(k_resid_sumsq, dim3(gx, G.n_views), dim3(WG), resid_lds_bytes(G.N), st, G, y, z, partials);
+    hipLaunchKernelGGL(k_resid_sumsq, dim3(gx, G.n_views), dim3(WG), resid_lds_bytes(G.N, WG), st, G, y, z, partials);
     *n_partials = (int)(gx * G.n_views);
     return hipGetLastError();
 }

@@ -170,3 +170,41 @@ def test_solve_matches_stepping():
     x3n = x3.double().cpu().numpy()
     ratio = np.linalg.norm(A.T @ (y64 - A @ x3n)) / np.linalg.norm(A.T @ y64)
     assert it3 < 200 * s.epoch_iters and ratio <= 0.05 * 1.001
+
+
+@pytest.mark.parametrize("name,im,tv", [("fan", "colnorm", 0.0), ("cone", None, 0.5), ("parallel", None, 0.0)])
+def test_graph_replay_matches_eager(name, im, tv):
+    """Whole-epoch calls replay a captured HIP graph; every replay must equal the eager
+    launches bit for bit, with other device work and synchronisations in between."""
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver
+    dev = require_gpu()
+    g = SMALL[name].with_(im_mode=im or "none")
+    log(f"graph replay {name} im={im} tv={tv}")
+    A, x_true, y64, y32 = _data(SMALL[name])
+    mu = _mu(A, 0.3)
+    p = oracle_problem(SMALL[name])
+    geom = Geometry(g, im_table=im_table(p, im) if im else None)
+    yd = torch.tensor(y32, device=dev)
+    xg = torch.zeros(A.shape[1], device=dev)
+    xe = torch.zeros(A.shape[1], device=dev)
+    sg = Solver(geom, yd, xg, rows_per_iter=1, blocks_per_iter=2, mu=mu, seed=21, tv_lambda=tv)
+    se = Solver(geom, yd, xe, rows_per_iter=1, blocks_per_iter=2, mu=mu, seed=21, tv_lambda=tv, eager=True)
+    T = sg.epoch_iters
+    for rep in range(4):
+        sg.step(T if rep % 2 == 0 else 2 * T)
+        se.step(T if rep % 2 == 0 else 2 * T)
+        junk = geom.forward_project(xg)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), rep
+        assert float(junk.sum()) == float(junk.sum())
+    rg, bg, dg = sg.last_schedule()
+    re_, be, de = se.last_schedule()
+    assert np.array_equal(rg, re_) and np.array_equal(bg, be) and np.array_equal(dg, de)
+    # a call that does not start at an epoch boundary runs eagerly and stays in step
+    sg.step(3)
+    se.step(3)
+    sg.step(T)
+    se.step(T)
+    torch.cuda.synchronize()
+    assert torch.equal(xg, xe)
