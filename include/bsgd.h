@@ -190,6 +190,15 @@ bsgd_status bsgd_solver_create(const bsgd_geometry* geom, const float* y, float*
  * Algorithm 1); a non-finite value returns BSGD_E_DIVERGED. */
 bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_norm_out);
 
+/* Run n_iters iterations of every solver in solvers[0..n) with one launch per phase
+ * (forward projection, residual rebuild, back projection + step) covering all of
+ * them: the batched, continuous-serving form of bsgd_step. Each solve's arithmetic is
+ * the same as in bsgd_step (same kernels, same per-workgroup decomposition), so its
+ * iterates are bitwise identical alone and in any batch. All solvers must have been
+ * created on `stream`, share the dimension (2D or 3D) and be distinct. Asynchronous.
+ * Errors mark every solver of the batch as failed. */
+bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, int32_t n_iters, void* stream);
+
 /* Iterations done so far, and alpha M, gamma N, iterations per effective epoch. */
 bsgd_status bsgd_solver_counts(const bsgd_solver* s, int64_t* iters_done, int32_t* rows_per_iter,
                                int32_t* blocks_per_iter, int32_t* epoch_iters);

@@ -68,7 +68,7 @@ EXPORTED = (
     "bsgd_geometry_create", "bsgd_geometry_destroy", "bsgd_geometry_get_info", "bsgd_geometry_table",
     "bsgd_forward_project", "bsgd_back_project", "bsgd_solver_create", "bsgd_step", "bsgd_solver_counts",
     "bsgd_solver_last_schedule", "bsgd_solver_state", "bsgd_solver_set_profiling", "bsgd_solver_kernel_times",
-    "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error",
+    "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error", "bsgd_step_batch",
 )
 
 _lib = None
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "bsgd_solve": (i32, [P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(i32),
                              ctypes.POINTER(ctypes.c_double)]),
         "bsgd_last_error": (ctypes.c_char_p, []),
+        "bsgd_step_batch": (i32, [ctypes.POINTER(P), i32, i32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -326,6 +327,12 @@ class Solver:
         _check(load_library().bsgd_solver_kernel_times(self._h, ms.ctypes.data_as(ctypes.c_void_p),
                                                        n.ctypes.data_as(ctypes.c_void_p)))
         return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(KERNELS)}
+
+
+def step_batch(solvers, n_iters: int, stream=None):
+    """n_iters iterations of every solver with shared launches (bsgd_step_batch)."""
+    arr = (ctypes.c_void_p * len(solvers))(*[s._h.value for s in solvers])
+    _check(load_library().bsgd_step_batch(arr, len(solvers), int(n_iters), _stream_ptr(stream)))
 
 
 def solve(geom: Geometry, y, x, stream=None, **opts):

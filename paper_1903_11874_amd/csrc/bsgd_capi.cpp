@@ -663,6 +663,9 @@ struct bsgd_solver {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     DevBuf g_sched, g_work, g_draws;
+    // entry table of batched calls led by this solver
+    DevBuf batch_dev;
+    Staging batch_stage;
     double* norm_host = nullptr;
     // last call's schedule (host) for export
     std::vector<int32_t> last_sched;
@@ -982,6 +985,107 @@ extern "C" bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_
         }
         if (!std::isfinite(*resid_norm_out)) return fail(BSGD_E_DIVERGED, "residual norm is not finite");
     }
+    return BSGD_OK;
+}
+
+// Schedule, upload and plan n_iters iterations of one solver on stream st (no kernels
+// of the iteration itself).
+static bsgd_status prepare_iterations(bsgd_solver* s, int n_iters, hipStream_t st)
+{
+    const bsgd_geometry* g = s->g;
+    bsgd_status stt = ensure_sched(s, n_iters);
+    if (stt != BSGD_OK) return stt;
+    const size_t sched_bytes = (size_t)n_iters * s->L.stride * sizeof(int32_t);
+    HIP_TRY(s->stage.reserve(sched_bytes));
+    int32_t* host = reinterpret_cast<int32_t*>(s->stage.host);
+    fill_schedule(s, n_iters, host);
+    s->last_sched.assign(host, host + (size_t)n_iters * s->L.stride);
+    s->last_n = n_iters;
+    HIP_TRY(s->stage.upload(s->sched.p, sched_bytes, st));
+    HIP_TRY(launch_plan(g->dg, s->sched.as<int32_t>(), s->L, n_iters, s->o.seed,
+                        s->im ? g->d_q.as<uint32_t>() : nullptr, s->im ? s->draws.as<int8_t>() : nullptr,
+                        s->work.as<PairWork>(), st));
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, int32_t n_iters, void* stream)
+{
+    if (!solvers || n < 1 || n > 65536) return fail(BSGD_E_INVALID_ARG, "need 1 <= n <= 65536 solvers");
+    if (n_iters < 0 || n_iters > (1 << 20)) return fail(BSGD_E_INVALID_ARG, "n_iters must be in [0, 2^20]");
+    hipStream_t st = (hipStream_t)stream;
+    const int dim = solvers[0] ? solvers[0]->g->dim : 0;
+    for (int i = 0; i < n; ++i) {
+        bsgd_solver* s = solvers[i];
+        if (!s) return fail(BSGD_E_INVALID_ARG, "solver %d is NULL", i);
+        if (s->failed) return fail(BSGD_E_STATE, "solver %d is in a failed state", i);
+        if (s->st != st) return fail(BSGD_E_INVALID_ARG, "solver %d was created on another stream", i);
+        if (s->g->dim != dim) return fail(BSGD_E_INVALID_ARG, "a batch mixes 2D and 3D solves");
+        for (int j = 0; j < i; ++j)
+            if (solvers[j] == s) return fail(BSGD_E_INVALID_ARG, "solver %d appears twice", i);
+    }
+    if (n_iters == 0) return BSGD_OK;
+    auto mark_failed = [&](bsgd_status e) {
+        for (int i = 0; i < n; ++i) solvers[i]->failed = true;
+        return e;
+    };
+    for (int i = 0; i < n; ++i) {
+        bsgd_status stt = prepare_iterations(solvers[i], n_iters, st);
+        if (stt != BSGD_OK) return mark_failed(stt);
+    }
+    // entry table
+    bsgd_solver* lead = solvers[0];
+    std::vector<BatchEntry> E(n);
+    int wgs[3] = {0, 0, 0};
+    size_t fp_lds = 0, res_lds = 0;
+    for (int i = 0; i < n; ++i) {
+        bsgd_solver* s = solvers[i];
+        BatchEntry& e = E[i];
+        std::memset(&e, 0, sizeof e);
+        e.G = s->g->dg;
+        e.L = s->L;
+        e.sched = s->sched.as<int32_t>();
+        e.work = s->work.as<PairWork>();
+        e.y = s->y;
+        e.x = s->x;
+        e.z = s->z.as<float>();
+        e.ghat = s->ghat.as<float>();
+        e.gsum = s->gsum.as<float>();
+        e.r_sel = s->r_sel.as<float>();
+        e.mu = (float)s->o.mu;
+        e.n_vox = s->g->n_vox;
+        batch_grids(e);
+        const int per[3] = {e.gx[0] * (e.fp_lds ? e.L.B : 1), e.gx[1] * e.L.maxv, e.gx[2] * e.L.B};
+        for (int p = 0; p < 3; ++p) {
+            e.base[p] = wgs[p];
+            wgs[p] += per[p];
+        }
+        fp_lds = std::max(fp_lds, e.fp_lds ? fp_lds_bytes_for(e.G) : (size_t)0);
+        res_lds = std::max(res_lds, resid_lds_bytes_for(e.G));
+    }
+    const size_t eb = E.size() * sizeof(BatchEntry);
+    hipError_t he = lead->batch_stage.reserve(eb);
+    if (he == hipSuccess && lead->batch_dev.bytes < eb) {
+        he = hipStreamSynchronize(st);
+        if (he == hipSuccess) he = lead->batch_dev.alloc(eb);
+    }
+    if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batch table: %s", hipGetErrorString(he)));
+    std::memcpy(lead->batch_stage.host, E.data(), eb);
+    he = lead->batch_stage.upload(lead->batch_dev.p, eb, st);
+    if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batch table upload: %s", hipGetErrorString(he)));
+    const BatchEntry* dE = lead->batch_dev.as<BatchEntry>();
+    for (int it = 0; it < n_iters; ++it) {
+        he = launch_batch_iteration(dE, n, dim, it, wgs, fp_lds, res_lds, st);
+        if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batched launch: %s", hipGetErrorString(he)));
+        for (int i = 0; i < n; ++i) {
+            bsgd_solver* s = solvers[i];
+            if (s->o.tv_lambda > 0 && (s->k + it + 1) % s->tv_every == 0) {
+                he = launch_tv_prox(s->g->dg, s->x, (float)(s->o.mu * s->o.tv_lambda), s->o.tv_inner_iters,
+                                    s->tv_p.as<float>(), s->tv_a.as<float>(), s->tv_b.as<float>(), st);
+                if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "tv: %s", hipGetErrorString(he)));
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) solvers[i]->k += n_iters;
     return BSGD_OK;
 }
 

@@ -34,6 +34,38 @@ constexpr int MAX_BLOCKS = 1024;
 // Views per workgroup of the LDS-staged forward projector (tunable).
 extern int fp_chunk_views;
 
+// One solve of a batched launch (device array). base[p] is the entry's first
+// workgroup in the batched grid of phase p (0 forward projection, 1 residual,
+// 2 back projection + step); gx[p] its workgroups along x (the per-solve grid's
+// y extent is B, maxv, B).
+struct BatchEntry {
+    DevGeom G;
+    SchedLayout L;
+    const int32_t* sched;  // schedule records of this call
+    const PairWork* work;  // work records of this call
+    const float* y;
+    float* x;
+    float* z;
+    float* ghat;
+    float* gsum;
+    float* r_sel;
+    float mu;
+    int fp_chunk;
+    int fp_lds;
+    long long n_vox;
+    int gx[3];
+    int base[3];
+};
+
+// Per-solve grid of each phase (x extent, total workgroups) for a batch entry.
+void batch_grids(BatchEntry& e);
+// Launch one iteration (index `it` into every entry's records) of all entries; the
+// entries must share the dimension; wgs[p] = total workgroups of phase p.
+hipError_t launch_batch_iteration(const BatchEntry* dev_entries, int n, int dim, int it, const int (&wgs)[3],
+                                  size_t fp_lds_bytes, size_t res_lds_bytes, hipStream_t st);
+size_t fp_lds_bytes_for(const DevGeom& G);
+size_t resid_lds_bytes_for(const DevGeom& G);
+
 hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStream_t st);
 
 // Draws (when q != NULL) and per-(block slot, view slot) work records for n_iters

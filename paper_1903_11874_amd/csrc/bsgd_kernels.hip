@@ -304,12 +304,10 @@ __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restric
 // pair's range. Lanes walk consecutive detector pixels, so z stores are contiguous.
 // x is gathered from global memory (blocks too large for LDS).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
-                                                 const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
-                                                 float* __restrict__ z)
+__device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork* __restrict__ work, SchedLayout L,
+                                               const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
+                                               float* __restrict__ z, int wave, int lane)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (WG / 64) + (threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
     if (wave >= L.maxv * L.B) return;
     const int b = wave / L.maxv;
     const PairWork W = work[wave];
@@ -333,26 +331,37 @@ __global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __re
     }
 }
 
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
+                                                 const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
+                                                 float* __restrict__ z)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (WG / 64) + (threadIdx.x >> 6));
+    fp_global_body<DIM>(G, work, L, blocks_sel, x, z, wave, threadIdx.x & 63);
+}
+
 constexpr int FP_MAX_CHUNK = 16;
 constexpr int FP_LDS_MAX_FLOATS = 16384;  // blocks up to 64 KB are staged in LDS
 
 // Workgroup per (view chunk, block slot): the block's image tile is copied to LDS
 // once and every ray of the chunk's pairs walks it there. Work items are the rays
 // of all pairs of the chunk, flattened.
+struct FpLds {
+    PairWork pw[FP_MAX_CHUNK];
+    int off[FP_MAX_CHUNK + 1];
+};
+
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
-                                                     const int32_t* __restrict__ blocks_sel,
-                                                     const float* __restrict__ x, float* __restrict__ z, int chunk)
+__device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __restrict__ work, SchedLayout L,
+                                            const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
+                                            float* __restrict__ z, int chunk, int bx, int by, float* xs, FpLds& sh)
 {
-    extern __shared__ float xs[];
-    __shared__ PairWork pw[FP_MAX_CHUNK];
-    __shared__ int s_off[FP_MAX_CHUNK + 1];
-    const int b = blockIdx.y;
-    const int a_begin = blockIdx.x * chunk;
+    const int b = by;
+    const int a_begin = bx * chunk;
     if (a_begin >= L.maxv) return;
     const int nch = min(chunk, L.maxv - a_begin);
     const PairWork* wb = work + (int64_t)b * L.maxv + a_begin;
-    if (threadIdx.x < nch) pw[threadIdx.x] = wb[threadIdx.x];
+    if (threadIdx.x < nch) sh.pw[threadIdx.x] = wb[threadIdx.x];
     const BlockInfo B = G.blocks[blocks_sel[b]];
     const int plane = B.nbx * B.nby;
     const int nvox_b = plane * B.nbz;
@@ -364,18 +373,18 @@ __global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* 
     if (threadIdx.x == 0) {
         int off = 0;
         for (int q = 0; q < nch; ++q) {
-            s_off[q] = off;
-            off += max(0, pw[q].k1 - pw[q].k0) * max(0, pw[q].l1 - pw[q].l0);
+            sh.off[q] = off;
+            off += max(0, sh.pw[q].k1 - sh.pw[q].k0) * max(0, sh.pw[q].l1 - sh.pw[q].l0);
         }
-        s_off[nch] = off;
+        sh.off[nch] = off;
     }
     __syncthreads();
-    const int total = s_off[nch];
+    const int total = sh.off[nch];
     for (int item = threadIdx.x; item < total; item += WG) {
         int q = 0;
-        while (s_off[q + 1] <= item) ++q;
-        const PairWork& W = pw[q];
-        const int r = item - s_off[q];
+        while (sh.off[q + 1] <= item) ++q;
+        const PairWork& W = sh.pw[q];
+        const int r = item - sh.off[q];
         int k, l;
         if (DIM == 2) {
             k = W.k0 + r;
@@ -388,6 +397,19 @@ __global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* 
         z[W.zbase + (int64_t)l * W.zw + k] =
             fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xs, (int64_t)B.nbx, (int64_t)plane);
     }
+}
+
+// Workgroup per (view chunk, block slot): the block's image tile is copied to LDS
+// once and every ray of the chunk's pairs walks it there. Work items are the rays
+// of all pairs of the chunk, flattened.
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
+                                                     const int32_t* __restrict__ blocks_sel,
+                                                     const float* __restrict__ x, float* __restrict__ z, int chunk)
+{
+    extern __shared__ float xs[];
+    __shared__ FpLds sh;
+    fp_lds_body<DIM>(G, work, L, blocks_sel, x, z, chunk, blockIdx.x, blockIdx.y, xs, sh);
 }
 
 // ------------------------------------------------------------ solver: residual rebuild
@@ -447,22 +469,29 @@ __host__ __device__ constexpr size_t resid_lds_bytes(int N, int threads)
     return (size_t)N * (sizeof(int4) + sizeof(long long)) + (size_t)threads * RES_BATCH * sizeof(long long);
 }
 
+__device__ __forceinline__ void resid_body(const DevGeom& G, const int32_t* __restrict__ S_, SchedLayout L,
+                                           const float* __restrict__ y, const float* __restrict__ z,
+                                           float* __restrict__ r_sel, int bx, int by, int4* rc)
+{
+    long long* zo = reinterpret_cast<long long*>(rc + G.N);
+    long long* cand = zo + G.N + threadIdx.x * RES_BATCH;
+    const int a = by;
+    if (a >= S_[0]) return;
+    const int v = S_[L.off_views() + a];
+    stage_rects(G, v, rc, zo);
+    const int per_view = G.nu * G.nv;
+    const int ray = bx * RES_WG + threadIdx.x;
+    if (ray >= per_view) return;
+    const int k = ray % G.nu, l = ray / G.nu;
+    r_sel[(int64_t)a * per_view + ray] = resid_ray(G, v, k, l, y, z, rc, zo, cand, per_view, ray);
+}
+
 __global__ __launch_bounds__(RES_WG) void k_resid(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
                                                   const float* __restrict__ y, const float* __restrict__ z,
                                                   float* __restrict__ r_sel)
 {
     extern __shared__ int4 rc[];
-    long long* zo = reinterpret_cast<long long*>(rc + G.N);
-    long long* cand = zo + G.N + threadIdx.x * RES_BATCH;
-    const int a = blockIdx.y;
-    if (a >= S_[0]) return;
-    const int v = S_[L.off_views() + a];
-    stage_rects(G, v, rc, zo);
-    const int per_view = G.nu * G.nv;
-    const int ray = blockIdx.x * RES_WG + threadIdx.x;
-    if (ray >= per_view) return;
-    const int k = ray % G.nu, l = ray / G.nu;
-    r_sel[(int64_t)a * per_view + ray] = resid_ray(G, v, k, l, y, z, rc, zo, cand, per_view, ray);
+    resid_body(G, S_, L, y, z, r_sel, blockIdx.x, blockIdx.y, rc);
 }
 
 // ------------------------------------------------------------ solver: back projection + step
@@ -501,13 +530,13 @@ __device__ __forceinline__ bool tile_voxel(const BlockInfo& B, int tile, int vl,
 // g += sum_i (g_hat^i_new - g_hat^i_old); g_hat^i = g_hat^i_new; then x += mu g.
 // A voxel's update reads only r, so voxels are independent (no atomics).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
-                                                SchedLayout L, const float* __restrict__ r_sel,
-                                                float* __restrict__ ghat, float* __restrict__ gsum,
-                                                float* __restrict__ x, float mu, long long n_vox)
+__device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __restrict__ S_,
+                                             const PairWork* __restrict__ work, SchedLayout L,
+                                             const float* __restrict__ r_sel, float* __restrict__ ghat,
+                                             float* __restrict__ gsum, float* __restrict__ x, float mu, long long n_vox,
+                                             int bx, int by, float (&part)[BP_SPLIT][BP_VOX])
 {
-    __shared__ float part[BP_SPLIT][BP_VOX];
-    const int b = blockIdx.y;
+    const int b = by;
     const int j = S_[L.off_blocks() + b];
     const BlockInfo B = G.blocks[j];
     int nb[3];
@@ -517,7 +546,7 @@ __global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __rest
     const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
     int li[3];
     bool tile_ok;
-    const bool valid = tile_voxel<DIM>(B, blockIdx.x, vl, li, tile_ok);
+    const bool valid = tile_voxel<DIM>(B, bx, vl, li, tile_ok);
     if (!tile_ok) return;  // uniform over the workgroup
     const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
     const int per_view = G.nu * G.nv;
@@ -553,6 +582,81 @@ __global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __rest
         gsum[vox] = gv;
         x[vox] = fmaf(mu, gv, x[vox]);
     }
+}
+
+// For each selected row block i: g_hat^i_new = 2 (A_{rows(i,j)}^{J_j})^T r;
+// g += sum_i (g_hat^i_new - g_hat^i_old); g_hat^i = g_hat^i_new; then x += mu g.
+// A voxel's update reads only r, so voxels are independent (no atomics).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
+                                                SchedLayout L, const float* __restrict__ r_sel,
+                                                float* __restrict__ ghat, float* __restrict__ gsum,
+                                                float* __restrict__ x, float mu, long long n_vox)
+{
+    __shared__ float part[BP_SPLIT][BP_VOX];
+    bp_step_body<DIM>(G, S_, work, L, r_sel, ghat, gsum, x, mu, n_vox, blockIdx.x, blockIdx.y, part);
+}
+
+// ------------------------------------------------------------ batched solves
+
+// Many solves in one launch per phase: workgroup id -> (entry, local workgroup) by a
+// binary search over each entry's first workgroup; the entry's own body then runs
+// exactly as in the single-solve kernels, so a solve's arithmetic does not depend on
+// the batch it runs in.
+__device__ __forceinline__ int find_entry(const BatchEntry* __restrict__ E, int n, int phase, int id)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (E[mid].base[phase] <= id) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fp_batch(const BatchEntry* __restrict__ E, int n, int it)
+{
+    extern __shared__ float xs[];
+    __shared__ FpLds sh;
+    const int id = blockIdx.x;
+    const int e = __builtin_amdgcn_readfirstlane(find_entry(E, n, 0, id));
+    const BatchEntry& B = E[e];
+    const int local = id - B.base[0];
+    const int32_t* S_ = B.sched + (int64_t)it * B.L.stride;
+    const PairWork* W = B.work + (int64_t)it * B.L.maxv * B.L.B;
+    if (B.fp_lds) {
+        fp_lds_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, B.fp_chunk, local % B.gx[0], local / B.gx[0],
+                         xs, sh);
+    } else {
+        const int wave = __builtin_amdgcn_readfirstlane(local * (WG / 64) + (threadIdx.x >> 6));
+        fp_global_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, wave, threadIdx.x & 63);
+    }
+}
+
+__global__ __launch_bounds__(RES_WG) void k_resid_batch(const BatchEntry* __restrict__ E, int n, int it)
+{
+    extern __shared__ int4 rc[];
+    const int id = blockIdx.x;
+    const int e = __builtin_amdgcn_readfirstlane(find_entry(E, n, 1, id));
+    const BatchEntry& B = E[e];
+    const int local = id - B.base[1];
+    const int32_t* S_ = B.sched + (int64_t)it * B.L.stride;
+    resid_body(B.G, S_, B.L, B.y, B.z, B.r_sel, local % B.gx[1], local / B.gx[1], rc);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_bp_batch(const BatchEntry* __restrict__ E, int n, int it)
+{
+    __shared__ float part[BP_SPLIT][BP_VOX];
+    const int id = blockIdx.x;
+    const int e = __builtin_amdgcn_readfirstlane(find_entry(E, n, 2, id));
+    const BatchEntry& B = E[e];
+    const int local = id - B.base[2];
+    const int32_t* S_ = B.sched + (int64_t)it * B.L.stride;
+    const PairWork* W = B.work + (int64_t)it * B.L.maxv * B.L.B;
+    bp_step_body<DIM>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2], local / B.gx[2],
+                      part);
 }
 
 // ------------------------------------------------------------ standalone projectors
@@ -799,6 +903,53 @@ hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayou
         hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, z);
     else
         hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, z);
+    return hipGetLastError();
+}
+
+size_t fp_lds_bytes_for(const DevGeom& G)
+{
+    const int maxvox = max_block_voxels(G);
+    return maxvox <= FP_LDS_MAX_FLOATS ? (size_t)maxvox * sizeof(float) : 0;
+}
+
+size_t resid_lds_bytes_for(const DevGeom& G) { return resid_lds_bytes(G.N, RES_WG); }
+
+static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int dim);
+
+void batch_grids(BatchEntry& e)
+{
+    const DevGeom& G = e.G;
+    const SchedLayout& L = e.L;
+    if (max_block_voxels(G) <= FP_LDS_MAX_FLOATS) {
+        e.fp_lds = 1;
+        e.fp_chunk = std::max(1, std::min(FP_MAX_CHUNK, fp_chunk_views));
+        e.gx[0] = (L.maxv + e.fp_chunk - 1) / e.fp_chunk;
+    } else {
+        e.fp_lds = 0;
+        e.fp_chunk = 0;
+        e.gx[0] = (int)(((int64_t)L.maxv * L.B + 3) / 4);
+    }
+    e.gx[1] = (G.nu * G.nv + RES_WG - 1) / RES_WG;
+    e.gx[2] = max_tiles(G, nullptr, G.dim);
+}
+
+hipError_t launch_batch_iteration(const BatchEntry* dev_entries, int n, int dim, int it, const int (&wgs)[3],
+                                  size_t fp_lds, size_t res_lds, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    if (dim == 3)
+        hipLaunchKernelGGL(k_fp_batch<3>, dim3(wgs[0]), dim3(WG), fp_lds, st, dev_entries, n, it);
+    else
+        hipLaunchKernelGGL(k_fp_batch<2>, dim3(wgs[0]), dim3(WG), fp_lds, st, dev_entries, n, it);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resid_batch, dim3(wgs[1]), dim3(RES_WG), res_lds, st, dev_entries, n, it);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (dim == 3)
+        hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(WG), 0, st, dev_entries, n, it);
+    else
+        hipLaunchKernelGGL(k_bp_batch<2>, dim3(wgs[2]), dim3(WG), 0, st, dev_entries, n, it);
     return hipGetLastError();
 }
 

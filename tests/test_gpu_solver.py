@@ -208,3 +208,45 @@ def test_graph_replay_matches_eager(name, im, tv):
     se.step(T)
     torch.cuda.synchronize()
     assert torch.equal(xg, xe)
+
+
+def test_batched_solves_equal_solo_solves():
+    """Several solves of different geometries in shared launches give bit-identical
+    iterates to the same solves run alone."""
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver, step_batch
+    dev = require_gpu()
+    log("batched vs solo")
+    specs = [(SMALL["fan"].with_(im_mode="colnorm"), 1, 3, 0.0, 31), (SMALL["parallel"], 2, 2, 0.3, 32),
+             (SMALL["fan"], 1, 9, 0.0, 33), (SMALL["parallel"], 1, 1, 0.0, 34)]
+    geoms, runs = {}, []
+    for g, R, B, tv, seed in specs:
+        base = g.with_(im_mode="none")
+        A, x_true, y64, y32 = _data(base, seed)
+        key = (g.kind, g.im_mode)
+        if key not in geoms:
+            geoms[key] = Geometry(g)
+        yd = torch.tensor(y32, device=dev)
+        mu = _mu(A, 0.3)
+        pair = []
+        for _ in range(2):
+            x = torch.zeros(A.shape[1], device=dev)
+            pair.append((x, Solver(geoms[key], yd, x, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=seed,
+                                   tv_lambda=tv, eager=True)))
+        runs.append(pair)
+    for rep, n in enumerate((7, 1, 12)):
+        step_batch([r[0][1] for r in runs], n)
+        for r in runs:
+            r[1][1].step(n)
+        torch.cuda.synchronize()
+        for i, r in enumerate(runs):
+            assert torch.equal(r[0][0], r[1][0]), (rep, i)
+    # a batch of a subset, then the rest, keeps every solve in step with its solo twin
+    step_batch([runs[1][0][1], runs[3][0][1]], 5)
+    step_batch([runs[0][0][1], runs[2][0][1]], 5)
+    for r in runs:
+        r[1][1].step(5)
+    torch.cuda.synchronize()
+    for i, r in enumerate(runs):
+        assert torch.equal(r[0][0], r[1][0]), i
+        assert r[0][1].iterations == r[1][1].iterations
