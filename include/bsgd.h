@@ -124,6 +124,17 @@ typedef enum {
 } bsgd_table;
 bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* out, size_t bytes);
 
+/* Launch-shape tuning of a geometry (does not change any result). fp_views_per_group:
+ * views whose rays one workgroup of the LDS-staged forward projector walks, in [1, 16]
+ * (default 3). Solvers read it at each launch; a solver that already captured its
+ * epoch graph keeps the shape it captured. */
+typedef struct {
+    int32_t fp_views_per_group;
+    int32_t reserved[7];
+} bsgd_tuning;
+bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* geom, const bsgd_tuning* tuning);
+bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* geom, bsgd_tuning* tuning);
+
 #define BSGD_ACCUMULATE 1u
 
 /* Forward projection (Sec. I: FP = A x):
@@ -158,7 +169,13 @@ bsgd_status bsgd_back_project(const bsgd_geometry* geom, const float* y, float* 
  *   (one epoch = round(1/(alpha gamma)) iterations), or earlier when tol > 0 and the
  *   relative normal-equation residual ||A^T(y - A x)|| / ||A^T y|| <= tol, checked
  *   every check_every epochs (0 = every epoch).
- * flags: BSGD_FLAG_EAGER (below). */
+ * flags: BSGD_FLAG_EAGER (below).
+ * auto_mu: Algorithm 3 (Sec. II-A). Every M iterations the g of the last M iterations
+ *   are summed into an effective update direction (EUD), theta is the cosine of two
+ *   consecutive EUDs and ||r|| = ||y - sum_j z^j||; once three norms and two thetas
+ *   exist: three decreasing norms -> mu *= 1 + eps; three increasing norms and
+ *   (|theta - theta_prev| > t1 or theta < t2) -> mu *= 1 - delta. Costs one
+ *   synchronisation every M iterations; not available in bsgd_step_batch. */
 typedef struct {
     int32_t rows_per_iter;
     int32_t blocks_per_iter;
@@ -172,6 +189,10 @@ typedef struct {
     double tol;
     int32_t check_every;
     int32_t flags;                /* BSGD_FLAG_* */
+    int32_t auto_mu;              /* 1: automatic step length (Algorithm 3) */
+    int32_t reserved;
+    double mu_eps, mu_delta;      /* Algorithm 3 epsilon, delta; 0 = 0.05, 0.4 */
+    double mu_t1, mu_t2;          /* Algorithm 3 thresholds t1, t2; 0 = 0.1, 0.5 */
 } bsgd_options;
 
 /* Launch every kernel directly instead of replaying a captured HIP graph of one
@@ -198,6 +219,10 @@ bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_norm_out);
  * created on `stream`, share the dimension (2D or 3D) and be distinct. Asynchronous.
  * Errors mark every solver of the batch as failed. */
 bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, int32_t n_iters, void* stream);
+
+/* Current step length and its value after each Algorithm 3 check (history[0..cap)). */
+bsgd_status bsgd_solver_step_length(const bsgd_solver* s, double* mu_now, double* history, int32_t cap,
+                                    int32_t* n_history);
 
 /* Iterations done so far, and alpha M, gamma N, iterations per effective epoch. */
 bsgd_status bsgd_solver_counts(const bsgd_solver* s, int64_t* iters_done, int32_t* rows_per_iter,

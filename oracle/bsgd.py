@@ -208,12 +208,49 @@ def image_shape(g: GeometrySpec):
     return (g.nz, g.ny, g.nx) if g.is_3d else (g.ny, g.nx)
 
 
+@dataclass
+class AutoMu:
+    """Algorithm 3 (automatic step length). Every M iterations the g's of the last M
+    iterations are summed into an effective update direction (EUD); theta is the
+    cosine between consecutive EUDs; ||r|| is the norm of the maintained residual
+    y - sum_j z^j. Once three residual norms and two thetas exist (k >= 3M, the
+    reading used for the paper's "k > M" whose earlier terms are undefined):
+      ||r||^k < ||r||^{k-M} < ||r||^{k-2M}                   -> mu *= 1 + eps
+      ||r||^k > ||r||^{k-M} > ||r||^{k-2M} and
+        (|theta^k - theta^{k-M}| > t1 or theta^k < t2)        -> mu *= 1 - delta
+    The paper gives delta = 0.4 (Sec. III-C); eps, t1, t2 are not given (readings)."""
+    eps: float = 0.05
+    delta: float = 0.4
+    t1: float = 0.1
+    t2: float = 0.5
+    mu_history: list = field(default_factory=list)
+
+
 def run(p: Problem, y: np.ndarray, mu: float, rows_per_iter: int, blocks_per_iter: int,
         n_iters: int, seed: int, q=None, x0=None, tv_lambda: float = 0.0, tv_iters: int = 20,
-        trace: Optional[list] = None, callback=None) -> State:
+        trace: Optional[list] = None, callback=None, auto_mu: Optional[AutoMu] = None) -> State:
     st = initial_state(p, y, x0)
+    eud = np.zeros(p.A.shape[1])
+    prev_eud = None
+    r_hist, theta_hist = [], []
     for _ in range(n_iters):
         iterate(p, st, y, mu, rows_per_iter, blocks_per_iter, seed, q, tv_lambda, tv_iters, trace)
+        if auto_mu is not None:
+            eud += st.gsum
+            if st.k % p.M == 0:
+                r_hist.append(float(np.linalg.norm(st.r)))
+                if prev_eud is not None:
+                    theta_hist.append(float(eud @ prev_eud / (np.linalg.norm(eud) * np.linalg.norm(prev_eud))))
+                if len(r_hist) >= 3 and len(theta_hist) >= 2:
+                    r0, r1, r2 = r_hist[-1], r_hist[-2], r_hist[-3]
+                    th, th_prev = theta_hist[-1], theta_hist[-2]
+                    if r0 < r1 < r2:
+                        mu = (1.0 + auto_mu.eps) * mu
+                    if r0 > r1 > r2 and (abs(th - th_prev) > auto_mu.t1 or th < auto_mu.t2):
+                        mu = (1.0 - auto_mu.delta) * mu
+                auto_mu.mu_history.append(mu)
+                prev_eud = eud
+                eud = np.zeros(p.A.shape[1])
         if callback is not None:
             callback(st)
     return st

@@ -61,14 +61,21 @@ class Options(ctypes.Structure):
         ("tv_inner_iters", ctypes.c_int32), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("tv_lambda", ctypes.c_double), ("tv_every", ctypes.c_int32), ("max_effective_epochs", ctypes.c_int32),
         ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("auto_mu", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu_eps", ctypes.c_double),
+        ("mu_delta", ctypes.c_double), ("mu_t1", ctypes.c_double), ("mu_t2", ctypes.c_double),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fp_views_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 EXPORTED = (
     "bsgd_geometry_create", "bsgd_geometry_destroy", "bsgd_geometry_get_info", "bsgd_geometry_table",
     "bsgd_forward_project", "bsgd_back_project", "bsgd_solver_create", "bsgd_step", "bsgd_solver_counts",
     "bsgd_solver_last_schedule", "bsgd_solver_state", "bsgd_solver_set_profiling", "bsgd_solver_kernel_times",
-    "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error", "bsgd_step_batch",
+    "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error", "bsgd_step_batch", "bsgd_geometry_set_tuning",
+    "bsgd_geometry_get_tuning", "bsgd_solver_step_length",
 )
 
 _lib = None
@@ -103,6 +110,9 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(ctypes.c_double)]),
         "bsgd_last_error": (ctypes.c_char_p, []),
         "bsgd_step_batch": (i32, [ctypes.POINTER(P), i32, i32, P]),
+        "bsgd_geometry_set_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
+        "bsgd_geometry_get_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
+        "bsgd_solver_step_length": (i32, [P, ctypes.POINTER(ctypes.c_double), P, i32, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -191,6 +201,18 @@ class Geometry:
         except Exception:
             pass
 
+    @property
+    def fp_views_per_group(self) -> int:
+        t = Tuning()
+        _check(load_library().bsgd_geometry_get_tuning(self._h, ctypes.byref(t)))
+        return t.fp_views_per_group
+
+    @fp_views_per_group.setter
+    def fp_views_per_group(self, value: int):
+        t = Tuning()
+        t.fp_views_per_group = int(value)
+        _check(load_library().bsgd_geometry_set_tuning(self._h, ctypes.byref(t)))
+
     def table(self, name: str) -> np.ndarray:
         g = self.spec
         V, S, N, M = g.n_views, g.su * g.sv, g.n_blocks, g.n_row_blocks
@@ -247,12 +269,14 @@ FLAG_EAGER = 1
 
 def make_options(rows_per_iter=0, blocks_per_iter=0, node_count=0, mu=0.0, seed=0, tv_lambda=0.0,
                  tv_inner_iters=20, tv_every=0, max_effective_epochs=0, tol=0.0, check_every=0,
-                 eager=False) -> Options:
+                 eager=False, auto_mu=False, mu_eps=0.0, mu_delta=0.0, mu_t1=0.0, mu_t2=0.0) -> Options:
     o = Options()
     o.rows_per_iter, o.blocks_per_iter, o.node_count = rows_per_iter, blocks_per_iter, node_count
     o.tv_inner_iters, o.mu, o.seed, o.tv_lambda, o.tv_every = tv_inner_iters, mu, seed, tv_lambda, tv_every
     o.max_effective_epochs, o.tol, o.check_every = max_effective_epochs, tol, check_every
     o.flags = FLAG_EAGER if eager else 0
+    o.auto_mu, o.reserved = (1 if auto_mu else 0), 0
+    o.mu_eps, o.mu_delta, o.mu_t1, o.mu_t2 = mu_eps, mu_delta, mu_t1, mu_t2
     return o
 
 
@@ -294,6 +318,15 @@ class Solver:
         out = ctypes.c_double() if residual else None
         _check(load_library().bsgd_step(self._h, int(n_iters), ctypes.byref(out) if residual else None))
         return out.value if residual else None
+
+    def step_length(self):
+        """(current mu, list of mu after each Algorithm 3 check)."""
+        lib = load_library()
+        mu, n = ctypes.c_double(), ctypes.c_int32()
+        _check(lib.bsgd_solver_step_length(self._h, ctypes.byref(mu), None, 0, ctypes.byref(n)))
+        hist = np.zeros(max(n.value, 1))
+        _check(lib.bsgd_solver_step_length(self._h, None, hist.ctypes.data_as(ctypes.c_void_p), n.value, None))
+        return mu.value, list(hist[: n.value])
 
     def last_schedule(self):
         lib = load_library()

@@ -437,6 +437,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.blocks = g->d_blocks.as<BlockInfo>();
     G.raydir = g->d_raydir.as<float4>();
     G.rayv = g->d_rayv.as<float2>();
+    G.fp_chunk = 3;
     return BSGD_OK;
 }
 
@@ -578,6 +579,23 @@ extern "C" bsgd_status bsgd_geometry_table(const bsgd_geometry* g, int32_t which
     return BSGD_OK;
 }
 
+extern "C" bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* g, const bsgd_tuning* t)
+{
+    if (!g || !t) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    if (t->fp_views_per_group < 1 || t->fp_views_per_group > FP_CHUNK_MAX)
+        return fail(BSGD_E_INVALID_ARG, "fp_views_per_group must be in [1, %d]", FP_CHUNK_MAX);
+    g->dg.fp_chunk = t->fp_views_per_group;
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* g, bsgd_tuning* t)
+{
+    if (!g || !t) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    std::memset(t, 0, sizeof *t);
+    t->fp_views_per_group = g->dg.fp_chunk;
+    return BSGD_OK;
+}
+
 // Device view list for a standalone projector call.
 static bsgd_status view_list(bsgd_geometry* g, const int32_t* views, int32_t n, hipStream_t st, const int32_t** dev)
 {
@@ -666,6 +684,14 @@ struct bsgd_solver {
     // entry table of batched calls led by this solver
     DevBuf batch_dev;
     Staging batch_stage;
+    // step length on the device (read by the back-projection kernel) and Algorithm 3
+    DevBuf mu_dev, eud_cur, eud_prev;
+    float* mu_host = nullptr;
+    double mu_cur = 0.0;
+    bool auto_mu = false, have_prev_eud = false;
+    double prev_eud_n2 = 0.0;
+    double am_eps = 0.05, am_delta = 0.4, am_t1 = 0.1, am_t2 = 0.5;
+    std::vector<double> r_hist, theta_hist, mu_hist;
     double* norm_host = nullptr;
     // last call's schedule (host) for export
     std::vector<int32_t> last_sched;
@@ -686,6 +712,7 @@ struct bsgd_solver {
         }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         if (norm_host) (void)hipHostFree(norm_host);
+        if (mu_host) (void)hipHostFree(mu_host);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -754,6 +781,9 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     if (o->tv_lambda > 0 && o->tv_inner_iters < 1) return fail(BSGD_E_INVALID_ARG, "tv_inner_iters must be >= 1");
     if (o->tv_every < 0 || o->max_effective_epochs < 0 || o->check_every < 0 || !(o->tol >= 0.0))
         return fail(BSGD_E_INVALID_ARG, "negative option");
+    if (o->auto_mu && (!(o->mu_eps >= 0) || !(o->mu_delta >= 0 && o->mu_delta < 1) || !(o->mu_t1 >= 0) ||
+                       !(o->mu_t2 >= 0) || !(o->mu > 0)))
+        return fail(BSGD_E_INVALID_ARG, "auto_mu needs mu > 0, eps >= 0, 0 <= delta < 1, t1, t2 >= 0");
     bsgd_solver* s = new (std::nothrow) bsgd_solver();
     if (!s) return fail(BSGD_E_OUT_OF_MEMORY, "host allocation failed");
     s->g = g;
@@ -790,8 +820,24 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     S_TRY(s->r_sel.alloc((size_t)s->maxv * per_view * sizeof(float)));
     const int n_part = (int)(((per_view + 255) / 256) * g->d.n_views);
     S_TRY(s->partials.alloc((size_t)std::max(n_part, 4096) * sizeof(double)));
-    S_TRY(s->norm_out.alloc(sizeof(double)));
-    S_TRY(hipHostMalloc((void**)&s->norm_host, sizeof(double), hipHostMallocDefault));
+    S_TRY(s->norm_out.alloc(4 * sizeof(double)));
+    S_TRY(hipHostMalloc((void**)&s->norm_host, 4 * sizeof(double), hipHostMallocDefault));
+    S_TRY(s->mu_dev.alloc(sizeof(float)));
+    S_TRY(hipHostMalloc((void**)&s->mu_host, sizeof(float), hipHostMallocDefault));
+    s->mu_cur = o->mu;
+    *s->mu_host = (float)o->mu;
+    S_TRY(hipMemcpyAsync(s->mu_dev.p, s->mu_host, sizeof(float), hipMemcpyHostToDevice, st));
+    S_TRY(hipStreamSynchronize(st));
+    s->auto_mu = o->auto_mu != 0;
+    if (s->auto_mu) {
+        if (o->mu_eps > 0) s->am_eps = o->mu_eps;
+        if (o->mu_delta > 0) s->am_delta = o->mu_delta;
+        if (o->mu_t1 > 0) s->am_t1 = o->mu_t1;
+        if (o->mu_t2 > 0) s->am_t2 = o->mu_t2;
+        S_TRY(s->eud_cur.alloc((size_t)g->n_vox * sizeof(float)));
+        S_TRY(s->eud_prev.alloc((size_t)g->n_vox * sizeof(float)));
+        S_TRY(launch_fill(s->eud_cur.as<float>(), 0.0f, g->n_vox, st));
+    }
     if (o->tv_lambda > 0) {
         const size_t nb = (size_t)g->dim * g->n_vox * sizeof(float);
         S_TRY(s->tv_p.alloc(nb));
@@ -886,11 +932,15 @@ static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32
         if (e != hipSuccess) return e;
         e = timed(s, KID_BP, [&] {
             return launch_bp_step(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->ghat.as<float>(), s->gsum.as<float>(),
-                                  s->x, (float)s->o.mu, g->n_vox, st);
+                                  s->x, s->mu_dev.as<float>(), g->n_vox, st);
         });
         if (e != hipSuccess) return e;
+        if (s->auto_mu) {
+            e = launch_add(s->eud_cur.as<float>(), s->gsum.as<float>(), g->n_vox, st);
+            if (e != hipSuccess) return e;
+        }
         if (s->o.tv_lambda > 0 && (k_first + it + 1) % s->tv_every == 0) {
-            const float w = (float)(s->o.mu * s->o.tv_lambda);
+            const float w = (float)(s->mu_cur * s->o.tv_lambda);
             e = timed(s, KID_TV, [&] {
                 return launch_tv_prox(g->dg, s->x, w, s->o.tv_inner_iters, s->tv_p.as<float>(), s->tv_a.as<float>(),
                                       s->tv_b.as<float>(), st);
@@ -924,7 +974,7 @@ static bsgd_status build_graph(bsgd_solver* s)
     return BSGD_OK;
 }
 
-static bsgd_status step_impl(bsgd_solver* s, int n_iters)
+static bsgd_status step_segment(bsgd_solver* s, int n_iters)
 {
     const int T = s->T;
     const bool tv_aligned = !(s->o.tv_lambda > 0) || (T % s->tv_every == 0);
@@ -962,6 +1012,79 @@ static bsgd_status step_impl(bsgd_solver* s, int n_iters)
     HIP_TRY(hipEventRecord(s->stage.done, s->st));
     s->stage.pending = true;
     s->k += n_iters;
+    return BSGD_OK;
+}
+
+// Algorithm 3 check at an iteration count that is a multiple of M: EUD norms, the
+// cosine between consecutive EUDs, the residual norm, then the two criteria.
+static bsgd_status auto_mu_check(bsgd_solver* s)
+{
+    const bsgd_geometry* g = s->g;
+    double* dp = s->partials.as<double>();
+    double* out = s->norm_out.as<double>();
+    int np = 0;
+    HIP_TRY(launch_dot(s->eud_cur.as<float>(), s->eud_cur.as<float>(), g->n_vox, dp, &np, s->st));
+    HIP_TRY(launch_sum_partials(dp, np, out, s->st));
+    if (s->have_prev_eud) {
+        HIP_TRY(launch_dot(s->eud_cur.as<float>(), s->eud_prev.as<float>(), g->n_vox, dp, &np, s->st));
+        HIP_TRY(launch_sum_partials(dp, np, out + 1, s->st));
+    }
+    HIP_TRY(launch_resid_sumsq(g->dg, s->y, s->z.as<float>(), dp, &np, s->st));
+    HIP_TRY(launch_sum_partials(dp, np, out + 2, s->st));
+    HIP_TRY(hipMemcpyAsync(s->norm_host, out, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(hipStreamSynchronize(s->st));
+    const double n2 = s->norm_host[0], cross = s->norm_host[1], r = std::sqrt(s->norm_host[2]);
+    s->r_hist.push_back(r);
+    if (s->have_prev_eud) s->theta_hist.push_back(cross / std::sqrt(n2 * s->prev_eud_n2));
+    const size_t nr = s->r_hist.size(), nt = s->theta_hist.size();
+    if (nr >= 3 && nt >= 2) {
+        const double r0 = s->r_hist[nr - 1], r1 = s->r_hist[nr - 2], r2 = s->r_hist[nr - 3];
+        const double th = s->theta_hist[nt - 1], thp = s->theta_hist[nt - 2];
+        double mu = s->mu_cur;
+        if (r0 < r1 && r1 < r2) mu = (1.0 + s->am_eps) * mu;
+        if (r0 > r1 && r1 > r2 && (std::fabs(th - thp) > s->am_t1 || th < s->am_t2)) mu = (1.0 - s->am_delta) * mu;
+        if (mu != s->mu_cur) {
+            s->mu_cur = mu;
+            *s->mu_host = (float)mu;
+            HIP_TRY(hipMemcpyAsync(s->mu_dev.p, s->mu_host, sizeof(float), hipMemcpyHostToDevice, s->st));
+            HIP_TRY(hipStreamSynchronize(s->st));
+        }
+    }
+    s->mu_hist.push_back(s->mu_cur);
+    s->prev_eud_n2 = n2;
+    s->have_prev_eud = true;
+    HIP_TRY(hipMemcpyAsync(s->eud_prev.p, s->eud_cur.p, (size_t)g->n_vox * sizeof(float), hipMemcpyDeviceToDevice,
+                           s->st));
+    HIP_TRY(launch_fill(s->eud_cur.as<float>(), 0.0f, g->n_vox, s->st));
+    return BSGD_OK;
+}
+
+static bsgd_status step_impl(bsgd_solver* s, int n_iters)
+{
+    if (!s->auto_mu) return step_segment(s, n_iters);
+    const int M = s->g->M;
+    int left = n_iters;
+    while (left > 0) {
+        const int seg = std::min<int64_t>(left, M - s->k % M);
+        bsgd_status stt = step_segment(s, seg);
+        if (stt != BSGD_OK) return stt;
+        left -= seg;
+        if (s->k % M == 0) {
+            stt = auto_mu_check(s);
+            if (stt != BSGD_OK) return stt;
+        }
+    }
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_solver_step_length(const bsgd_solver* s, double* mu_now, double* history, int32_t cap,
+                                              int32_t* n_history)
+{
+    if (!s) return fail(BSGD_E_INVALID_ARG, "solver is NULL");
+    if (mu_now) *mu_now = s->mu_cur;
+    if (n_history) *n_history = (int32_t)s->mu_hist.size();
+    if (history)
+        for (int32_t i = 0; i < cap && i < (int32_t)s->mu_hist.size(); ++i) history[i] = s->mu_hist[i];
     return BSGD_OK;
 }
 
@@ -1020,6 +1143,7 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         if (s->failed) return fail(BSGD_E_STATE, "solver %d is in a failed state", i);
         if (s->st != st) return fail(BSGD_E_INVALID_ARG, "solver %d was created on another stream", i);
         if (s->g->dim != dim) return fail(BSGD_E_INVALID_ARG, "a batch mixes 2D and 3D solves");
+        if (s->auto_mu) return fail(BSGD_E_UNSUPPORTED, "solver %d tunes its step length; step it alone", i);
         for (int j = 0; j < i; ++j)
             if (solvers[j] == s) return fail(BSGD_E_INVALID_ARG, "solver %d appears twice", i);
     }
@@ -1051,7 +1175,7 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         e.ghat = s->ghat.as<float>();
         e.gsum = s->gsum.as<float>();
         e.r_sel = s->r_sel.as<float>();
-        e.mu = (float)s->o.mu;
+        e.mu = s->mu_dev.as<float>();
         e.n_vox = s->g->n_vox;
         batch_grids(e);
         const int per[3] = {e.gx[0] * (e.fp_lds ? e.L.B : 1), e.gx[1] * e.L.maxv, e.gx[2] * e.L.B};
@@ -1079,7 +1203,7 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         for (int i = 0; i < n; ++i) {
             bsgd_solver* s = solvers[i];
             if (s->o.tv_lambda > 0 && (s->k + it + 1) % s->tv_every == 0) {
-                he = launch_tv_prox(s->g->dg, s->x, (float)(s->o.mu * s->o.tv_lambda), s->o.tv_inner_iters,
+                he = launch_tv_prox(s->g->dg, s->x, (float)(s->mu_cur * s->o.tv_lambda), s->o.tv_inner_iters,
                                     s->tv_p.as<float>(), s->tv_a.as<float>(), s->tv_b.as<float>(), st);
                 if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "tv: %s", hipGetErrorString(he)));
             }

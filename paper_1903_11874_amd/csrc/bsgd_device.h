@@ -72,6 +72,8 @@ struct DevGeom {
     const BlockInfo* blocks;   // [N]
     const float4* raydir;      // [n_views][nu]: 1/a, 1/b, |(a,b)|^2 (cone) or |d| (2D), unused
     const float2* rayv;        // [nv]: 1/v, v^2 (cone only)
+    int32_t fp_chunk;          // views per workgroup of the LDS forward projector (tuning)
+    int32_t pad_;
 };
 
 // Sub-detector s covers u in [k0, k1), v in [l0, l1).

@@ -31,8 +31,8 @@ constexpr int8_t DRAW_SKIP = -1;
 // Maximum column blocks per geometry (the residual kernels stage one view's
 // footprint rectangles in LDS).
 constexpr int MAX_BLOCKS = 1024;
-// Views per workgroup of the LDS-staged forward projector (tunable).
-extern int fp_chunk_views;
+// Largest views-per-workgroup of the LDS-staged forward projector.
+constexpr int FP_CHUNK_MAX = 16;
 
 // One solve of a batched launch (device array). base[p] is the entry's first
 // workgroup in the batched grid of phase p (0 forward projection, 1 residual,
@@ -49,7 +49,7 @@ struct BatchEntry {
     float* ghat;
     float* gsum;
     float* r_sel;
-    float mu;
+    const float* mu;  // device scalar (the current step length)
     int fp_chunk;
     int fp_lds;
     long long n_vox;
@@ -82,7 +82,7 @@ hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L
                         const float* z, float* r_sel, hipStream_t st);
 
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
-                          const float* r_sel, float* ghat, float* gsum, float* x, float mu, int64_t n_vox,
+                          const float* r_sel, float* ghat, float* gsum, float* x, const float* mu, int64_t n_vox,
                           hipStream_t st);
 
 // Standalone projectors over a device view list (views[n_sel]); block < 0 = all blocks.
@@ -102,6 +102,10 @@ hipError_t launch_sum_partials(const double* partials, int n, double* out, hipSt
 // a[i] = b[i] - c[i]
 hipError_t launch_sub(const float* b, const float* c, float* a, int64_t n, hipStream_t st);
 hipError_t launch_fill(float* a, float v, int64_t n, hipStream_t st);
+// a[i] += b[i]
+hipError_t launch_add(float* a, const float* b, int64_t n, hipStream_t st);
+// partial sums of a . b (FP64) into partials
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partials, int* n_partials, hipStream_t st);
 
 // TV proximal step of BSGD-TV on x (in place): iters fast-gradient-projection steps.
 // p, ra, rb: device [dim][n_vox] scratch.

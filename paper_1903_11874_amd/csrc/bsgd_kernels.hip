@@ -533,8 +533,9 @@ template <int DIM>
 __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __restrict__ S_,
                                              const PairWork* __restrict__ work, SchedLayout L,
                                              const float* __restrict__ r_sel, float* __restrict__ ghat,
-                                             float* __restrict__ gsum, float* __restrict__ x, float mu, long long n_vox,
-                                             int bx, int by, float (&part)[BP_SPLIT][BP_VOX])
+                                             float* __restrict__ gsum, float* __restrict__ x,
+                                             const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
+                                             float (&part)[BP_SPLIT][BP_VOX])
 {
     const int b = by;
     const int j = S_[L.off_blocks() + b];
@@ -580,7 +581,7 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
     if (grp == 0 && valid) {
         const float gv = gsum[vox] + dg;
         gsum[vox] = gv;
-        x[vox] = fmaf(mu, gv, x[vox]);
+        x[vox] = fmaf(*mu_ptr, gv, x[vox]);
     }
 }
 
@@ -591,7 +592,8 @@ template <int DIM>
 __global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
                                                 SchedLayout L, const float* __restrict__ r_sel,
                                                 float* __restrict__ ghat, float* __restrict__ gsum,
-                                                float* __restrict__ x, float mu, long long n_vox)
+                                                float* __restrict__ x, const float* __restrict__ mu,
+                                                long long n_vox)
 {
     __shared__ float part[BP_SPLIT][BP_VOX];
     bp_step_body<DIM>(G, S_, work, L, r_sel, ghat, gsum, x, mu, n_vox, blockIdx.x, blockIdx.y, part);
@@ -776,6 +778,23 @@ __global__ __launch_bounds__(WG) void k_sub(const float* __restrict__ b, const f
     if (i < n) a[i] = b[i] - c[i];
 }
 
+__global__ __launch_bounds__(WG) void k_add(float* __restrict__ a, const float* __restrict__ b, long long n)
+{
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) a[i] += b[i];
+}
+
+__global__ __launch_bounds__(WG) void k_dot(const float* __restrict__ a, const float* __restrict__ b, long long n,
+                                            double* __restrict__ partials)
+{
+    __shared__ double lds[4];
+    double val = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) val += (double)a[i] * (double)b[i];
+    const double s = block_sum(val, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 __global__ __launch_bounds__(WG) void k_fill(float* __restrict__ a, float v, long long n)
 {
     const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -879,14 +898,12 @@ static int max_block_voxels(const DevGeom& G)
     return ((G.nx + G.bx - 1) / G.bx) * ((G.ny + G.by - 1) / G.by) * ((G.nz + G.bz - 1) / G.bz);
 }
 
-int fp_chunk_views = 3;  // views per workgroup of the LDS forward projector
-
 hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,
                            const float* x, float* z, hipStream_t st)
 {
     const int maxvox = max_block_voxels(G);
     if (maxvox <= FP_LDS_MAX_FLOATS) {
-        const int chunk = std::max(1, std::min(FP_MAX_CHUNK, fp_chunk_views));
+        const int chunk = std::max(1, std::min(FP_MAX_CHUNK, G.fp_chunk));
         const unsigned gx = (unsigned)((L.maxv + chunk - 1) / chunk);
         const size_t lds = (size_t)maxvox * sizeof(float);
         if (G.dim == 3)
@@ -922,7 +939,7 @@ void batch_grids(BatchEntry& e)
     const SchedLayout& L = e.L;
     if (max_block_voxels(G) <= FP_LDS_MAX_FLOATS) {
         e.fp_lds = 1;
-        e.fp_chunk = std::max(1, std::min(FP_MAX_CHUNK, fp_chunk_views));
+        e.fp_chunk = std::max(1, std::min(FP_MAX_CHUNK, G.fp_chunk));
         e.gx[0] = (L.maxv + e.fp_chunk - 1) / e.fp_chunk;
     } else {
         e.fp_lds = 0;
@@ -974,7 +991,7 @@ static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int 
 }
 
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
-                          const float* r_sel, float* ghat, float* gsum, float* x, float mu, int64_t n_vox,
+                          const float* r_sel, float* ghat, float* gsum, float* x, const float* mu, int64_t n_vox,
                           hipStream_t st)
 {
     const int tiles = max_tiles(G, nullptr, G.dim);
@@ -1046,6 +1063,23 @@ hipError_t launch_sub(const float* b, const float* c, float* a, int64_t n, hipSt
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sub, dim3(grid1(n)), dim3(WG), 0, st, b, c, a, (long long)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(float* a, const float* b, int64_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add, dim3(grid1(n)), dim3(WG), 0, st, a, b, (long long)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partials, int* n_partials, hipStream_t st)
+{
+    int64_t blocks = (n + WG - 1) / WG;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_dot, dim3((unsigned)blocks), dim3(WG), 0, st, a, b, (long long)n, partials);
+    *n_partials = (int)blocks;
     return hipGetLastError();
 }
 

@@ -250,3 +250,52 @@ def test_batched_solves_equal_solo_solves():
     for i, r in enumerate(runs):
         assert torch.equal(r[0][0], r[1][0]), i
         assert r[0][1].iterations == r[1][1].iterations
+
+
+def test_autotuner_shapes_do_not_change_results():
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver
+    from paper_1903_11874_amd.tuning import autotune
+    dev = require_gpu()
+    log("autotuner")
+    g = SMALL["fan"].with_(im_mode="colnorm")
+    A, x_true, y64, y32 = _data(SMALL["fan"])
+    mu = _mu(A, 0.3)
+    geom = Geometry(g)
+    yd = torch.tensor(y32, device=dev)
+    timings = autotune(geom, yd, node_count=9, mu=mu, candidates=(1, 2, 5, 16), epochs=1)
+    assert set(timings) == {1, 2, 5, 16} and geom.fp_views_per_group in timings
+    outs = []
+    for c in (1, 4, 16):
+        geom.fp_views_per_group = c
+        x = torch.zeros(A.shape[1], device=dev)
+        Solver(geom, yd, x, node_count=9, mu=mu, seed=3, eager=True).step(20)
+        outs.append(x)
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
+
+
+@pytest.mark.parametrize("scale,eager", [(2.0, True), (0.05, False)])
+def test_auto_step_length_matches_oracle(scale, eager):
+    """Algorithm 3: the same step-length decisions as the oracle, and the iterate."""
+    import torch
+    from oracle.bsgd import AutoMu
+    from paper_1903_11874_amd import Geometry, Solver
+    dev = require_gpu()
+    g = SMALL["fan"]
+    log(f"auto mu scale={scale}")
+    p = oracle_problem(g)
+    A, x_true, y64, y32 = _data(g)
+    mu = _mu(A, scale)
+    am = AutoMu()
+    R, B, n = 1, 9, 16 * g.n_row_blocks  # T = M: checks at every epoch boundary
+    st = run(p, y64, mu, R, B, n, 17, auto_mu=am)
+    geom = Geometry(g)
+    yd = torch.tensor(y32, device=dev)
+    xd = torch.zeros(A.shape[1], device=dev)
+    s = Solver(geom, yd, xd, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=17, auto_mu=True, eager=eager)
+    s.step(n)
+    mu_now, hist = s.step_length()
+    assert len(hist) == len(am.mu_history) == 16
+    assert np.allclose(hist, am.mu_history, rtol=1e-12)
+    assert hist[-1] != mu  # the rule acted
+    assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL

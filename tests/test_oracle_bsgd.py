@@ -147,3 +147,21 @@ def test_tv_period_and_zero_lambda(e1):
         if k < T - 1:
             assert np.array_equal(st.x, plain.x)
     assert np.allclose(st.x, fgp_prox(plain.x.reshape(16, 16), mu * lam, 20).ravel(), atol=1e-14)
+
+
+def test_auto_mu_shrinks_a_diverging_step_and_grows_a_small_one():
+    from oracle.bsgd import AutoMu
+    p = _e1_problem(M=4, bx=2)
+    r = np.random.Generator(np.random.PCG64(12))
+    y = p.A @ r.uniform(size=p.A.shape[1])
+    L = lipschitz(p.A)
+    big = AutoMu()
+    st = run(p, y, 3.0 / (2 * L), 1, 1, 400, seed=3, auto_mu=big)
+    assert len(big.mu_history) == 100
+    assert min(big.mu_history) < 3.0 / (2 * L)          # criteria 1 + 2 cut the step
+    assert np.isfinite(st.x).all()
+    small = AutoMu()
+    run(p, y, 0.02 / (2 * L), 1, 1, 400, seed=3, auto_mu=small)
+    assert small.mu_history[-1] > 0.02 / (2 * L)         # steady decrease grows the step
+    # no change before three residual norms and two thetas exist (k < 3M)
+    assert small.mu_history[0] == small.mu_history[1] == 0.02 / (2 * L)
