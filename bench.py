@@ -96,12 +96,54 @@ def cpu_baseline(spec, x, budget_s=12.0):
                       f"{updates:.3e} updates in {elapsed:.2f} s"}
 
 
+def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
+    """Continuous-batching server vs the plain per-solve loop on a seeded Poisson stream
+    of 2D fan-beam solves (sides 128..1024, views = bins = 1.5 side, 1% noise)."""
+    import torch
+    from bsgd_inputs.configs import SERVING_SIDES, fan_request_geometry
+    from bsgd_inputs.phantoms import phantom_for, add_gaussian_noise
+    from paper_1903_11874_amd.serving import Request, Server, latency_stats
+    rng = np.random.Generator(np.random.PCG64(seed))
+    server = Server(max_slots=max_slots)
+    mus = {}
+    reqs = []
+    t = 0.0
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        side = int(rng.choice(SERVING_SIDES))
+        spec = fan_request_geometry(side)
+        geom = server.geometry(spec)
+        if spec not in mus:
+            mus[spec] = 0.5 / (2.0 * lipschitz_gpu(geom, spec.nx * spec.ny, iters=15))
+        x_true = torch.tensor(phantom_for(spec, 10, 5000 + rid), dtype=torch.float32, device="cuda")
+        y = add_gaussian_noise(geom.forward_project(x_true).double().cpu().numpy(), 0.01, 6000 + rid)
+        reqs.append(Request(rid=rid, geometry=spec, y=torch.tensor(y, dtype=torch.float32, device="cuda"),
+                            arrival=t, mu=mus[spec], seed=rid, node_count=64, tol=tol, max_epochs=max_epochs,
+                            check_every=5))
+    torch.cuda.synchronize()
+    log(f"serving: {n_requests} requests over {t:.2f} s, sides {sorted(set(r.geometry.nx for r in reqs))}")
+    served = server.run(reqs)
+    seq = Server(max_slots=1).run_sequential(reqs)
+    same = all(torch.equal(a.x, b.x) for a, b in zip(served, seq))
+    st_b, st_s = latency_stats(served), latency_stats(seq)
+    return {"requests": n_requests, "rate_per_s": rate, "arrival_span_s": t, "max_slots": max_slots,
+            "stop_rule": f"||A^T(y-Ax)||/||A^T y|| <= {tol} checked every 5 epochs, at most {max_epochs} epochs",
+            "batched": st_b, "sequential": st_s,
+            "solves_per_s_ratio": st_b["solves_per_s"] / st_s["solves_per_s"],
+            "identical_results": bool(same),
+            "max_active": max(n for _, n in server.log) if server.log else 0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=48,
+                    help="requests of the continuous-batching serving measurement (0 = skip)")
+    ap.add_argument("--serving-tol", type=float, default=1e-3)
+    ap.add_argument("--serving-max-epochs", type=int, default=30)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -224,6 +266,8 @@ def main():
         "residual_norm": {"before": r0, "after": r1},
         "updates_per_step": updates / args.steps,
     }
+    if args.serving > 0:
+        out["serving"] = serving_bench(args.serving, 20.0, 32, args.serving_tol, args.serving_max_epochs)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(spec, x_true)

@@ -162,9 +162,10 @@ struct bsgd_geometry {
     std::vector<double> im_w;
     std::vector<int64_t> im_nnz;
     std::vector<uint32_t> im_q;
-    std::vector<float4> raydir;
+    std::vector<float4> raydir, raynorm, raytrap;
     std::vector<float2> rayv;
-    DevBuf d_cs, d_pairs, d_blocks, d_q, d_all_views, d_views, d_raydir, d_rayv;
+    std::vector<float> kspan;
+    DevBuf d_cs, d_pairs, d_blocks, d_q, d_all_views, d_views, d_raydir, d_rayv, d_raynorm, d_raytrap, d_kspan;
     Staging stage;
     DevGeom dg{};
 };
@@ -382,6 +383,44 @@ static void build_tables(bsgd_geometry* g)
         const double vv = (l - lv) * d.dv;
         g->rayv[l] = make_float2(recip(vv), (float)(vv * vv));
     }
+
+    // 2D chord tables: unit normal of each ray, xi (n . p = lambda xi for the anchor
+    // point p = lambda e_u), and the chord trapezoid through one voxel
+    if (!is3d) {
+        const double hx = 0.5 * d.vx, hy = 0.5 * d.vy;
+        g->raynorm.resize((size_t)d.n_views * d.nu);
+        g->raytrap.resize((size_t)d.n_views * d.nu);
+        g->kspan.resize(d.n_views);
+        for (int v = 0; v < d.n_views; ++v) {
+            const double c = std::cos(d.angles_rad[v]), s = std::sin(d.angles_rad[v]);
+            double span = 0.0;
+            for (int k = 0; k < d.nu; ++k) {
+                double nx, ny, xi, len;
+                if (par) {
+                    nx = -s;
+                    ny = c;
+                    xi = 1.0;
+                    len = 1.0;
+                } else {
+                    const double u = (k - ku) * d.du;
+                    const double a = -d.sdd * c - u * s, b = -d.sdd * s + u * c;
+                    len = std::sqrt(d.sdd * d.sdd + u * u);
+                    nx = -b / len;
+                    ny = a / len;
+                    xi = -d.sdd / len;
+                }
+                const double ax = std::fabs(nx), ay = std::fabs(ny);
+                const double w2 = hx * ax + hy * ay, w1 = std::fabs(hx * ax - hy * ay);
+                const double lx = ay > 0 ? d.vx / ay : INFINITY, ly = ax > 0 ? d.vy / ax : INFINITY;
+                const double lmax = std::min(lx, ly);
+                const double slope = w2 > w1 ? lmax / (w2 - w1) : INFINITY;
+                g->raynorm[(size_t)v * d.nu + k] = make_float4((float)nx, (float)ny, (float)xi, 0.0f);
+                g->raytrap[(size_t)v * d.nu + k] = make_float4((float)w1, (float)w2, (float)lmax, (float)slope);
+                span = std::max(span, w2 * len / d.du);
+            }
+            g->kspan[v] = (float)(span * (1.0 + 1e-5));
+        }
+    }
 }
 
 static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
@@ -401,6 +440,17 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     HIP_TRY(hipMemcpyAsync(g->d_raydir.p, g->raydir.data(), g->raydir.size() * sizeof(float4), hipMemcpyHostToDevice,
                            st));
     HIP_TRY(hipMemcpyAsync(g->d_rayv.p, g->rayv.data(), g->rayv.size() * sizeof(float2), hipMemcpyHostToDevice, st));
+    if (!g->raynorm.empty()) {
+        HIP_TRY(g->d_raynorm.alloc(g->raynorm.size() * sizeof(float4)));
+        HIP_TRY(g->d_raytrap.alloc(g->raytrap.size() * sizeof(float4)));
+        HIP_TRY(g->d_kspan.alloc(g->kspan.size() * sizeof(float)));
+        HIP_TRY(hipMemcpyAsync(g->d_raynorm.p, g->raynorm.data(), g->raynorm.size() * sizeof(float4),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(g->d_raytrap.p, g->raytrap.data(), g->raytrap.size() * sizeof(float4),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(g->d_kspan.p, g->kspan.data(), g->kspan.size() * sizeof(float), hipMemcpyHostToDevice,
+                               st));
+    }
     HIP_TRY(hipMemcpyAsync(g->d_cs.p, cs.data(), cs.size() * sizeof(float2), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(g->d_pairs.p, g->pairs.data(), g->pairs.size() * sizeof(PairInfo), hipMemcpyHostToDevice,
                            st));
@@ -438,6 +488,9 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.raydir = g->d_raydir.as<float4>();
     G.rayv = g->d_rayv.as<float2>();
     G.fp_chunk = 3;
+    G.raynorm = g->raynorm.empty() ? nullptr : g->d_raynorm.as<float4>();
+    G.raytrap = g->raytrap.empty() ? nullptr : g->d_raytrap.as<float4>();
+    G.kspan = g->kspan.empty() ? nullptr : g->d_kspan.as<float>();
     return BSGD_OK;
 }
 

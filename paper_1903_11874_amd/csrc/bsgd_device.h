@@ -74,6 +74,15 @@ struct DevGeom {
     const float2* rayv;        // [nv]: 1/v, v^2 (cone only)
     int32_t fp_chunk;          // views per workgroup of the LDS forward projector (tuning)
     int32_t pad_;
+    // 2D chord tables: per (view, pixel) the unit normal (nx, ny) of the ray, xi with
+    // n . p = lambda xi for the ray's anchor point p, and the trapezoid of the chord
+    // length through one voxel as a function of the signed distance of the voxel
+    // centre from the ray: plateau half-width w1, support half-width w2, plateau
+    // length lmax and flank slope lmax / (w2 - w1). Per view: kspan, the candidate
+    // half-range in pixels times the voxel depth (fan) or in pixels (parallel).
+    const float4* raynorm;     // [n_views][nu]: nx, ny, xi, unused
+    const float4* raytrap;     // [n_views][nu]: w1, w2, lmax, slope
+    const float* kspan;        // [n_views]
 };
 
 // Sub-detector s covers u in [k0, k1), v in [l0, l1).
@@ -255,6 +264,15 @@ __device__ __forceinline__ float voxel_dt(const Ray& R, const int (&ix)[3], cons
         }
     }
     return fmaxf(tx - te, 0.0f);
+}
+
+// Exact length of a line through an axis-aligned rectangle (2D voxel) as a function
+// of the signed distance delta of the rectangle centre from the line: lmax on the
+// plateau |delta| <= w1, falling linearly to 0 at |delta| = w2 (a trapezoid).
+__device__ __forceinline__ float chord_2d(float delta, const float4& trap)
+{
+    const float a = fabsf(delta);
+    return fminf(trap.z, fmaxf(0.0f, (trap.y - a) * trap.w));
 }
 
 // SplitMix64 output function and the counter-based draws (same definition as the

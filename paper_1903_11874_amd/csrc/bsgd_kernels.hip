@@ -171,6 +171,42 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float
     return acc;
 }
 
+// 2D back projection of one view into one voxel with the closed-form chord: the
+// candidate rays are those whose pixel lies within kspan / depth of the projection
+// of the voxel centre; each contributes chord_2d(delta) * r.
+template <class Anchor>
+__device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, float c, float s, const Anchor& P,
+                                                  const int (&li)[3], const float (&h)[3], const float (&vs)[3],
+                                                  int k0, int k1, const float* __restrict__ rview)
+{
+    const float qx = plane_pos(li[0], vs[0], h[0]) + 0.5f * vs[0];
+    const float qy = plane_pos(li[1], vs[1], h[1]) + 0.5f * vs[1];
+    const float w = fmaf(qy, c, -(qx * s)) + P.cu;  // lateral coordinate of the voxel centre
+    const float ku = 0.5f * (float)(G.nu - 1);
+    const float inv_du = __builtin_amdgcn_rcpf(G.du);
+    float kc, span;
+    if (G.kind == KIND_PARALLEL_2D) {
+        kc = fmaf(w, inv_du, ku);
+        span = G.kspan[view];
+    } else {
+        const float rdep = __builtin_amdgcn_rcpf(P.depth - fmaf(qx, c, qy * s));
+        kc = fmaf(G.sdd * w * rdep, inv_du, ku);
+        span = G.kspan[view] * rdep;
+    }
+    const int klo = max(k0, (int)ceilf(fminf(fmaxf(kc - span - SHADOW_EPS, (float)k0), (float)k1)));
+    const int khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kc + span + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
+    const float4* nrm = G.raynorm + (int64_t)view * G.nu;
+    const float4* trp = G.raytrap + (int64_t)view * G.nu;
+    float acc = 0.0f;
+    for (int k = klo; k <= khi; ++k) {
+        const float4 n = nrm[k];
+        const float lam = fmaf((float)(k - P.kc), P.au, P.bu);
+        const float delta = fmaf(n.x, qx, fmaf(n.y, qy, -(lam * n.z)));
+        acc = fmaf(chord_2d(delta, trp[k]), rview[k], acc);
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------ geometry statistics
 
 // One wave per (view, block) pair: for every sub-detector s, w = sum over its rays
@@ -560,8 +596,12 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
             for (int a = a0 + grp; a < a1; a += BP_SPLIT) {
                 const PairWork W = wb[a];
                 if (W.k1 <= W.k0) continue;
-                acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
-                                          r_sel + (int64_t)a * per_view);
+                if (DIM == 2)
+                    acc += bp_voxel_view_2d(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1,
+                                            r_sel + (int64_t)a * per_view);
+                else
+                    acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
+                                              r_sel + (int64_t)a * per_view);
             }
         }
         part[grp][vl] = acc;
@@ -714,8 +754,11 @@ __global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __rest
             const PairInfo P = G.pairs[(int64_t)v * G.N + j];
             if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
             const float2 cs = G.cs[v];
-            acc += bp_voxel_view<DIM>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
-                                      y + (int64_t)a * per_view);
+            if (DIM == 2)
+                acc += bp_voxel_view_2d(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, y + (int64_t)a * per_view);
+            else
+                acc += bp_voxel_view<DIM>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
+                                          y + (int64_t)a * per_view);
         }
     }
     part[grp][vl] = acc;
