@@ -112,6 +112,8 @@ def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
         t += rng.exponential(1.0 / rate)
         side = int(rng.choice(SERVING_SIDES))
         spec = fan_request_geometry(side)
+        if spec not in server.geoms:
+            log(f"serving: geometry side {side}")
         geom = server.geometry(spec)
         if spec not in mus:
             mus[spec] = 0.5 / (2.0 * lipschitz_gpu(geom, spec.nx * spec.ny, iters=15))
@@ -122,7 +124,9 @@ def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
                             check_every=5))
     torch.cuda.synchronize()
     log(f"serving: {n_requests} requests over {t:.2f} s, sides {sorted(set(r.geometry.nx for r in reqs))}")
+    log("serving: batched run")
     served = server.run(reqs)
+    log("serving: sequential run")
     seq = Server(max_slots=1).run_sequential(reqs)
     same = all(torch.equal(a.x, b.x) for a, b in zip(served, seq))
     st_b, st_s = latency_stats(served), latency_stats(seq)

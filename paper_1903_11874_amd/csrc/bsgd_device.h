@@ -245,6 +245,61 @@ __device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], con
     }
 }
 
+// Forward-projection walk of a 2D ray through one block: returns the sum over the
+// pixels the ray crosses of (parameter length) * value(off), off = iy sy + ix. Entry
+// pixel, first crossing per axis and Siddon order (ties cross x first) as in
+// walk_block. The m-th later crossing of an axis is fmaf(m, v |inv|, t0) from that
+// axis' first crossing t0: one FMA per axis and step, with an error relative to the
+// chord rather than to |inv| (an affine form in the plane index would cancel badly
+// for near-axis rays). No bounds tests: the walk ends at the slab exit thi. A crossing
+// rounded to just below thi can step one pixel past the block; the offset is clamped
+// into the block, and that pixel's length is a few ulps of t.
+template <class Load>
+__device__ __forceinline__ float walk_2d_sum(const Ray& R, const int (&nb)[3], const float (&h)[3],
+                                             const float (&vs)[3], int sy, Load&& load)
+{
+    float tlo = -INFINITY, thi = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const float X0 = -h[a];
+        const float Xn = plane_pos(nb[a], vs[a], h[a]);
+        if (!axis_fixed(R.inv[a])) {
+            const float t0 = (X0 - R.p[a]) * R.inv[a];
+            const float t1 = (Xn - R.p[a]) * R.inv[a];
+            tlo = fmaxf(tlo, fminf(t0, t1));
+            thi = fminf(thi, fmaxf(t0, t1));
+        } else if (!(X0 <= R.p[a] && R.p[a] < Xn)) {
+            return 0.0f;
+        }
+    }
+    if (!(tlo < thi)) return 0.0f;
+    int ix, iy, sx, sy_;
+    float tx0, ty0;
+    walk_axis_init(R, 0, nb[0], h[0], vs[0], tlo, ix, sx, tx0);
+    walk_axis_init(R, 1, nb[1], h[1], vs[1], tlo, iy, sy_, ty0);
+    const float ax = axis_fixed(R.inv[0]) ? 0.0f : vs[0] * fabsf(R.inv[0]);
+    const float ay = axis_fixed(R.inv[1]) ? 0.0f : vs[1] * fabsf(R.inv[1]);
+    float mx = 0.0f, my = 0.0f, tx = tx0, ty = ty0;
+    const int dox = sx, doy = sy_ * sy;
+    const unsigned last = (unsigned)((nb[1] - 1) * sy + nb[0] - 1);
+    int off = iy * sy + ix;
+    float t = tlo, acc = 0.0f;
+    const int max_steps = nb[0] + nb[1] + 2;
+    for (int it = 0; it < max_steps; ++it) {
+        const bool cx = tx <= ty;
+        const float tm = fminf(fminf(tx, ty), thi);
+        acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
+        if (tm >= thi) break;
+        t = tm;
+        off += cx ? dox : doy;
+        mx += cx ? 1.0f : 0.0f;
+        my += cx ? 0.0f : 1.0f;
+        tx = fmaf(mx, ax, tx0);
+        ty = fmaf(my, ay, ty0);
+    }
+    return acc;
+}
+
 // Length parameter of ray R inside block-local voxel (ix, iy, iz): the slab test
 // with the same plane formula as walk_block. Returns dt (0 when the ray misses).
 template <int DIM>

@@ -95,6 +95,7 @@ __device__ __forceinline__ float fp_ray_block(const DevGeom& G, int view, float 
     int nb[3];
     float h[3], vs[3];
     block_dims(G, B, nb, h, vs);
+    if (DIM == 2) return walk_2d_sum(R, nb, h, vs, (int)sy, [&](unsigned off) { return xb[off]; }) * R.len;
     float acc = 0.0f;
     walk_block<DIM>(R, nb, h, vs, (int)sy, (int)sz, [&](int off, float dt) { acc = fmaf(dt, xb[off], acc); });
     return acc * R.len;
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __re
 }
 
 constexpr int FP_MAX_CHUNK = 16;
-constexpr int FP_LDS_MAX_FLOATS = 16384;  // blocks up to 64 KB are staged in LDS
+constexpr int FP_LDS_MAX_FLOATS = 16384;  // block copies up to 64 KB are staged in LDS; larger blocks read x from global memory
 
 // Workgroup per (view chunk, block slot): the block's image tile is copied to LDS
 // once and every ray of the chunk's pairs walks it there. Work items are the rays
@@ -399,12 +400,19 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
     const PairWork* wb = work + (int64_t)b * L.maxv + a_begin;
     if (threadIdx.x < nch) sh.pw[threadIdx.x] = wb[threadIdx.x];
     const BlockInfo B = G.blocks[blocks_sel[b]];
-    const int plane = B.nbx * B.nby;
-    const int nvox_b = plane * B.nbz;
+    // 2D rows are padded by one float: at a given step, rays one pixel apart sit one
+    // row apart, and an unpadded stride of nbx floats maps them to one LDS bank.
+    const int rs = B.nbx + (DIM == 2 ? 1 : 0);
+    const int plane = rs * B.nby;
+    const int nvox_b = B.nbx * B.nby * B.nbz;
     for (int i = threadIdx.x; i < nvox_b; i += WG) {
-        const int ix = i % B.nbx, iy = (i / B.nbx) % B.nby, iz = i / plane;
-        xs[i] = x[((int64_t)(B.z0 + iz) * G.ny + (B.y0 + iy)) * (int64_t)G.nx + (B.x0 + ix)];
+        const int ix = i % B.nbx, iy = (i / B.nbx) % B.nby, iz = i / (B.nbx * B.nby);
+        xs[iz * plane + iy * rs + ix] = x[((int64_t)(B.z0 + iz) * G.ny + (B.y0 + iy)) * (int64_t)G.nx + (B.x0 + ix)];
     }
+    // the walk may step one pixel past an x face with a length of a few ulps; that
+    // read lands in the padding column, which must hold a finite value
+    if (DIM == 2)
+        for (int iy = threadIdx.x; iy < B.nby; iy += WG) xs[iy * rs + B.nbx] = 0.0f;
     __syncthreads();
     if (threadIdx.x == 0) {
         int off = 0;
@@ -431,7 +439,7 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
             k = W.k0 + (r - (l - W.l0) * wk);
         }
         z[W.zbase + (int64_t)l * W.zw + k] =
-            fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xs, (int64_t)B.nbx, (int64_t)plane);
+            fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xs, (int64_t)rs, (int64_t)plane);
     }
 }
 
@@ -936,19 +944,21 @@ hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, in
     return hipGetLastError();
 }
 
-static int max_block_voxels(const DevGeom& G)
+// Floats of the largest block's LDS copy in the forward projector (2D rows padded).
+static int fp_tile_floats(const DevGeom& G)
 {
-    return ((G.nx + G.bx - 1) / G.bx) * ((G.ny + G.by - 1) / G.by) * ((G.nz + G.bz - 1) / G.bz);
+    const int nbx = (G.nx + G.bx - 1) / G.bx + (G.dim == 2 ? 1 : 0);
+    return nbx * ((G.ny + G.by - 1) / G.by) * ((G.nz + G.bz - 1) / G.bz);
 }
 
 hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,
                            const float* x, float* z, hipStream_t st)
 {
-    const int maxvox = max_block_voxels(G);
-    if (maxvox <= FP_LDS_MAX_FLOATS) {
+    const int tile = fp_tile_floats(G);
+    if (tile <= FP_LDS_MAX_FLOATS) {
         const int chunk = std::max(1, std::min(FP_MAX_CHUNK, G.fp_chunk));
         const unsigned gx = (unsigned)((L.maxv + chunk - 1) / chunk);
-        const size_t lds = (size_t)maxvox * sizeof(float);
+        const size_t lds = (size_t)tile * sizeof(float);
         if (G.dim == 3)
             hipLaunchKernelGGL(k_fp_pairs_lds<3>, dim3(gx, L.B), dim3(WG), lds, st, G, work_it, L, blocks_sel, x, z,
                                chunk);
@@ -968,8 +978,8 @@ hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayou
 
 size_t fp_lds_bytes_for(const DevGeom& G)
 {
-    const int maxvox = max_block_voxels(G);
-    return maxvox <= FP_LDS_MAX_FLOATS ? (size_t)maxvox * sizeof(float) : 0;
+    const int tile = fp_tile_floats(G);
+    return tile <= FP_LDS_MAX_FLOATS ? (size_t)tile * sizeof(float) : 0;
 }
 
 size_t resid_lds_bytes_for(const DevGeom& G) { return resid_lds_bytes(G.N, RES_WG); }
@@ -980,7 +990,7 @@ void batch_grids(BatchEntry& e)
 {
     const DevGeom& G = e.G;
     const SchedLayout& L = e.L;
-    if (max_block_voxels(G) <= FP_LDS_MAX_FLOATS) {
+    if (fp_tile_floats(G) <= FP_LDS_MAX_FLOATS) {
         e.fp_lds = 1;
         e.fp_chunk = std::max(1, std::min(FP_MAX_CHUNK, G.fp_chunk));
         e.gx[0] = (L.maxv + e.fp_chunk - 1) / e.fp_chunk;
