@@ -148,6 +148,9 @@ def main():
                     help="requests of the continuous-batching serving measurement (0 = skip)")
     ap.add_argument("--serving-tol", type=float, default=1e-3)
     ap.add_argument("--serving-max-epochs", type=int, default=30)
+    ap.add_argument("--tune", default="auto",
+                    help="forward-projector launch shape: 'auto' (autotuner, before the timed region) "
+                         "or 'V,S' (views per workgroup, lanes per ray)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -186,6 +189,15 @@ def main():
     L = lipschitz_gpu(geom, n_vox)
     mu = wl.solver.mu_scale / (2.0 * L)
     log(f"L = {L:.4e}, mu = {mu:.4e}")
+
+    if args.tune == "auto":
+        from paper_1903_11874_amd.tuning import autotune
+        tt = autotune(geom, yd, node_count=64, mu=mu, epochs=2, seed=wl.solver.seed)
+        log("autotune: " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in sorted(tt.items(), key=lambda kv: kv[1])[:4]))
+    else:
+        v_, s_ = (int(t) for t in args.tune.split(","))
+        geom.set_tuning(fp_views_per_group=v_, fp_ray_split=s_)
+    log(f"forward projector shape: {geom.fp_views_per_group} views per workgroup, {geom.fp_ray_split} lanes per ray")
 
     x = torch.zeros(n_vox, dtype=torch.float32, device=dev)
     solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed)
@@ -260,7 +272,8 @@ def main():
         "config": {"workload": "2D fan-beam BSGD-IM 512x512 @0.5 mm, 720 views/360 deg, 768 bins @1 mm, "
                                "SOD 500 SDD 1000, 8x8 blocks, 16 angle subsets, 4 sub-detectors, node count 64",
                    "rows_per_iter": solver.rows_per_iter, "blocks_per_iter": solver.blocks_per_iter,
-                   "iters_per_step": T, "step": "one effective epoch"},
+                   "iters_per_step": T, "step": "one effective epoch",
+                   "fp_views_per_group": geom.fp_views_per_group, "fp_ray_split": geom.fp_ray_split},
         "roofline": roofline,
         "kernels_avg_ms": avg_ms,
         "kernel_launches": {k: n for k, (ms, n) in times.items()},

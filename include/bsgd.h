@@ -124,13 +124,18 @@ typedef enum {
 } bsgd_table;
 bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* out, size_t bytes);
 
-/* Launch-shape tuning of a geometry (does not change any result). fp_views_per_group:
- * views whose rays one workgroup of the LDS-staged forward projector walks, in [1, 16]
- * (default 3). Solvers read it at each launch; a solver that already captured its
- * epoch graph keeps the shape it captured. */
+/* Launch-shape tuning of a geometry. fp_views_per_group: views whose rays one
+ * workgroup of the LDS-staged forward projector walks, in [1, 16] (default 3); it
+ * does not change any result. fp_ray_split: lanes that share one ray of a 2D forward
+ * projection through a block, 1, 2 or 4 (default 2): the chord is cut into that many
+ * equal parameter segments, walked in parallel and summed in a fixed order, so
+ * results depend on it only through FP32 rounding and are reproducible for a given
+ * value (3D rays are never split). Solvers read both at each launch; a solver that
+ * already captured its epoch graph keeps the shape it captured. reserved must be 0. */
 typedef struct {
     int32_t fp_views_per_group;
-    int32_t reserved[7];
+    int32_t fp_ray_split;
+    int32_t reserved[6];
 } bsgd_tuning;
 bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* geom, const bsgd_tuning* tuning);
 bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* geom, bsgd_tuning* tuning);

@@ -67,7 +67,8 @@ class Options(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("fp_views_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("fp_views_per_group", ctypes.c_int32), ("fp_ray_split", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 EXPORTED = (
@@ -201,17 +202,35 @@ class Geometry:
         except Exception:
             pass
 
-    @property
-    def fp_views_per_group(self) -> int:
+    def _get_tuning(self) -> Tuning:
         t = Tuning()
         _check(load_library().bsgd_geometry_get_tuning(self._h, ctypes.byref(t)))
-        return t.fp_views_per_group
+        return t
+
+    def set_tuning(self, fp_views_per_group: Optional[int] = None, fp_ray_split: Optional[int] = None):
+        """Launch shape of the forward projector (bsgd_geometry_set_tuning)."""
+        t = self._get_tuning()
+        if fp_views_per_group is not None:
+            t.fp_views_per_group = int(fp_views_per_group)
+        if fp_ray_split is not None:
+            t.fp_ray_split = int(fp_ray_split)
+        _check(load_library().bsgd_geometry_set_tuning(self._h, ctypes.byref(t)))
+
+    @property
+    def fp_views_per_group(self) -> int:
+        return self._get_tuning().fp_views_per_group
 
     @fp_views_per_group.setter
     def fp_views_per_group(self, value: int):
-        t = Tuning()
-        t.fp_views_per_group = int(value)
-        _check(load_library().bsgd_geometry_set_tuning(self._h, ctypes.byref(t)))
+        self.set_tuning(fp_views_per_group=value)
+
+    @property
+    def fp_ray_split(self) -> int:
+        return self._get_tuning().fp_ray_split
+
+    @fp_ray_split.setter
+    def fp_ray_split(self, value: int):
+        self.set_tuning(fp_ray_split=value)
 
     def table(self, name: str) -> np.ndarray:
         g = self.spec

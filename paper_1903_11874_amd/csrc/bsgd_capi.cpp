@@ -488,6 +488,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.raydir = g->d_raydir.as<float4>();
     G.rayv = g->d_rayv.as<float2>();
     G.fp_chunk = 3;
+    G.fp_split = 2;
     G.raynorm = g->raynorm.empty() ? nullptr : g->d_raynorm.as<float4>();
     G.raytrap = g->raytrap.empty() ? nullptr : g->d_raytrap.as<float4>();
     G.kspan = g->kspan.empty() ? nullptr : g->d_kspan.as<float>();
@@ -637,7 +638,12 @@ extern "C" bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* g, const bsgd_tun
     if (!g || !t) return fail(BSGD_E_INVALID_ARG, "NULL argument");
     if (t->fp_views_per_group < 1 || t->fp_views_per_group > FP_CHUNK_MAX)
         return fail(BSGD_E_INVALID_ARG, "fp_views_per_group must be in [1, %d]", FP_CHUNK_MAX);
+    if (t->fp_ray_split != 1 && t->fp_ray_split != 2 && t->fp_ray_split != 4)
+        return fail(BSGD_E_INVALID_ARG, "fp_ray_split must be 1, 2 or 4");
+    for (int i = 0; i < 6; ++i)
+        if (t->reserved[i] != 0) return fail(BSGD_E_INVALID_ARG, "reserved tuning fields must be 0");
     g->dg.fp_chunk = t->fp_views_per_group;
+    g->dg.fp_split = t->fp_ray_split;
     return BSGD_OK;
 }
 
@@ -646,6 +652,7 @@ extern "C" bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* g, bsgd_tun
     if (!g || !t) return fail(BSGD_E_INVALID_ARG, "NULL argument");
     std::memset(t, 0, sizeof *t);
     t->fp_views_per_group = g->dg.fp_chunk;
+    t->fp_ray_split = g->dg.fp_split;
     return BSGD_OK;
 }
 

@@ -73,6 +73,7 @@ struct DevGeom {
     const float4* raydir;      // [n_views][nu]: 1/a, 1/b, |(a,b)|^2 (cone) or |d| (2D), unused
     const float2* rayv;        // [nv]: 1/v, v^2 (cone only)
     int32_t fp_chunk;          // views per workgroup of the LDS forward projector (tuning)
+    int32_t fp_split;          // lanes per 2D ray in the LDS forward projector: 1, 2 or 4 (tuning)
     int32_t pad_;
     // 2D chord tables: per (view, pixel) the unit normal (nx, ny) of the ray, xi with
     // n . p = lambda xi for the ray's anchor point p, and the trapezoid of the chord
@@ -245,20 +246,13 @@ __device__ __forceinline__ void walk_block(const Ray& R, const int (&nb)[3], con
     }
 }
 
-// Forward-projection walk of a 2D ray through one block: returns the sum over the
-// pixels the ray crosses of (parameter length) * value(off), off = iy sy + ix. Entry
-// pixel, first crossing per axis and Siddon order (ties cross x first) as in
-// walk_block. The m-th later crossing of an axis is fmaf(m, v |inv|, t0) from that
-// axis' first crossing t0: one FMA per axis and step, with an error relative to the
-// chord rather than to |inv| (an affine form in the plane index would cancel badly
-// for near-axis rays). No bounds tests: the walk ends at the slab exit thi. A crossing
-// rounded to just below thi can step one pixel past the block; the offset is clamped
-// into the block, and that pixel's length is a few ulps of t.
-template <class Load>
-__device__ __forceinline__ float walk_2d_sum(const Ray& R, const int (&nb)[3], const float (&h)[3],
-                                             const float (&vs)[3], int sy, Load&& load)
+// Parameter interval [tlo, thi) of a 2D ray inside a block (same slab formula as
+// walk_block); false when the ray misses the block.
+__device__ __forceinline__ bool slab_2d(const Ray& R, const int (&nb)[3], const float (&h)[3], const float (&vs)[3],
+                                        float& tlo, float& thi)
 {
-    float tlo = -INFINITY, thi = INFINITY;
+    tlo = -INFINITY;
+    thi = INFINITY;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const float X0 = -h[a];
@@ -269,27 +263,44 @@ __device__ __forceinline__ float walk_2d_sum(const Ray& R, const int (&nb)[3], c
             tlo = fmaxf(tlo, fminf(t0, t1));
             thi = fminf(thi, fmaxf(t0, t1));
         } else if (!(X0 <= R.p[a] && R.p[a] < Xn)) {
-            return 0.0f;
+            return false;
         }
     }
-    if (!(tlo < thi)) return 0.0f;
+    return tlo < thi;
+}
+
+// Forward-projection walk of a 2D ray over the parameter range [t0, t1) inside one
+// block (t0, t1 within the slab): returns the sum over the pixels crossed of
+// (parameter length) * value(off), off = iy sy + ix. The starting pixel, the first
+// crossing per axis and the Siddon order (ties cross x first) are those of
+// walk_block. The m-th later crossing of an axis is fmaf(m, v |inv|, t_first): one
+// FMA per axis and step, with an error relative to the chord rather than to |inv|
+// (an affine form in the plane index would cancel badly for near-axis rays). No
+// bounds tests: the walk ends at t1. A crossing rounded to just below the block's
+// exit can step one pixel past the block; the offset is clamped into the block, and
+// that pixel's length is a few ulps of t.
+template <class Load>
+__device__ __forceinline__ float walk_2d_range(const Ray& R, const int (&nb)[3], const float (&h)[3],
+                                               const float (&vs)[3], int sy, float t0, float t1, Load&& load)
+{
+    if (!(t0 < t1)) return 0.0f;
     int ix, iy, sx, sy_;
     float tx0, ty0;
-    walk_axis_init(R, 0, nb[0], h[0], vs[0], tlo, ix, sx, tx0);
-    walk_axis_init(R, 1, nb[1], h[1], vs[1], tlo, iy, sy_, ty0);
+    walk_axis_init(R, 0, nb[0], h[0], vs[0], t0, ix, sx, tx0);
+    walk_axis_init(R, 1, nb[1], h[1], vs[1], t0, iy, sy_, ty0);
     const float ax = axis_fixed(R.inv[0]) ? 0.0f : vs[0] * fabsf(R.inv[0]);
     const float ay = axis_fixed(R.inv[1]) ? 0.0f : vs[1] * fabsf(R.inv[1]);
     float mx = 0.0f, my = 0.0f, tx = tx0, ty = ty0;
     const int dox = sx, doy = sy_ * sy;
     const unsigned last = (unsigned)((nb[1] - 1) * sy + nb[0] - 1);
     int off = iy * sy + ix;
-    float t = tlo, acc = 0.0f;
+    float t = t0, acc = 0.0f;
     const int max_steps = nb[0] + nb[1] + 2;
     for (int it = 0; it < max_steps; ++it) {
         const bool cx = tx <= ty;
-        const float tm = fminf(fminf(tx, ty), thi);
+        const float tm = fminf(fminf(tx, ty), t1);
         acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
-        if (tm >= thi) break;
+        if (tm >= t1) break;
         t = tm;
         off += cx ? dox : doy;
         mx += cx ? 1.0f : 0.0f;
@@ -298,6 +309,16 @@ __device__ __forceinline__ float walk_2d_sum(const Ray& R, const int (&nb)[3], c
         ty = fmaf(my, ay, ty0);
     }
     return acc;
+}
+
+// Whole chord of a 2D ray through one block.
+template <class Load>
+__device__ __forceinline__ float walk_2d_sum(const Ray& R, const int (&nb)[3], const float (&h)[3],
+                                             const float (&vs)[3], int sy, Load&& load)
+{
+    float tlo, thi;
+    if (!slab_2d(R, nb, h, vs, tlo, thi)) return 0.0f;
+    return walk_2d_range(R, nb, h, vs, sy, tlo, thi, load);
 }
 
 // Length parameter of ray R inside block-local voxel (ix, iy, iz): the slab test

@@ -424,20 +424,44 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
     }
     __syncthreads();
     const int total = sh.off[nch];
+    if (DIM == 2) {
+        // S adjacent lanes per ray, each walking 1/S of the chord's parameter range;
+        // the S partial sums are combined as (s0 + s1) + (s2 + s3), a fixed order.
+        const int lg = G.fp_split >= 4 ? 2 : (G.fp_split >= 2 ? 1 : 0);
+        const int S = 1 << lg;
+        const float invS = 1.0f / (float)S;
+        int nb[3];
+        float h[3], vs[3];
+        block_dims(G, B, nb, h, vs);
+        for (int item = threadIdx.x; item < (total << lg); item += WG) {
+            const int ray = item >> lg, seg = item & (S - 1);
+            int q = 0;
+            while (sh.off[q + 1] <= ray) ++q;
+            const PairWork& W = sh.pw[q];
+            const int k = W.k0 + (ray - sh.off[q]);
+            Ray R;
+            make_ray<2>(G, W.view, W.c, W.s, W, k, W.l0, R);
+            float acc = 0.0f, tlo, thi;
+            if (slab_2d(R, nb, h, vs, tlo, thi)) {
+                const float span = thi - tlo;
+                const float t0 = seg == 0 ? tlo : fmaf((float)seg * invS, span, tlo);
+                const float t1 = seg == S - 1 ? thi : fmaf((float)(seg + 1) * invS, span, tlo);
+                acc = walk_2d_range(R, nb, h, vs, rs, t0, t1, [&](unsigned off) { return xs[off]; });
+            }
+            if (S >= 2) acc += __shfl_xor(acc, 1, 64);
+            if (S >= 4) acc += __shfl_xor(acc, 2, 64);
+            if (seg == 0) z[W.zbase + (int64_t)W.l0 * W.zw + k] = acc * R.len;
+        }
+        return;
+    }
     for (int item = threadIdx.x; item < total; item += WG) {
         int q = 0;
         while (sh.off[q + 1] <= item) ++q;
         const PairWork& W = sh.pw[q];
         const int r = item - sh.off[q];
-        int k, l;
-        if (DIM == 2) {
-            k = W.k0 + r;
-            l = W.l0;
-        } else {
-            const int wk = W.k1 - W.k0;
-            l = W.l0 + r / wk;
-            k = W.k0 + (r - (l - W.l0) * wk);
-        }
+        const int wk = W.k1 - W.k0;
+        const int l = W.l0 + r / wk;
+        const int k = W.k0 + (r - (l - W.l0) * wk);
         z[W.zbase + (int64_t)l * W.zw + k] =
             fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xs, (int64_t)rs, (int64_t)plane);
     }

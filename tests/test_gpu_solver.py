@@ -263,15 +263,20 @@ def test_autotuner_shapes_do_not_change_results():
     mu = _mu(A, 0.3)
     geom = Geometry(g)
     yd = torch.tensor(y32, device=dev)
-    timings = autotune(geom, yd, node_count=9, mu=mu, candidates=(1, 2, 5, 16), epochs=1)
-    assert set(timings) == {1, 2, 5, 16} and geom.fp_views_per_group in timings
-    outs = []
-    for c in (1, 4, 16):
-        geom.fp_views_per_group = c
-        x = torch.zeros(A.shape[1], device=dev)
-        Solver(geom, yd, x, node_count=9, mu=mu, seed=3, eager=True).step(20)
-        outs.append(x)
-    assert all(torch.equal(outs[0], o) for o in outs[1:])
+    timings = autotune(geom, yd, node_count=9, mu=mu, views=(1, 2, 5, 16), splits=(1, 4), epochs=1)
+    assert set(timings) == {(c, s) for c in (1, 2, 5, 16) for s in (1, 4)}
+    assert (geom.fp_views_per_group, geom.fp_ray_split) in timings
+    outs = {}
+    for sp in (1, 2, 4):
+        for c in (1, 4, 16):
+            geom.set_tuning(fp_views_per_group=c, fp_ray_split=sp)
+            x = torch.zeros(A.shape[1], device=dev)
+            Solver(geom, yd, x, node_count=9, mu=mu, seed=3, eager=True).step(20)
+            outs[(c, sp)] = x
+    # views per workgroup never changes a bit; the ray split only the FP32 rounding
+    for sp in (1, 2, 4):
+        assert all(torch.equal(outs[(1, sp)], outs[(c, sp)]) for c in (4, 16))
+        assert rel_l2(outs[(1, sp)].double().cpu().numpy(), outs[(1, 1)].double().cpu().numpy()) < 1e-5
 
 
 @pytest.mark.parametrize("scale,eager", [(2.0, True), (0.05, False)])

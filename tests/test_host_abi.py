@@ -37,10 +37,11 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header():
     import subprocess
     import tempfile
-    from paper_1903_11874_amd.bsgd import GeometryDesc, Options, GeometryInfo
-    src = '#include "%s"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%%zu %%zu %%zu %%zu %%zu", ' \
+    from paper_1903_11874_amd.bsgd import GeometryDesc, Options, GeometryInfo, Tuning
+    src = '#include "%s"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu", ' \
           'sizeof(bsgd_geometry_desc), sizeof(bsgd_options), sizeof(bsgd_geometry_info), ' \
-          'offsetof(bsgd_geometry_desc, im_table), offsetof(bsgd_options, tol));return 0;}\n' % HEADER
+          'offsetof(bsgd_geometry_desc, im_table), offsetof(bsgd_options, tol), sizeof(bsgd_tuning), ' \
+          'offsetof(bsgd_tuning, fp_ray_split));return 0;}\n' % HEADER
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -48,7 +49,7 @@ def test_struct_layouts_match_header():
         out = subprocess.check_output([os.path.join(d, "s")]).decode().split()
     assert [int(v) for v in out] == [ctypes.sizeof(GeometryDesc), ctypes.sizeof(Options),
                                       ctypes.sizeof(GeometryInfo), GeometryDesc.im_table.offset,
-                                      Options.tol.offset]
+                                      Options.tol.offset, ctypes.sizeof(Tuning), Tuning.fp_ray_split.offset]
 
 
 def _desc(**kw):
