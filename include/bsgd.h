@@ -127,7 +127,7 @@ bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* 
 /* Launch-shape tuning of a geometry. fp_views_per_group: views whose rays one
  * workgroup of the LDS-staged forward projector walks, in [1, 16] (default 3); it
  * does not change any result. fp_ray_split: lanes that share one ray of a 2D forward
- * projection through a block, 1, 2 or 4 (default 2): the chord is cut into that many
+ * projection through a block, 1, 2 or 4 (default 1): the chord is cut into that many
  * equal parameter segments, walked in parallel and summed in a fixed order, so
  * results depend on it only through FP32 rounding and are reproducible for a given
  * value (3D rays are never split). Solvers read both at each launch; a solver that

@@ -488,7 +488,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.raydir = g->d_raydir.as<float4>();
     G.rayv = g->d_rayv.as<float2>();
     G.fp_chunk = 3;
-    G.fp_split = 2;
+    G.fp_split = 1;
     G.raynorm = g->raynorm.empty() ? nullptr : g->d_raynorm.as<float4>();
     G.raytrap = g->raytrap.empty() ? nullptr : g->d_raytrap.as<float4>();
     G.kspan = g->kspan.empty() ? nullptr : g->d_kspan.as<float>();

@@ -311,6 +311,62 @@ __device__ __forceinline__ float walk_2d_range(const Ray& R, const int (&nb)[3],
     return acc;
 }
 
+// Largest int over the 64 lanes of a wave (all lanes must be active).
+__device__ __forceinline__ int wave_max_int(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// walk_2d_range with a wave-uniform trip count, for callers whose 64 lanes are all
+// active: each lane bounds its pixel count by the plane crossings its parameter range
+// can hold, the wave loops to the largest bound on a scalar counter, and a lane past
+// its end adds zero-length steps (tm = t = t1). No per-lane exit, so no exec-mask
+// bookkeeping per step. live = false gives 0.
+template <class Load>
+__device__ __forceinline__ float walk_2d_range_wave(const Ray& R, const int (&nb)[3], const float (&h)[3],
+                                                    const float (&vs)[3], int sy, float t0, float t1, bool live,
+                                                    Load&& load)
+{
+    live = live && (t0 < t1);
+    int ix = 0, iy = 0, sx = 0, sy_ = 0;
+    float tx0 = INFINITY, ty0 = INFINITY;
+    if (live) {
+        walk_axis_init(R, 0, nb[0], h[0], vs[0], t0, ix, sx, tx0);
+        walk_axis_init(R, 1, nb[1], h[1], vs[1], t0, iy, sy_, ty0);
+    } else {
+        t0 = t1 = 0.0f;
+    }
+    const float ax = (live && !axis_fixed(R.inv[0])) ? vs[0] * fabsf(R.inv[0]) : 0.0f;
+    const float ay = (live && !axis_fixed(R.inv[1])) ? vs[1] * fabsf(R.inv[1]) : 0.0f;
+    // pixels visited <= crossings of each axis in (t0, t1) + 1, plus one step past
+    // the exit by rounding; fminf also maps inf/NaN (fixed axis, empty range) away
+    const float cap = (float)(nb[0] + nb[1] + 2);
+    const float span = t1 - t0;
+    const float nxf = ax > 0.0f ? fminf(floorf(span * __builtin_amdgcn_rcpf(ax)), cap) : 0.0f;
+    const float nyf = ay > 0.0f ? fminf(floorf(span * __builtin_amdgcn_rcpf(ay)), cap) : 0.0f;
+    const int n = live ? (int)fminf(nxf + nyf + 4.0f, cap) : 0;
+    const int n_wave = wave_max_int(n);
+    float mx = 0.0f, my = 0.0f, tx = tx0, ty = ty0;
+    const int dox = sx, doy = sy_ * sy;
+    const unsigned last = (unsigned)((nb[1] - 1) * sy + nb[0] - 1);
+    int off = iy * sy + ix;
+    float t = t0, acc = 0.0f;
+    for (int it = 0; it < n_wave; ++it) {
+        const bool cx = tx <= ty;
+        const float tm = fminf(fminf(tx, ty), t1);
+        acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
+        t = tm;
+        off += cx ? dox : doy;
+        mx += cx ? 1.0f : 0.0f;
+        my += cx ? 0.0f : 1.0f;
+        tx = fmaf(mx, ax, tx0);
+        ty = fmaf(my, ay, ty0);
+    }
+    return acc;
+}
+
 // Whole chord of a 2D ray through one block.
 template <class Load>
 __device__ __forceinline__ float walk_2d_sum(const Ray& R, const int (&nb)[3], const float (&h)[3],

@@ -433,24 +433,29 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
         int nb[3];
         float h[3], vs[3];
         block_dims(G, B, nb, h, vs);
-        for (int item = threadIdx.x; item < (total << lg); item += WG) {
-            const int ray = item >> lg, seg = item & (S - 1);
+        // every thread runs every round (items past the end are dead lanes), so the
+        // walk's wave-uniform trip count and the shuffles see all 64 lanes
+        const int n_items = total << lg;
+        const int rounds = (n_items + WG - 1) / WG;
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int item = rd * WG + (int)threadIdx.x;
+            const bool on = item < n_items;
+            const int ray = on ? (item >> lg) : 0, seg = item & (S - 1);
             int q = 0;
-            while (sh.off[q + 1] <= ray) ++q;
+            while (q < nch - 1 && sh.off[q + 1] <= ray) ++q;
             const PairWork& W = sh.pw[q];
             const int k = W.k0 + (ray - sh.off[q]);
             Ray R;
             make_ray<2>(G, W.view, W.c, W.s, W, k, W.l0, R);
-            float acc = 0.0f, tlo, thi;
-            if (slab_2d(R, nb, h, vs, tlo, thi)) {
-                const float span = thi - tlo;
-                const float t0 = seg == 0 ? tlo : fmaf((float)seg * invS, span, tlo);
-                const float t1 = seg == S - 1 ? thi : fmaf((float)(seg + 1) * invS, span, tlo);
-                acc = walk_2d_range(R, nb, h, vs, rs, t0, t1, [&](unsigned off) { return xs[off]; });
-            }
+            float tlo = 0.0f, thi = 0.0f;
+            const bool hit = on && slab_2d(R, nb, h, vs, tlo, thi);
+            const float span = thi - tlo;
+            const float t0 = seg == 0 ? tlo : fmaf((float)seg * invS, span, tlo);
+            const float t1 = seg == S - 1 ? thi : fmaf((float)(seg + 1) * invS, span, tlo);
+            float acc = walk_2d_range_wave(R, nb, h, vs, rs, t0, t1, hit, [&](unsigned off) { return xs[off]; });
             if (S >= 2) acc += __shfl_xor(acc, 1, 64);
             if (S >= 4) acc += __shfl_xor(acc, 2, 64);
-            if (seg == 0) z[W.zbase + (int64_t)W.l0 * W.zw + k] = acc * R.len;
+            if (on && seg == 0) z[W.zbase + (int64_t)W.l0 * W.zw + k] = acc * R.len;
         }
         return;
     }
