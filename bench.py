@@ -135,7 +135,9 @@ def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
             "batched": st_b, "sequential": st_s,
             "solves_per_s_ratio": st_b["solves_per_s"] / st_s["solves_per_s"],
             "identical_results": bool(same),
-            "max_active": max(n for _, n in server.log) if server.log else 0}
+            "max_active": max(e[1] for e in server.log) if server.log else 0,
+            "ticks": len(server.log),
+            "enqueue_s": sum(e[2] for e in server.log), "check_and_wait_s": sum(e[3] for e in server.log)}
 
 
 def main():

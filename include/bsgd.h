@@ -225,6 +225,16 @@ bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_norm_out);
  * Errors mark every solver of the batch as failed. */
 bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, int32_t n_iters, void* stream);
 
+/* Stopping statistic of bsgd_solve for several solves at once: out[i] =
+ * ||A^T (y - A x_i)|| of solver i's current image (the normal-equation residual; the
+ * least-squares problem of Sec. I is solved where it vanishes), divided by
+ * ||A^T y|| when `relative` is non-zero (computed on the first relative call and
+ * kept). Everything is enqueued on `stream` (every solver must have been created on
+ * it) and the call synchronises once. Each solver allocates n_rays + n_voxels floats
+ * of scratch on its first call. out is host memory of n doubles. */
+bsgd_status bsgd_normal_residual(bsgd_solver* const* solvers, int32_t n, int32_t relative, double* out,
+                                 void* stream);
+
 /* Current step length and its value after each Algorithm 3 check (history[0..cap)). */
 bsgd_status bsgd_solver_step_length(const bsgd_solver* s, double* mu_now, double* history, int32_t cap,
                                     int32_t* n_history);

@@ -76,7 +76,7 @@ EXPORTED = (
     "bsgd_forward_project", "bsgd_back_project", "bsgd_solver_create", "bsgd_step", "bsgd_solver_counts",
     "bsgd_solver_last_schedule", "bsgd_solver_state", "bsgd_solver_set_profiling", "bsgd_solver_kernel_times",
     "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error", "bsgd_step_batch", "bsgd_geometry_set_tuning",
-    "bsgd_geometry_get_tuning", "bsgd_solver_step_length",
+    "bsgd_geometry_get_tuning", "bsgd_solver_step_length", "bsgd_normal_residual",
 )
 
 _lib = None
@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH):
         "bsgd_geometry_set_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
         "bsgd_geometry_get_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
         "bsgd_solver_step_length": (i32, [P, ctypes.POINTER(ctypes.c_double), P, i32, ctypes.POINTER(i32)]),
+        "bsgd_normal_residual": (i32, [ctypes.POINTER(P), i32, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -385,6 +386,16 @@ def step_batch(solvers, n_iters: int, stream=None):
     """n_iters iterations of every solver with shared launches (bsgd_step_batch)."""
     arr = (ctypes.c_void_p * len(solvers))(*[s._h.value for s in solvers])
     _check(load_library().bsgd_step_batch(arr, len(solvers), int(n_iters), _stream_ptr(stream)))
+
+
+def normal_residual(solvers, relative: bool = True, stream=None):
+    """||A^T (y - A x)|| (divided by ||A^T y|| when relative) of each solver's current
+    image, with one synchronisation (bsgd_normal_residual)."""
+    arr = (ctypes.c_void_p * len(solvers))(*[s._h.value for s in solvers])
+    out = np.zeros(len(solvers), dtype=np.float64)
+    _check(load_library().bsgd_normal_residual(arr, len(solvers), int(bool(relative)),
+                                               out.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+    return out
 
 
 def solve(geom: Geometry, y, x, stream=None, **opts):

@@ -413,7 +413,9 @@ static void build_tables(bsgd_geometry* g)
                 const double w2 = hx * ax + hy * ay, w1 = std::fabs(hx * ax - hy * ay);
                 const double lx = ay > 0 ? d.vx / ay : INFINITY, ly = ax > 0 ? d.vy / ax : INFINITY;
                 const double lmax = std::min(lx, ly);
-                const double slope = w2 > w1 ? lmax / (w2 - w1) : INFINITY;
+                // an axis-aligned ray has a box profile (w1 = w2): a huge finite slope
+                // gives the same chord and keeps (w2 - |delta|) * slope free of inf * 0
+                const double slope = w2 > w1 ? std::min(lmax / (w2 - w1), 1e30) : 1e30;
                 g->raynorm[(size_t)v * d.nu + k] = make_float4((float)nx, (float)ny, (float)xi, 0.0f);
                 g->raytrap[(size_t)v * d.nu + k] = make_float4((float)w1, (float)w2, (float)lmax, (float)slope);
                 span = std::max(span, w2 * len / d.du);
@@ -742,10 +744,10 @@ struct bsgd_solver {
     hipGraphExec_t graph_exec = nullptr;
     DevBuf g_sched, g_work, g_draws;
     // entry table of batched calls led by this solver
-    DevBuf batch_dev;
-    Staging batch_stage;
     // step length on the device (read by the back-projection kernel) and Algorithm 3
     DevBuf mu_dev, eud_cur, eud_prev;
+    DevBuf nr_ty, nr_tg;   // normal-residual scratch (bsgd_normal_residual)
+    double nr_ref = -1.0;  // ||A^T y||, once computed
     float* mu_host = nullptr;
     double mu_cur = 0.0;
     bool auto_mu = false, have_prev_eud = false;
@@ -1216,55 +1218,70 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         bsgd_status stt = prepare_iterations(solvers[i], n_iters, st);
         if (stt != BSGD_OK) return mark_failed(stt);
     }
-    // entry table
-    bsgd_solver* lead = solvers[0];
-    std::vector<BatchEntry> E(n);
-    int wgs[3] = {0, 0, 0};
-    size_t fp_lds = 0, res_lds = 0;
-    for (int i = 0; i < n; ++i) {
-        bsgd_solver* s = solvers[i];
-        BatchEntry& e = E[i];
-        std::memset(&e, 0, sizeof e);
-        e.G = s->g->dg;
-        e.L = s->L;
-        e.sched = s->sched.as<int32_t>();
-        e.work = s->work.as<PairWork>();
-        e.y = s->y;
-        e.x = s->x;
-        e.z = s->z.as<float>();
-        e.ghat = s->ghat.as<float>();
-        e.gsum = s->gsum.as<float>();
-        e.r_sel = s->r_sel.as<float>();
-        e.mu = s->mu_dev.as<float>();
-        e.n_vox = s->g->n_vox;
-        batch_grids(e);
-        const int per[3] = {e.gx[0] * (e.fp_lds ? e.L.B : 1), e.gx[1] * e.L.maxv, e.gx[2] * e.L.B};
-        for (int p = 0; p < 3; ++p) {
-            e.base[p] = wgs[p];
-            wgs[p] += per[p];
+    // launch groups of up to BATCH_GROUP entries (passed as kernel arguments), each
+    // with the LDS-staged forward projections first, sorted by LDS size (the order of
+    // the entries does not affect any solve's arithmetic)
+    std::vector<bsgd_solver*> order(solvers, solvers + n);
+    std::stable_sort(order.begin(), order.end(), [](const bsgd_solver* a, const bsgd_solver* b) {
+        return fp_lds_bytes_for(a->g->dg) > fp_lds_bytes_for(b->g->dg);
+    });
+    struct Group {
+        BatchArgs A;
+        int wgs[3];
+        std::vector<FpLaunchClass> classes;
+        size_t res_lds;
+    };
+    std::vector<Group> groups;
+    for (int g0 = 0; g0 < n; g0 += BATCH_GROUP) {
+        groups.emplace_back();
+        Group& grp = groups.back();
+        std::memset(&grp.A, 0, sizeof grp.A);
+        grp.wgs[0] = grp.wgs[1] = grp.wgs[2] = 0;
+        grp.res_lds = 0;
+        const int m = std::min(BATCH_GROUP, n - g0);
+        for (int i = 0; i < m; ++i) {
+            bsgd_solver* s = order[g0 + i];
+            BatchEntry& e = grp.A.e[i];
+            e.G = s->g->dg;
+            e.L = s->L;
+            e.sched = s->sched.as<int32_t>();
+            e.work = s->work.as<PairWork>();
+            e.y = s->y;
+            e.x = s->x;
+            e.z = s->z.as<float>();
+            e.ghat = s->ghat.as<float>();
+            e.gsum = s->gsum.as<float>();
+            e.r_sel = s->r_sel.as<float>();
+            e.mu = s->mu_dev.as<float>();
+            e.n_vox = s->g->n_vox;
+            batch_grids(e);
+            const int per[3] = {e.gx[0] * (e.fp_lds ? e.L.B : 1), e.gx[1] * e.L.maxv, e.gx[2] * e.L.B};
+            for (int p = 0; p < 3; ++p) {
+                e.base[p] = grp.wgs[p];
+                grp.wgs[p] += per[p];
+            }
+            const size_t lb = e.fp_lds ? fp_lds_bytes_for(e.G) : (size_t)0;
+            if (grp.classes.empty() || grp.classes.back().lds_bytes != lb)
+                grp.classes.push_back({(int)e.base[0], 0, lb});
+            grp.classes.back().wgs += per[0];
+            grp.res_lds = std::max(grp.res_lds, resid_lds_bytes_for(e.G));
         }
-        fp_lds = std::max(fp_lds, e.fp_lds ? fp_lds_bytes_for(e.G) : (size_t)0);
-        res_lds = std::max(res_lds, resid_lds_bytes_for(e.G));
+        grp.A.n = m;
     }
-    const size_t eb = E.size() * sizeof(BatchEntry);
-    hipError_t he = lead->batch_stage.reserve(eb);
-    if (he == hipSuccess && lead->batch_dev.bytes < eb) {
-        he = hipStreamSynchronize(st);
-        if (he == hipSuccess) he = lead->batch_dev.alloc(eb);
-    }
-    if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batch table: %s", hipGetErrorString(he)));
-    std::memcpy(lead->batch_stage.host, E.data(), eb);
-    he = lead->batch_stage.upload(lead->batch_dev.p, eb, st);
-    if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batch table upload: %s", hipGetErrorString(he)));
-    const BatchEntry* dE = lead->batch_dev.as<BatchEntry>();
     for (int it = 0; it < n_iters; ++it) {
-        he = launch_batch_iteration(dE, n, dim, it, wgs, fp_lds, res_lds, st);
-        if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batched launch: %s", hipGetErrorString(he)));
+        for (Group& grp : groups) {
+            grp.A.it = it;
+            hipError_t he = launch_batch_iteration(grp.A, dim, grp.wgs, grp.classes.data(), (int)grp.classes.size(),
+                                                   grp.res_lds, st);
+            if (he != hipSuccess)
+                return mark_failed(fail(BSGD_E_DEVICE, "batched launch: %s", hipGetErrorString(he)));
+        }
         for (int i = 0; i < n; ++i) {
             bsgd_solver* s = solvers[i];
             if (s->o.tv_lambda > 0 && (s->k + it + 1) % s->tv_every == 0) {
-                he = launch_tv_prox(s->g->dg, s->x, (float)(s->mu_cur * s->o.tv_lambda), s->o.tv_inner_iters,
-                                    s->tv_p.as<float>(), s->tv_a.as<float>(), s->tv_b.as<float>(), st);
+                hipError_t he = launch_tv_prox(s->g->dg, s->x, (float)(s->mu_cur * s->o.tv_lambda),
+                                               s->o.tv_inner_iters, s->tv_p.as<float>(), s->tv_a.as<float>(),
+                                               s->tv_b.as<float>(), st);
                 if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "tv: %s", hipGetErrorString(he)));
             }
         }
@@ -1373,6 +1390,52 @@ static bsgd_status normal_residual(const bsgd_geometry* g, const float* y, const
     HIP_TRY(hipMemcpyAsync(host_out, dout, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *out = std::sqrt(*host_out);
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_normal_residual(bsgd_solver* const* solvers, int32_t n, int32_t relative, double* out,
+                                            void* stream)
+{
+    if (!solvers || !out || n < 1 || n > 65536) return fail(BSGD_E_INVALID_ARG, "need 1 <= n <= 65536 solvers and out");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        if (!solvers[i]) return fail(BSGD_E_INVALID_ARG, "solver %d is NULL", i);
+        if (solvers[i]->st != st) return fail(BSGD_E_INVALID_ARG, "solver %d was created on another stream", i);
+    }
+    // norm_out slots: [2] = ||A^T (y - A x)||^2, [3] = ||A^T y||^2 (first relative call)
+    for (int i = 0; i < n; ++i) {
+        bsgd_solver* s = solvers[i];
+        const bsgd_geometry* g = s->g;
+        if (!s->nr_ty.p) {
+            HIP_TRY(s->nr_ty.alloc((size_t)g->n_rays * sizeof(float)));
+            HIP_TRY(s->nr_tg.alloc((size_t)g->n_vox * sizeof(float)));
+        }
+        double* dout = s->norm_out.as<double>();
+        double* part = s->partials.as<double>();
+        float* ty = s->nr_ty.as<float>();
+        float* tg = s->nr_tg.as<float>();
+        const int32_t* views = g->d_all_views.as<int32_t>();
+        int np = 0;
+        if (relative && s->nr_ref < 0.0) {
+            HIP_TRY(launch_fill(tg, 0.0f, g->n_vox, st));
+            HIP_TRY(launch_bp_full(g->dg, views, g->d.n_views, -1, s->y, tg, 1.0f, 0, st));
+            HIP_TRY(launch_sumsq(tg, g->n_vox, part, &np, st));
+            HIP_TRY(launch_sum_partials(part, np, dout + 3, st));
+        }
+        HIP_TRY(launch_fp_full(g->dg, views, g->d.n_views, -1, s->x, ty, 0, st));
+        HIP_TRY(launch_sub(s->y, ty, ty, g->n_rays, st));
+        HIP_TRY(launch_bp_full(g->dg, views, g->d.n_views, -1, ty, tg, 1.0f, 0, st));
+        HIP_TRY(launch_sumsq(tg, g->n_vox, part, &np, st));
+        HIP_TRY(launch_sum_partials(part, np, dout + 2, st));
+        HIP_TRY(hipMemcpyAsync(s->norm_host + 2, dout + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+        bsgd_solver* s = solvers[i];
+        if (relative && s->nr_ref < 0.0) s->nr_ref = std::sqrt(s->norm_host[3]);
+        const double v = std::sqrt(s->norm_host[2]);
+        out[i] = relative ? v / std::max(s->nr_ref, 1e-300) : v;
+    }
     return BSGD_OK;
 }
 

@@ -403,8 +403,9 @@ __device__ __forceinline__ float voxel_dt(const Ray& R, const int (&ix)[3], cons
 // plateau |delta| <= w1, falling linearly to 0 at |delta| = w2 (a trapezoid).
 __device__ __forceinline__ float chord_2d(float delta, const float4& trap)
 {
-    const float a = fabsf(delta);
-    return fminf(trap.z, fmaxf(0.0f, (trap.y - a) * trap.w));
+    // the slope is finite (capped on the host), so the product is never NaN and the
+    // clamp to [0, lmax] is one median-of-three
+    return __builtin_amdgcn_fmed3f((trap.y - fabsf(delta)) * trap.w, 0.0f, trap.z);
 }
 
 // SplitMix64 output function and the counter-based draws (same definition as the

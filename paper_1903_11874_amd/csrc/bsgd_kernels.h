@@ -59,10 +59,28 @@ struct BatchEntry {
 
 // Per-solve grid of each phase (x extent, total workgroups) for a batch entry.
 void batch_grids(BatchEntry& e);
-// Launch one iteration (index `it` into every entry's records) of all entries; the
-// entries must share the dimension; wgs[p] = total workgroups of phase p.
-hipError_t launch_batch_iteration(const BatchEntry* dev_entries, int n, int dim, int it, const int (&wgs)[3],
-                                  size_t fp_lds_bytes, size_t res_lds_bytes, hipStream_t st);
+
+// Entries of one batched launch group, passed by value as the kernel argument (the
+// 4 KB argument segment holds up to BATCH_GROUP entries): pointers read from kernel
+// arguments are known to address global memory, so the shared bodies compile to the
+// same global (not flat) loads and scalar loads as in the single-solve kernels.
+constexpr int BATCH_GROUP = 12;
+struct BatchArgs {
+    BatchEntry e[BATCH_GROUP];
+    int n;    // entries in use
+    int it;   // iteration index into every entry's records
+    int id0;  // workgroup id of this launch's first workgroup (phase 0 classes)
+};
+
+// A contiguous range of phase-0 workgroups whose entries share one LDS size.
+struct FpLaunchClass {
+    int wg0, wgs;
+    size_t lds_bytes;
+};
+// Launch one iteration (A.it) of all entries of A; the entries share the dimension;
+// wgs[p] = total workgroups of phase p over the group.
+hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], const FpLaunchClass* fp_classes,
+                                  int n_fp_classes, size_t res_lds_bytes, hipStream_t st);
 size_t fp_lds_bytes_for(const DevGeom& G);
 size_t resid_lds_bytes_for(const DevGeom& G);
 

@@ -682,7 +682,7 @@ __global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __rest
 // binary search over each entry's first workgroup; the entry's own body then runs
 // exactly as in the single-solve kernels, so a solve's arithmetic does not depend on
 // the batch it runs in.
-__device__ __forceinline__ int find_entry(const BatchEntry* __restrict__ E, int n, int phase, int id)
+__device__ __forceinline__ int find_entry(const BatchEntry* E, int n, int phase, int id)
 {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -694,48 +694,48 @@ __device__ __forceinline__ int find_entry(const BatchEntry* __restrict__ E, int 
 }
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_fp_batch(const BatchEntry* __restrict__ E, int n, int it)
+__global__ __launch_bounds__(WG) void k_fp_batch(const BatchArgs A)
 {
     extern __shared__ float xs[];
     __shared__ FpLds sh;
-    const int id = blockIdx.x;
-    const int e = __builtin_amdgcn_readfirstlane(find_entry(E, n, 0, id));
-    const BatchEntry& B = E[e];
+    const int id = A.id0 + (int)blockIdx.x;
+    const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 0, id));
+    const BatchEntry& B = A.e[e];
     const int local = id - B.base[0];
-    const int32_t* S_ = B.sched + (int64_t)it * B.L.stride;
-    const PairWork* W = B.work + (int64_t)it * B.L.maxv * B.L.B;
+    const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
+    const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
     if (B.fp_lds) {
-        fp_lds_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, B.fp_chunk, local % B.gx[0], local / B.gx[0],
-                         xs, sh);
+        fp_lds_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, B.fp_chunk, local % B.gx[0],
+                         local / B.gx[0], xs, sh);
     } else {
         const int wave = __builtin_amdgcn_readfirstlane(local * (WG / 64) + (threadIdx.x >> 6));
         fp_global_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, wave, threadIdx.x & 63);
     }
 }
 
-__global__ __launch_bounds__(RES_WG) void k_resid_batch(const BatchEntry* __restrict__ E, int n, int it)
+__global__ __launch_bounds__(RES_WG) void k_resid_batch(const BatchArgs A)
 {
     extern __shared__ int4 rc[];
     const int id = blockIdx.x;
-    const int e = __builtin_amdgcn_readfirstlane(find_entry(E, n, 1, id));
-    const BatchEntry& B = E[e];
+    const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 1, id));
+    const BatchEntry& B = A.e[e];
     const int local = id - B.base[1];
-    const int32_t* S_ = B.sched + (int64_t)it * B.L.stride;
+    const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
     resid_body(B.G, S_, B.L, B.y, B.z, B.r_sel, local % B.gx[1], local / B.gx[1], rc);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_bp_batch(const BatchEntry* __restrict__ E, int n, int it)
+__global__ __launch_bounds__(WG) void k_bp_batch(const BatchArgs A)
 {
     __shared__ float part[BP_SPLIT][BP_VOX];
     const int id = blockIdx.x;
-    const int e = __builtin_amdgcn_readfirstlane(find_entry(E, n, 2, id));
-    const BatchEntry& B = E[e];
+    const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 2, id));
+    const BatchEntry& B = A.e[e];
     const int local = id - B.base[2];
-    const int32_t* S_ = B.sched + (int64_t)it * B.L.stride;
-    const PairWork* W = B.work + (int64_t)it * B.L.maxv * B.L.B;
-    bp_step_body<DIM>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2], local / B.gx[2],
-                      part);
+    const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
+    const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
+    bp_step_body<DIM>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
+                      local / B.gx[2], part);
 }
 
 // ------------------------------------------------------------ standalone projectors
@@ -1032,23 +1032,32 @@ void batch_grids(BatchEntry& e)
     e.gx[2] = max_tiles(G, nullptr, G.dim);
 }
 
-hipError_t launch_batch_iteration(const BatchEntry* dev_entries, int n, int dim, int it, const int (&wgs)[3],
-                                  size_t fp_lds, size_t res_lds, hipStream_t st)
+hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], const FpLaunchClass* fp_classes,
+                                  int n_fp_classes, size_t res_lds, hipStream_t st)
 {
-    if (n == 0) return hipSuccess;
-    if (dim == 3)
-        hipLaunchKernelGGL(k_fp_batch<3>, dim3(wgs[0]), dim3(WG), fp_lds, st, dev_entries, n, it);
-    else
-        hipLaunchKernelGGL(k_fp_batch<2>, dim3(wgs[0]), dim3(WG), fp_lds, st, dev_entries, n, it);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_resid_batch, dim3(wgs[1]), dim3(RES_WG), res_lds, st, dev_entries, n, it);
+    if (A.n == 0) return hipSuccess;
+    // forward projection: one launch per LDS size class (contiguous workgroup ranges),
+    // so no solve runs with more LDS, and less occupancy, than its own tile needs
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < n_fp_classes; ++c) {
+        const FpLaunchClass& k = fp_classes[c];
+        if (k.wgs <= 0) continue;
+        A.id0 = k.wg0;
+        if (dim == 3)
+            hipLaunchKernelGGL(k_fp_batch<3>, dim3(k.wgs), dim3(WG), k.lds_bytes, st, A);
+        else
+            hipLaunchKernelGGL(k_fp_batch<2>, dim3(k.wgs), dim3(WG), k.lds_bytes, st, A);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    A.id0 = 0;
+    hipLaunchKernelGGL(k_resid_batch, dim3(wgs[1]), dim3(RES_WG), res_lds, st, A);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dim == 3)
-        hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(WG), 0, st, dev_entries, n, it);
+        hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(WG), 0, st, A);
     else
-        hipLaunchKernelGGL(k_bp_batch<2>, dim3(wgs[2]), dim3(WG), 0, st, dev_entries, n, it);
+        hipLaunchKernelGGL(k_bp_batch<2>, dim3(wgs[2]), dim3(WG), 0, st, A);
     return hipGetLastError();
 }
 

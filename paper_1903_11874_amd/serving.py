@@ -3,14 +3,17 @@
 Requests (a scan geometry, its measured projections y and a stopping rule) arrive
 over time. A request is admitted when a slot is free and the device has room for
 its state (measured free HBM minus a reserve). Every tick advances all admitted
-solves by whole effective epochs with one launch per phase (``bsgd_step_batch``),
-so small and large reconstructions share the GPU. Each solve stops when its relative
+solves by one effective epoch with one launch per phase (``bsgd_step_batch``), so
+small and large reconstructions share the GPU. A solve stops when its relative
 normal-equation residual ||A^T (y - A x)|| / ||A^T y|| falls to the requested
-tolerance (checked every ``check_every`` epochs) or at its epoch cap; finished solves
-free their slot at once and waiting requests are admitted in arrival order.
+tolerance (checked every ``check_every`` epochs, the rule of ``bsgd_solve``) or at
+its epoch cap; the checks of a tick are computed for all due solves with one
+synchronisation (``bsgd_normal_residual``). Finished solves free their slot at once
+and waiting requests are admitted in arrival order.
 
 Because a solve's arithmetic does not depend on the batch it runs in, the result of
-every request equals the result of the same request run alone (``run_sequential``).
+every request equals the same request solved alone by ``bsgd_solve``
+(``run_sequential``, the plain per-solve loop).
 """
 from __future__ import annotations
 
@@ -21,7 +24,7 @@ from typing import Callable, Dict, List, Optional
 
 import numpy as np
 
-from .bsgd import Geometry, Solver, step_batch
+from .bsgd import Geometry, Solver, normal_residual, solve, step_batch
 
 
 @dataclass
@@ -54,10 +57,6 @@ class Result:
         return self.finished - self.arrival
 
 
-def _norm(t) -> float:
-    return float(t.double().norm())
-
-
 class _Active:
     def __init__(self, req: Request, geom: Geometry, stream, admitted: float):
         import torch
@@ -69,13 +68,10 @@ class _Active:
                              seed=req.seed)
         self.epochs = 0
         self.admitted = admitted
-        self.aty = _norm(geom.back_project(req.y, stream=stream))
         self.ratio = math.inf
 
-    def check(self, stream) -> float:
-        r = self.req.y - self.geom.forward_project(self.x, stream=stream)
-        self.ratio = _norm(self.geom.back_project(r, stream=stream)) / max(self.aty, 1e-300)
-        return self.ratio
+    def due(self) -> bool:
+        return self.epochs % self.req.check_every == 0 or self.epochs >= self.req.max_epochs
 
     def done(self) -> bool:
         return self.ratio <= self.req.tol or self.epochs >= self.req.max_epochs
@@ -117,7 +113,6 @@ class Server:
         return free - state_bytes(geom, node_count) > self.hbm_reserve * total
 
     def run(self, requests: List[Request]) -> List[Result]:
-        import torch
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         active: List[_Active] = []
         results: List[Result] = []
@@ -141,17 +136,21 @@ class Server:
             for a in active:
                 key = (a.solver.epoch_iters, a.req.geometry.is_3d)
                 groups.setdefault(key, []).append(a)
+            t_tick = self.clock()
             for (T, _), grp in groups.items():
                 step_batch([a.solver for a in grp], T, stream=self.stream)
                 for a in grp:
                     a.epochs += 1
-            self.log.append((self.clock() - t0, len(active)))
+            t_enq = self.clock()
+            due = [a for a in active if a.due()]
+            if due:
+                for a, r in zip(due, normal_residual([a.solver for a in due], True, self.stream)):
+                    a.ratio = float(r)
+            # (tick end, active solves, seconds enqueueing the epoch, seconds in the checks)
+            self.log.append((self.clock() - t0, len(active), t_enq - t_tick, self.clock() - t_enq))
             still: List[_Active] = []
             for a in active:
-                if a.epochs % a.req.check_every == 0 or a.epochs >= a.req.max_epochs:
-                    a.check(self.stream)
-                if a.done():
-                    self.stream.synchronize()
+                if a.due() and a.done():
                     results.append(Result(a.req.rid, a.x, a.epochs, a.solver.iterations, a.req.arrival,
                                           a.admitted, self.clock() - t0, a.ratio))
                     a.solver.close()
@@ -161,28 +160,44 @@ class Server:
         return sorted(results, key=lambda r: r.rid)
 
     def run_sequential(self, requests: List[Request]) -> List[Result]:
-        """Baseline: the plain per-solve loop, one request at a time in arrival order,
-        same stopping rule and check cadence."""
+        """Baseline: the plain per-solve loop, bsgd_solve for one request at a time in
+        arrival order with the same stopping rule. The final statistic of each result
+        is recomputed after the timed loop (bsgd_solve does not return it)."""
+        import torch
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        results: List[Result] = []
+        epoch_iters: Dict[object, int] = {}
+        for req in pending:
+            if req.geometry not in epoch_iters:
+                geom = self.geometry(req.geometry)
+                g = req.geometry
+                probe = Solver(geom, req.y, torch.zeros(g.nx * g.ny * g.nz, dtype=torch.float32,
+                                                       device=req.y.device),
+                               stream=self.stream, node_count=req.node_count, mu=req.mu)
+                epoch_iters[req.geometry] = probe.epoch_iters
+                probe.close()
+        self.stream.synchronize()
+        raw = []
         t0 = self.clock()
         for req in pending:
             wait = req.arrival - (self.clock() - t0)
             if wait > 0:
                 time.sleep(wait)
             geom = self.geometry(req.geometry)
-            a = _Active(req, geom, self.stream, self.clock() - t0)
-            while True:
-                a.solver.step(a.solver.epoch_iters)
-                a.epochs += 1
-                if a.epochs % req.check_every == 0 or a.epochs >= req.max_epochs:
-                    a.check(self.stream)
-                if a.done():
-                    break
-            self.stream.synchronize()
-            results.append(Result(req.rid, a.x, a.epochs, a.solver.iterations, req.arrival, a.admitted,
-                                  self.clock() - t0, a.ratio))
-            a.solver.close()
+            g = req.geometry
+            admitted = self.clock() - t0
+            x = torch.zeros(g.nx * g.ny * g.nz, dtype=torch.float32, device=req.y.device)
+            iters, _ = solve(geom, req.y, x, stream=self.stream, node_count=req.node_count, mu=req.mu,
+                             seed=req.seed, tol=req.tol, max_effective_epochs=req.max_epochs,
+                             check_every=req.check_every)
+            raw.append((req, x, iters, admitted, self.clock() - t0))
+        results = []
+        for req, x, iters, admitted, finished in raw:
+            s = Solver(self.geometry(req.geometry), req.y, x, stream=self.stream, node_count=req.node_count,
+                       mu=req.mu)
+            ratio = float(normal_residual([s], True, self.stream)[0])
+            s.close()
+            results.append(Result(req.rid, x, iters // epoch_iters[req.geometry], iters, req.arrival, admitted,
+                                  finished, ratio))
         return sorted(results, key=lambda r: r.rid)
 
 

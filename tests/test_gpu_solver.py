@@ -304,3 +304,29 @@ def test_auto_step_length_matches_oracle(scale, eager):
     assert np.allclose(hist, am.mu_history, rtol=1e-12)
     assert hist[-1] != mu  # the rule acted
     assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
+
+
+@pytest.mark.parametrize("name", ["fan", "cone"])
+def test_normal_residual_matches_oracle(name):
+    """The stopping statistic ||A^T (y - A x)|| (and its ratio to ||A^T y||) of several
+    solvers in one call equals the oracle's, each at its own image."""
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver, normal_residual
+    dev = require_gpu()
+    g = SMALL[name]
+    log(f"normal residual {name}")
+    A, x_true, y64, y32 = _data(g)
+    geom = Geometry(g)
+    yd = torch.tensor(y32, device=dev)
+    rng = np.random.Generator(np.random.PCG64(17))
+    xs = [torch.tensor(x_true * s + rng.normal(0, 0.05, x_true.size), dtype=torch.float32, device=dev)
+          for s in (0.5, 0.9, 1.0)]
+    solvers = [Solver(geom, yd, x, node_count=4, mu=1e-3) for x in xs]
+    absolute = normal_residual(solvers, relative=False)
+    relative = normal_residual(solvers, relative=True)
+    ref_y = np.linalg.norm(A.T @ y64)
+    for x, a, r in zip(xs, absolute, relative):
+        x64 = x.double().cpu().numpy()
+        ref = np.linalg.norm(A.T @ (y64 - A @ x64))
+        assert abs(a - ref) <= 1e-4 * ref
+        assert abs(r - ref / ref_y) <= 1e-4 * ref / ref_y
