@@ -77,6 +77,100 @@ def schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w)
     return per_it
 
 
+def measure(geom, spec, solver, n_vox, warmup, steps, n_prof):
+    """Warm-up epochs, a timed region of `steps` epochs (captured HIP graphs, no
+    events), then an event-timed eager region of `n_prof` epochs for per-kernel
+    averages; exact update counts from the schedules; roofline of the dominant kernel."""
+    import torch
+    T = solver.epoch_iters
+    args_warmup, args_steps = warmup, steps
+    for _ in range(args_warmup):
+        solver.step(T)
+    r0 = solver.step(0, residual=True)
+    torch.cuda.synchronize()
+
+    # timed region: whole epochs, replayed as captured HIP graphs, no per-kernel events
+    solver.set_profiling(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(T * args_steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    rows, blocks, draws = solver.last_schedule()
+    # second timed region of the same length with HIP events around every kernel
+    # (eager launches on the solver's stream): per-kernel average durations
+    base_times = solver.kernel_times()
+    solver.set_profiling(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    solver.step(T * n_prof)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    times_p = solver.kernel_times()
+    solver.set_profiling(False)
+    times = {k: (times_p[k][0] - base_times[k][0], times_p[k][1] - base_times[k][1]) for k in times_p}
+    prow, pblk, pdr = solver.last_schedule()
+    r1 = solver.step(0, residual=True)
+
+    nnz_tab = geom.table("nnz")
+    fp_rect = geom.table("footprint")
+    subdet_w = [((a * spec.nu) // spec.su, ((a + 1) * spec.nu) // spec.su) for a in range(spec.su)]
+    per_it = schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w)
+    U_fp = sum(p[0] for p in per_it)
+    updates = 2 * U_fp
+    value = updates / elapsed
+
+    # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
+    per_it_p = schedule_counts(geom, spec, prow, pblk, pdr, nnz_tab, fp_rect, subdet_w)
+    n_it = len(per_it_p)
+    vsel = n_vox * solver.blocks_per_iter // geom.info["n_blocks"]
+    bytes_fp = sum(4 * u + 4 * zw for u, zw, _ in per_it_p) / n_it
+    bytes_bp = sum(4 * u for u, _, _ in per_it_p) / n_it + vsel * (8 * solver.rows_per_iter + 16)
+    avg_ms = {k: (ms / n if n else 0.0) for k, (ms, n) in times.items()}
+    dominant = max(("forward_project", "back_project_step"), key=lambda k: times[k][0])
+    alg_bytes = bytes_fp if dominant == "forward_project" else bytes_bp
+    achieved = alg_bytes / (avg_ms[dominant] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms[dominant]}
+
+    return {"elapsed": elapsed, "value": value, "updates": updates, "roofline": roofline,
+            "kernels_avg_ms": avg_ms, "times": times, "r0": r0, "r1": r1, "n_prof": n_prof, "t2": t2, "t3": t3}
+
+
+def cone_bench(steps, warmup, n_prof):
+    """The 3D cone-beam workload with TV (256^3, 360 views of 384^2): same measurement."""
+    import torch
+    from bsgd_inputs.configs import workload
+    from bsgd_inputs.phantoms import phantom_for, add_gaussian_noise
+    from paper_1903_11874_amd import Geometry, Solver
+    wl = workload("c3_cone256_tv")
+    spec = wl.geometry
+    log("cone: geometry")
+    geom = Geometry(spec)
+    n_vox = spec.nx * spec.ny * spec.nz
+    xt = torch.tensor(phantom_for(spec, wl.n_shapes, wl.phantom_seed), dtype=torch.float32, device="cuda")
+    y = add_gaussian_noise(geom.forward_project(xt).double().cpu().numpy(), wl.noise_level, wl.noise_seed)
+    yd = torch.tensor(y, dtype=torch.float32, device="cuda")
+    del xt, y
+    L = lipschitz_gpu(geom, n_vox, iters=6)
+    mu = wl.solver.mu_scale / (2.0 * L)
+    log(f"cone: L = {L:.4e}, mu = {mu:.4e}")
+    x = torch.zeros(n_vox, dtype=torch.float32, device="cuda")
+    solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed, tv_lambda=wl.solver.tv_lambda,
+                    tv_inner_iters=wl.solver.tv_inner_iters)
+    m = measure(geom, spec, solver, n_vox, warmup, steps, n_prof)
+    T = solver.epoch_iters
+    return {"workload": wl.description, "metric": "FP+BP ray-voxel updates/s", "value": m["value"],
+            "unit": "updates/s", "steps": steps, "ms_per_step": m["elapsed"] / steps * 1e3,
+            "rows_per_iter": solver.rows_per_iter, "blocks_per_iter": solver.blocks_per_iter,
+            "iters_per_step": T, "step": "one effective epoch (TV prox once per epoch)",
+            "roofline": m["roofline"], "kernels_avg_ms": m["kernels_avg_ms"],
+            "kernel_launches": {k: n for k, (ms, n) in m["times"].items()},
+            "residual_norm": {"before": m["r0"], "after": m["r1"]}, "updates_per_step": m["updates"] / steps}
+
+
 def cpu_baseline(spec, x, budget_s=12.0):
     """The FP64 oracle's matrix-free FP + BP over every ray, repeated to a bounded time budget."""
     from oracle.cfast import Projector
@@ -150,6 +244,8 @@ def main():
                     help="requests of the continuous-batching serving measurement (0 = skip)")
     ap.add_argument("--serving-tol", type=float, default=1e-3)
     ap.add_argument("--serving-max-epochs", type=int, default=30)
+    ap.add_argument("--cone-steps", type=int, default=3,
+                    help="epochs of the 3D cone-beam (256^3, TV) measurement reported as 'secondary' (0 = skip)")
     ap.add_argument("--tune", default="auto",
                     help="forward-projector launch shape: 'auto' (autotuner, before the timed region) "
                          "or 'V,S' (views per workgroup, lanes per ray)")
@@ -206,57 +302,11 @@ def main():
     T = solver.epoch_iters
     log(f"alpha M = {solver.rows_per_iter}, gamma N = {solver.blocks_per_iter}, epoch = {T} iterations")
 
-    for _ in range(args.warmup):
-        solver.step(T)
-    r0 = solver.step(0, residual=True)
-    torch.cuda.synchronize()
-
-    # timed region: whole epochs, replayed as captured HIP graphs, no per-kernel events
-    solver.set_profiling(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver.step(T * args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    rows, blocks, draws = solver.last_schedule()
-    # second timed region of the same length with HIP events around every kernel
-    # (eager launches on the solver's stream): per-kernel average durations
-    n_prof = args.profile_steps if args.profile_steps > 0 else args.steps
-    base_times = solver.kernel_times()
-    solver.set_profiling(True)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    solver.step(T * n_prof)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    times_p = solver.kernel_times()
-    solver.set_profiling(False)
-    times = {k: (times_p[k][0] - base_times[k][0], times_p[k][1] - base_times[k][1]) for k in times_p}
-    prow, pblk, pdr = solver.last_schedule()
-    r1 = solver.step(0, residual=True)
-
-    nnz_tab = geom.table("nnz")
-    fp_rect = geom.table("footprint")
-    subdet_w = [((a * spec.nu) // spec.su, ((a + 1) * spec.nu) // spec.su) for a in range(spec.su)]
-    per_it = schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w)
-    U_fp = sum(p[0] for p in per_it)
-    updates = 2 * U_fp
-    value = updates / elapsed
-
-    # roofline of the dominant kernel: algorithmic bytes per launch / mean launch time
-    per_it_p = schedule_counts(geom, spec, prow, pblk, pdr, nnz_tab, fp_rect, subdet_w)
-    n_it = len(per_it_p)
-    vsel = n_vox * solver.blocks_per_iter // geom.info["n_blocks"]
-    bytes_fp = sum(4 * u + 4 * zw for u, zw, _ in per_it_p) / n_it
-    bytes_bp = sum(4 * u for u, _, _ in per_it_p) / n_it + vsel * (8 * solver.rows_per_iter + 16)
-    avg_ms = {k: (ms / n if n else 0.0) for k, (ms, n) in times.items()}
-    dominant = max(("forward_project", "back_project_step"), key=lambda k: times[k][0])
-    alg_bytes = bytes_fp if dominant == "forward_project" else bytes_bp
-    achieved = alg_bytes / (avg_ms[dominant] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms[dominant]}
+    m = measure(geom, spec, solver, n_vox, args.warmup, args.steps,
+                args.profile_steps if args.profile_steps > 0 else args.steps)
+    elapsed, value, updates, roofline, avg_ms, times = (m["elapsed"], m["value"], m["updates"], m["roofline"],
+                                                        m["kernels_avg_ms"], m["times"])
+    r0, r1, n_prof, t2, t3 = m["r0"], m["r1"], m["n_prof"], m["t2"], m["t3"]
 
     out = {
         "metric": "FP+BP ray-voxel updates/s",
@@ -285,6 +335,10 @@ def main():
         "residual_norm": {"before": r0, "after": r1},
         "updates_per_step": updates / args.steps,
     }
+    if args.cone_steps > 0:
+        del solver, x, yd, geom
+        torch.cuda.empty_cache()
+        out["secondary"] = cone_bench(args.cone_steps, 1, args.cone_steps)
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, 20.0, 32, args.serving_tol, args.serving_max_epochs)
     if not args.no_cpu_baseline:

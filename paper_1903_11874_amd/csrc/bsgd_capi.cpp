@@ -491,6 +491,19 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.rayv = g->d_rayv.as<float2>();
     G.fp_chunk = 3;
     G.fp_split = 1;
+    // waves per pair of the global-memory forward projector: about three 64-pixel
+    // rounds per wave at the mean footprint area
+    {
+        double area = 0.0;
+        int64_t cnt = 0;
+        for (const PairInfo& P : g->pairs)
+            if (P.u1 > P.u0 && P.v1 > P.v0) {
+                area += (double)(P.u1 - P.u0) * (P.v1 - P.v0);
+                ++cnt;
+            }
+        const double mean = cnt ? area / (double)cnt : 0.0;
+        G.fp_wpp = (int)std::min(16.0, std::max(1.0, std::floor(mean / 192.0)));
+    }
     G.raynorm = g->raynorm.empty() ? nullptr : g->d_raynorm.as<float4>();
     G.raytrap = g->raytrap.empty() ? nullptr : g->d_raytrap.as<float4>();
     G.kspan = g->kspan.empty() ? nullptr : g->d_kspan.as<float>();

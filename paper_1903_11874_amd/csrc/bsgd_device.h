@@ -74,7 +74,7 @@ struct DevGeom {
     const float2* rayv;        // [nv]: 1/v, v^2 (cone only)
     int32_t fp_chunk;          // views per workgroup of the LDS forward projector (tuning)
     int32_t fp_split;          // lanes per 2D ray in the LDS forward projector: 1, 2 or 4 (tuning)
-    int32_t pad_;
+    int32_t fp_wpp;            // waves per (view, block) pair of the global-memory forward projector
     // 2D chord tables: per (view, pixel) the unit normal (nx, ny) of the ray, xi with
     // n . p = lambda xi for the ray's anchor point p, and the trapezoid of the chord
     // length through one voxel as a function of the signed distance of the voxel
@@ -363,6 +363,80 @@ __device__ __forceinline__ float walk_2d_range_wave(const Ray& R, const int (&nb
         my += cx ? 0.0f : 1.0f;
         tx = fmaf(mx, ax, tx0);
         ty = fmaf(my, ay, ty0);
+    }
+    return acc;
+}
+
+// Parameter interval [tlo, thi) of a 3D ray inside a block (same slab formula as
+// walk_block); false when the ray misses the block.
+__device__ __forceinline__ bool slab_3d(const Ray& R, const int (&nb)[3], const float (&h)[3], const float (&vs)[3],
+                                        float& tlo, float& thi)
+{
+    tlo = -INFINITY;
+    thi = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float X0 = -h[a];
+        const float Xn = plane_pos(nb[a], vs[a], h[a]);
+        if (!axis_fixed(R.inv[a])) {
+            const float t0 = (X0 - R.p[a]) * R.inv[a];
+            const float t1 = (Xn - R.p[a]) * R.inv[a];
+            tlo = fmaxf(tlo, fminf(t0, t1));
+            thi = fminf(thi, fmaxf(t0, t1));
+        } else if (!(X0 <= R.p[a] && R.p[a] < Xn)) {
+            return false;
+        }
+    }
+    return tlo < thi;
+}
+
+// The 3D form of walk_2d_range_wave: Siddon order with ties crossing x, then y, then
+// z (as walk_block); the m-th later crossing of an axis is fmaf(m, v |inv|, t_first);
+// wave-uniform trip count from the crossings each lane's range can hold; offsets
+// off = iz sz + iy sy + ix clamped into the block. All 64 lanes must be active.
+template <class Load>
+__device__ __forceinline__ float walk_3d_range_wave(const Ray& R, const int (&nb)[3], const float (&h)[3],
+                                                    const float (&vs)[3], int sy, int sz, float t0, float t1,
+                                                    bool live, Load&& load)
+{
+    live = live && (t0 < t1);
+    int ix = 0, iy = 0, iz = 0, sx = 0, sy_ = 0, sz_ = 0;
+    float tx0 = INFINITY, ty0 = INFINITY, tz0 = INFINITY;
+    if (live) {
+        walk_axis_init(R, 0, nb[0], h[0], vs[0], t0, ix, sx, tx0);
+        walk_axis_init(R, 1, nb[1], h[1], vs[1], t0, iy, sy_, ty0);
+        walk_axis_init(R, 2, nb[2], h[2], vs[2], t0, iz, sz_, tz0);
+    } else {
+        t0 = t1 = 0.0f;
+    }
+    const float ax = (live && !axis_fixed(R.inv[0])) ? vs[0] * fabsf(R.inv[0]) : 0.0f;
+    const float ay = (live && !axis_fixed(R.inv[1])) ? vs[1] * fabsf(R.inv[1]) : 0.0f;
+    const float az = (live && !axis_fixed(R.inv[2])) ? vs[2] * fabsf(R.inv[2]) : 0.0f;
+    const float cap = (float)(nb[0] + nb[1] + nb[2] + 2);
+    const float span = t1 - t0;
+    const float nxf = ax > 0.0f ? fminf(floorf(span * __builtin_amdgcn_rcpf(ax)), cap) : 0.0f;
+    const float nyf = ay > 0.0f ? fminf(floorf(span * __builtin_amdgcn_rcpf(ay)), cap) : 0.0f;
+    const float nzf = az > 0.0f ? fminf(floorf(span * __builtin_amdgcn_rcpf(az)), cap) : 0.0f;
+    const int n = live ? (int)fminf(nxf + nyf + nzf + 5.0f, cap) : 0;
+    const int n_wave = wave_max_int(n);
+    float mx = 0.0f, my = 0.0f, mz = 0.0f, tx = tx0, ty = ty0, tz = tz0;
+    const int dox = sx, doy = sy_ * sy, doz = sz_ * sz;
+    const unsigned last = (unsigned)((nb[2] - 1) * sz + (nb[1] - 1) * sy + nb[0] - 1);
+    int off = iz * sz + iy * sy + ix;
+    float t = t0, acc = 0.0f;
+    for (int it = 0; it < n_wave; ++it) {
+        const bool cx = (tx <= ty) && (tx <= tz);
+        const bool cy = !cx && (ty <= tz);
+        const float tm = fminf(fminf(fminf(tx, ty), tz), t1);
+        acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
+        t = tm;
+        off += cx ? dox : (cy ? doy : doz);
+        mx += cx ? 1.0f : 0.0f;
+        my += cy ? 1.0f : 0.0f;
+        mz += (cx || cy) ? 0.0f : 1.0f;
+        tx = fmaf(mx, ax, tx0);
+        ty = fmaf(my, ay, ty0);
+        tz = fmaf(mz, az, tz0);
     }
     return acc;
 }

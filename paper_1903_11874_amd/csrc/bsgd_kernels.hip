@@ -337,34 +337,48 @@ __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restric
 
 // ------------------------------------------------------------ solver: forward projection
 
-// One wave per (view slot, block slot) pair: z^j = A_{rows}^{J_j} x_{J_j} on the
-// pair's range. Lanes walk consecutive detector pixels, so z stores are contiguous.
-// x is gathered from global memory (blocks too large for LDS).
+// G.fp_wpp waves per (view slot, block slot) pair: z^j = A_{rows}^{J_j} x_{J_j} on the
+// pair's range. Wave w of a pair walks pixels q = lane + 64 (w + fp_wpp r) for a
+// wave-uniform number of rounds r; every lane runs every round (lanes past the pair's
+// pixels are dead), so the walk's trip count is wave-uniform. x is gathered from
+// global memory (blocks too large for LDS).
 template <int DIM>
 __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork* __restrict__ work, SchedLayout L,
                                                const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
                                                float* __restrict__ z, int wave, int lane)
 {
-    if (wave >= L.maxv * L.B) return;
-    const int b = wave / L.maxv;
-    const PairWork W = work[wave];
+    const int wpp = max(1, G.fp_wpp);
+    const int pair = wave / wpp, w = wave - pair * wpp;
+    if (pair >= L.maxv * L.B) return;
+    const int b = pair / L.maxv;
+    const PairWork W = work[pair];
     const int wk = W.k1 - W.k0, wl = W.l1 - W.l0;
     if (wk <= 0 || wl <= 0) return;
+    const int n = wk * wl;
+    if (n <= 64 * w) return;
     const BlockInfo B = G.blocks[blocks_sel[b]];
     const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
-    const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
-    const int n = wk * wl;
-    int l = W.l0 + lane / wk;
-    int k = W.k0 + lane % wk;
-    const int dl = 64 / wk, dk = 64 % wk;
-    for (int q = lane; q < n; q += 64) {
-        z[W.zbase + (int64_t)l * W.zw + k] = fp_ray_block<DIM>(G, W.view, W.c, W.s, W, B, k, l, xb, sy, sz);
-        k += dk;
-        l += dl;
-        if (k >= W.k1) {
-            k -= wk;
-            ++l;
+    const int sy = G.nx, sz = G.nx * G.ny;
+    int nb[3];
+    float h[3], vs[3];
+    block_dims(G, B, nb, h, vs);
+    const int rounds = (n - 64 * w + 64 * wpp - 1) / (64 * wpp);
+    for (int r = 0; r < rounds; ++r) {
+        const int q = lane + 64 * (w + wpp * r);
+        const bool on = q < n;
+        const int qq = on ? q : 0;
+        const int l = W.l0 + qq / wk, k = W.k0 + qq % wk;
+        Ray R;
+        make_ray<DIM>(G, W.view, W.c, W.s, W, k, l, R);
+        float tlo = 0.0f, thi = 0.0f, acc;
+        if (DIM == 2) {
+            const bool hit = on && slab_2d(R, nb, h, vs, tlo, thi);
+            acc = walk_2d_range_wave(R, nb, h, vs, sy, tlo, thi, hit, [&](unsigned off) { return xb[off]; });
+        } else {
+            const bool hit = on && slab_3d(R, nb, h, vs, tlo, thi);
+            acc = walk_3d_range_wave(R, nb, h, vs, sy, sz, tlo, thi, hit, [&](unsigned off) { return xb[off]; });
         }
+        if (on) z[W.zbase + (int64_t)l * W.zw + k] = acc * R.len;
     }
 }
 
@@ -996,7 +1010,7 @@ hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayou
                                chunk);
         return hipGetLastError();
     }
-    const int64_t waves = (int64_t)L.maxv * L.B;
+    const int64_t waves = (int64_t)L.maxv * L.B * std::max(1, G.fp_wpp);
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     if (G.dim == 3)
         hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, z);
@@ -1026,7 +1040,7 @@ void batch_grids(BatchEntry& e)
     } else {
         e.fp_lds = 0;
         e.fp_chunk = 0;
-        e.gx[0] = (int)(((int64_t)L.maxv * L.B + 3) / 4);
+        e.gx[0] = (int)(((int64_t)L.maxv * L.B * std::max(1, G.fp_wpp) + 3) / 4);
     }
     e.gx[1] = (G.nu * G.nv + RES_WG - 1) / RES_WG;
     e.gx[2] = max_tiles(G, nullptr, G.dim);

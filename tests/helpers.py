@@ -41,7 +41,15 @@ FAN_SMALL = GeometrySpec(kind="fan2d", nx=41, ny=35, nz=1, vx=0.8, vy=0.8, vz=0.
 CONE_SMALL = GeometrySpec(kind="cone3d", nx=20, ny=18, nz=14, vx=1.0, vy=1.0, vz=0.947, n_views=24,
                           angle_span=2 * math.pi, nu=28, nv=22, du=1.3, dv=1.2373, sod=40.0, sdd=90.0,
                           bx=2, by=3, bz=2, n_row_blocks=4, partition_seed=23, su=2, sv=2)
-SMALL = {"parallel": PARALLEL_SMALL, "fan": FAN_SMALL, "cone": CONE_SMALL}
+# blocks larger than the forward projector's 64 KB LDS stage (global-memory path)
+FAN_WIDE = GeometrySpec(kind="fan2d", nx=262, ny=260, nz=1, vx=0.3, vy=0.3, vz=0.3, n_views=30,
+                        angle_span=2 * math.pi, nu=180, nv=1, du=1.1, dv=1.0, sod=90.0, sdd=200.0,
+                        bx=2, by=2, bz=1, n_row_blocks=3, partition_seed=24)
+CONE_WIDE = GeometrySpec(kind="cone3d", nx=66, ny=64, nz=26, vx=0.5, vy=0.5, vz=0.47, n_views=16,
+                         angle_span=2 * math.pi, nu=44, nv=30, du=1.3, dv=1.2373, sod=60.0, sdd=130.0,
+                         bx=2, by=2, bz=1, n_row_blocks=4, partition_seed=25)
+SMALL = {"parallel": PARALLEL_SMALL, "fan": FAN_SMALL, "cone": CONE_SMALL, "fan_wide": FAN_WIDE,
+         "cone_wide": CONE_WIDE}
 
 
 @functools.lru_cache(maxsize=16)

@@ -60,7 +60,8 @@ def _check_schedule(p, trace, solver):
                     assert int(draws[it, a, b]) == t["draws"][(v, j)], (it, v, j)
 
 
-@pytest.mark.parametrize("name,R,B", [("fan", 1, 2), ("parallel", 2, 3), ("cone", 1, 4)])
+@pytest.mark.parametrize("name,R,B", [("fan", 1, 2), ("parallel", 2, 3), ("cone", 1, 4), ("fan_wide", 1, 2),
+                                      ("cone_wide", 2, 3)])
 def test_trajectory_plain(name, R, B):
     log(f"trajectory plain {name} R={R} B={B}")
     p, st, trace, solver, xd, rn = _pair(SMALL[name], 60, R, B, seed=7)
