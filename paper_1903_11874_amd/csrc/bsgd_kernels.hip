@@ -501,31 +501,54 @@ __global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* 
 
 // ------------------------------------------------------------ solver: residual rebuild
 
-constexpr int RES_WG = 64;
+// Residual workgroup size: 64 threads in 2D, where one iteration has few rays and
+// small workgroups spread them over every CU; 256 in 3D, where rays are plentiful and
+// fewer, larger workgroups stage each view's rectangles fewer times.
+__host__ __device__ constexpr int res_wg(int dim) { return dim == 3 ? 256 : 64; }
 
 // r = y - sum_j z^j for every ray of one view (j ascending); the view's footprint
-// rectangles are staged in LDS. The z offsets of the blocks containing the ray are
-// first collected (per thread, in LDS) and then loaded back to back, so the
-// gathers overlap instead of waiting one by one; subtraction order stays ascending j.
-constexpr int RES_BATCH = 16;
+// rectangles are staged in LDS, with the bounding rectangle of each group of blocks
+// that are consecutive in j (see res_group_size): a ray tests
+// a group's blocks only when the group's rectangle contains it. The z offsets of the
+// blocks containing the ray are first collected (per thread, in LDS) and then loaded
+// back to back, so the gathers overlap; subtraction order stays ascending j.
+// z offsets collected per thread before their gathers are issued (deeper in 2D, where
+// LDS per workgroup is small)
+__host__ __device__ constexpr int res_batch(int tpb) { return tpb == 64 ? 16 : 8; }
 
+// one z slab per group in 3D; in 2D the blocks form one group (a row of blocks spans
+// most of the detector, so a finer test prunes too little to pay for itself)
+__host__ __device__ inline int res_group_size(const DevGeom& G) { return G.bz > 1 ? G.bx * G.by : G.N; }
+__host__ __device__ inline int res_groups(const DevGeom& G)
+{
+    const int gs = res_group_size(G);
+    return (G.N + gs - 1) / gs;
+}
+
+template <int RB>
 __device__ __forceinline__ float resid_ray(const DevGeom& G, int v, int k, int l, const float* __restrict__ y,
                                            const float* __restrict__ z, const int4* rc, const long long* zo,
-                                           long long* cand, int per_view, int ray)
+                                           const int4* grc, long long* cand, int per_view, int ray)
 {
     float acc = y[(int64_t)v * per_view + ray];
+    const int gs = res_group_size(G), ng = res_groups(G);
     int cnt = 0;
-    for (int j = 0; j < G.N; ++j) {
-        const int4 r4 = rc[j];
-        if (k >= r4.x && k < r4.y && l >= r4.z && l < r4.w) {
-            cand[cnt++] = zo[j] + (int64_t)(l - r4.z) * (r4.y - r4.x) + (k - r4.x);
-            if (cnt == RES_BATCH) {
-                float vals[RES_BATCH];
+    for (int g = 0; g < ng; ++g) {
+        const int4 b4 = grc[g];
+        if (!(k >= b4.x && k < b4.y && l >= b4.z && l < b4.w)) continue;
+        const int j1 = min(G.N, (g + 1) * gs);
+        for (int j = g * gs; j < j1; ++j) {
+            const int4 r4 = rc[j];
+            if (k >= r4.x && k < r4.y && l >= r4.z && l < r4.w) {
+                cand[cnt++] = zo[j] + (int64_t)(l - r4.z) * (r4.y - r4.x) + (k - r4.x);
+                if (cnt == RB) {
+                    float vals[RB];
 #pragma unroll
-                for (int c = 0; c < RES_BATCH; ++c) vals[c] = z[cand[c]];
+                    for (int c = 0; c < RB; ++c) vals[c] = z[cand[c]];
 #pragma unroll
-                for (int c = 0; c < RES_BATCH; ++c) acc -= vals[c];
-                cnt = 0;
+                    for (int c = 0; c < RB; ++c) acc -= vals[c];
+                    cnt = 0;
+                }
             }
         }
     }
@@ -540,7 +563,9 @@ __device__ __forceinline__ float resid_ray(const DevGeom& G, int v, int k, int l
     return acc;
 }
 
-__device__ __forceinline__ void stage_rects(const DevGeom& G, int v, int4* rc, long long* zo)
+// Stage view v's footprint rectangles and z offsets, then the group bounding
+// rectangles (empty footprints ignored; an empty group gets an empty rectangle).
+__device__ __forceinline__ void stage_rects(const DevGeom& G, int v, int4* rc, long long* zo, int4* grc)
 {
     const PairInfo* pv = G.pairs + (int64_t)v * G.N;
     for (int j = threadIdx.x; j < G.N; j += blockDim.x) {
@@ -548,37 +573,64 @@ __device__ __forceinline__ void stage_rects(const DevGeom& G, int v, int4* rc, l
         zo[j] = pv[j].zoff;
     }
     __syncthreads();
+    const int gs = res_group_size(G), ng = res_groups(G);
+    if (ng == 1) {
+        if (threadIdx.x == 0) grc[0] = make_int4(-0x7fffffff, 0x7fffffff, -0x7fffffff, 0x7fffffff);
+        __syncthreads();
+        return;
+    }
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+        int4 u = make_int4(0x7fffffff, -0x7fffffff, 0x7fffffff, -0x7fffffff);
+        const int j1 = min(G.N, (g + 1) * gs);
+        for (int j = g * gs; j < j1; ++j) {
+            const int4 r4 = rc[j];
+            if (r4.y <= r4.x || r4.w <= r4.z) continue;
+            u.x = min(u.x, r4.x);
+            u.y = max(u.y, r4.y);
+            u.z = min(u.z, r4.z);
+            u.w = max(u.w, r4.w);
+        }
+        if (u.y <= u.x) u = make_int4(0, 0, 0, 0);
+        grc[g] = u;
+    }
+    __syncthreads();
 }
 
-// Dynamic LDS of the residual kernels: N int4 rectangles, then N 64-bit offsets.
-__host__ __device__ constexpr size_t resid_lds_bytes(int N, int threads)
+// Dynamic LDS of the residual kernels: N int4 rectangles, the group rectangles (the
+// 16-byte arrays first, so both stay 16-byte aligned), N 64-bit offsets, then
+// res_batch candidate offsets per thread.
+__host__ __device__ inline size_t resid_lds_bytes(const DevGeom& G, int threads)
 {
-    return (size_t)N * (sizeof(int4) + sizeof(long long)) + (size_t)threads * RES_BATCH * sizeof(long long);
+    return (size_t)G.N * (sizeof(int4) + sizeof(long long)) + (size_t)res_groups(G) * sizeof(int4) +
+           (size_t)threads * res_batch(threads) * sizeof(long long);
 }
 
+template <int TPB>
 __device__ __forceinline__ void resid_body(const DevGeom& G, const int32_t* __restrict__ S_, SchedLayout L,
                                            const float* __restrict__ y, const float* __restrict__ z,
                                            float* __restrict__ r_sel, int bx, int by, int4* rc)
 {
-    long long* zo = reinterpret_cast<long long*>(rc + G.N);
-    long long* cand = zo + G.N + threadIdx.x * RES_BATCH;
+    int4* grc = rc + G.N;
+    long long* zo = reinterpret_cast<long long*>(grc + res_groups(G));
+    long long* cand = zo + G.N + threadIdx.x * res_batch(TPB);
     const int a = by;
     if (a >= S_[0]) return;
     const int v = S_[L.off_views() + a];
-    stage_rects(G, v, rc, zo);
+    stage_rects(G, v, rc, zo, grc);
     const int per_view = G.nu * G.nv;
-    const int ray = bx * RES_WG + threadIdx.x;
+    const int ray = bx * TPB + threadIdx.x;
     if (ray >= per_view) return;
     const int k = ray % G.nu, l = ray / G.nu;
-    r_sel[(int64_t)a * per_view + ray] = resid_ray(G, v, k, l, y, z, rc, zo, cand, per_view, ray);
+    r_sel[(int64_t)a * per_view + ray] = resid_ray<res_batch(TPB)>(G, v, k, l, y, z, rc, zo, grc, cand, per_view, ray);
 }
 
-__global__ __launch_bounds__(RES_WG) void k_resid(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
+template <int TPB>
+__global__ __launch_bounds__(TPB) void k_resid(DevGeom G, const int32_t* __restrict__ S_, SchedLayout L,
                                                   const float* __restrict__ y, const float* __restrict__ z,
                                                   float* __restrict__ r_sel)
 {
     extern __shared__ int4 rc[];
-    resid_body(G, S_, L, y, z, r_sel, blockIdx.x, blockIdx.y, rc);
+    resid_body<TPB>(G, S_, L, y, z, r_sel, blockIdx.x, blockIdx.y, rc);
 }
 
 // ------------------------------------------------------------ solver: back projection + step
@@ -727,7 +779,8 @@ __global__ __launch_bounds__(WG) void k_fp_batch(const BatchArgs A)
     }
 }
 
-__global__ __launch_bounds__(RES_WG) void k_resid_batch(const BatchArgs A)
+template <int TPB>
+__global__ __launch_bounds__(TPB) void k_resid_batch(const BatchArgs A)
 {
     extern __shared__ int4 rc[];
     const int id = blockIdx.x;
@@ -735,7 +788,7 @@ __global__ __launch_bounds__(RES_WG) void k_resid_batch(const BatchArgs A)
     const BatchEntry& B = A.e[e];
     const int local = id - B.base[1];
     const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
-    resid_body(B.G, S_, B.L, B.y, B.z, B.r_sel, local % B.gx[1], local / B.gx[1], rc);
+    resid_body<TPB>(B.G, S_, B.L, B.y, B.z, B.r_sel, local % B.gx[1], local / B.gx[1], rc);
 }
 
 template <int DIM>
@@ -831,15 +884,16 @@ __global__ __launch_bounds__(WG) void k_resid_sumsq(DevGeom G, const float* __re
 {
     __shared__ double lds[4];
     extern __shared__ int4 rc[];
-    long long* zo = reinterpret_cast<long long*>(rc + G.N);
-    long long* cand = zo + G.N + threadIdx.x * RES_BATCH;
+    int4* grc = rc + G.N;
+    long long* zo = reinterpret_cast<long long*>(grc + res_groups(G));
+    long long* cand = zo + G.N + threadIdx.x * res_batch(WG);
     const int v = blockIdx.y;
-    stage_rects(G, v, rc, zo);
+    stage_rects(G, v, rc, zo, grc);
     const int per_view = G.nu * G.nv;
     const int ray = blockIdx.x * WG + threadIdx.x;
     double val = 0.0;
     if (ray < per_view) {
-        const float r = resid_ray(G, v, ray % G.nu, ray / G.nu, y, z, rc, zo, cand, per_view, ray);
+        const float r = resid_ray<res_batch(WG)>(G, v, ray % G.nu, ray / G.nu, y, z, rc, zo, grc, cand, per_view, ray);
         val = (double)r * (double)r;
     }
     const double s = block_sum(val, lds);
@@ -1025,7 +1079,7 @@ size_t fp_lds_bytes_for(const DevGeom& G)
     return tile <= FP_LDS_MAX_FLOATS ? (size_t)tile * sizeof(float) : 0;
 }
 
-size_t resid_lds_bytes_for(const DevGeom& G) { return resid_lds_bytes(G.N, RES_WG); }
+size_t resid_lds_bytes_for(const DevGeom& G) { return resid_lds_bytes(G, res_wg(G.dim)); }
 
 static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int dim);
 
@@ -1042,7 +1096,7 @@ void batch_grids(BatchEntry& e)
         e.fp_chunk = 0;
         e.gx[0] = (int)(((int64_t)L.maxv * L.B * std::max(1, G.fp_wpp) + 3) / 4);
     }
-    e.gx[1] = (G.nu * G.nv + RES_WG - 1) / RES_WG;
+    e.gx[1] = (G.nu * G.nv + res_wg(G.dim) - 1) / res_wg(G.dim);
     e.gx[2] = max_tiles(G, nullptr, G.dim);
 }
 
@@ -1065,7 +1119,10 @@ hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], co
         if (e != hipSuccess) return e;
     }
     A.id0 = 0;
-    hipLaunchKernelGGL(k_resid_batch, dim3(wgs[1]), dim3(RES_WG), res_lds, st, A);
+    if (dim == 3)
+        hipLaunchKernelGGL(k_resid_batch<res_wg(3)>, dim3(wgs[1]), dim3(res_wg(3)), res_lds, st, A);
+    else
+        hipLaunchKernelGGL(k_resid_batch<res_wg(2)>, dim3(wgs[1]), dim3(res_wg(2)), res_lds, st, A);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dim == 3)
@@ -1079,8 +1136,13 @@ hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L
                         float* r_sel, hipStream_t st)
 {
     const int per_view = G.nu * G.nv;
-    const unsigned gx = (unsigned)((per_view + RES_WG - 1) / RES_WG);
-    hipLaunchKernelGGL(k_resid, dim3(gx, L.maxv), dim3(RES_WG), resid_lds_bytes(G.N, RES_WG), st, G, sched_it, L, y, z,
+    const int tpb = res_wg(G.dim);
+    const unsigned gx = (unsigned)((per_view + tpb - 1) / tpb);
+    if (G.dim == 3)
+        hipLaunchKernelGGL(k_resid<res_wg(3)>, dim3(gx, L.maxv), dim3(tpb), resid_lds_bytes(G, tpb), st, G, sched_it, L,
+                           y, z, r_sel);
+    else
+        hipLaunchKernelGGL(k_resid<res_wg(2)>, dim3(gx, L.maxv), dim3(tpb), resid_lds_bytes(G, tpb), st, G, sched_it, L, y, z,
                        r_sel);
     return hipGetLastError();
 }
@@ -1143,7 +1205,7 @@ hipError_t launch_resid_sumsq(const DevGeom& G, const float* y, const float* z, 
 {
     const int per_view = G.nu * G.nv;
     const unsigned gx = grid1(per_view);
-    hipLaunchKernelGGL(k_resid_sumsq, dim3(gx, G.n_views), dim3(WG), resid_lds_bytes(G.N, WG), st, G, y, z, partials);
+    hipLaunchKernelGGL(k_resid_sumsq, dim3(gx, G.n_views), dim3(WG), resid_lds_bytes(G, WG), st, G, y, z, partials);
     *n_partials = (int)(gx * G.n_views);
     return hipGetLastError();
 }
