@@ -246,6 +246,8 @@ def main():
     ap.add_argument("--serving-max-epochs", type=int, default=30)
     ap.add_argument("--cone-steps", type=int, default=3,
                     help="epochs of the 3D cone-beam (256^3, TV) measurement reported as 'secondary' (0 = skip)")
+    ap.add_argument("--cone-only", action="store_true",
+                    help="profiling aid: run only the cone-beam measurement and print its object")
     ap.add_argument("--tune", default="auto",
                     help="forward-projector launch shape: 'auto' (autotuner, before the timed region) "
                          "or 'V,S' (views per workgroup, lanes per ray)")
@@ -268,6 +270,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.cone_only:
+        print(json.dumps(cone_bench(max(1, args.cone_steps), 1, max(1, args.cone_steps))), flush=True)
         return
     from bsgd_inputs.configs import workload
     from bsgd_inputs.phantoms import phantom_for, poisson_log_noise

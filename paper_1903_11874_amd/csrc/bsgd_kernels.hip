@@ -22,6 +22,7 @@ namespace {
 
 constexpr int WG = 256;
 constexpr float SHADOW_EPS = 1e-3f;  // candidate-range margin of the voxel shadow, in pixels
+constexpr int BP_AHEAD = 3;          // 2D back projection: candidates whose gathers are issued together
 
 __device__ __forceinline__ void block_dims(const DevGeom& G, const BlockInfo& B, int (&nb)[3], float (&h)[3],
                                            float (&vs)[3])
@@ -198,11 +199,32 @@ __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, fl
     const int khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kc + span + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
     const float4* nrm = G.raynorm + (int64_t)view * G.nu;
     const float4* trp = G.raytrap + (int64_t)view * G.nu;
+    // the first BP_AHEAD candidates' gathers are issued together, each only by the
+    // lanes whose range holds it, then consumed in ascending k; wider ranges continue
+    // in a loop
+    float4 n[BP_AHEAD], t[BP_AHEAD];
+    float r[BP_AHEAD];
+#pragma unroll
+    for (int i = 0; i < BP_AHEAD; ++i) {
+        if (klo + i <= khi) {
+            n[i] = nrm[klo + i];
+            t[i] = trp[klo + i];
+            r[i] = rview[klo + i];
+        }
+    }
     float acc = 0.0f;
-    for (int k = klo; k <= khi; ++k) {
-        const float4 n = nrm[k];
+#pragma unroll
+    for (int i = 0; i < BP_AHEAD; ++i) {
+        if (klo + i <= khi) {
+            const float lam = fmaf((float)(klo + i - P.kc), P.au, P.bu);
+            const float delta = fmaf(n[i].x, qx, fmaf(n[i].y, qy, -(lam * n[i].z)));
+            acc = fmaf(chord_2d(delta, t[i]), r[i], acc);
+        }
+    }
+    for (int k = klo + BP_AHEAD; k <= khi; ++k) {
+        const float4 nk = nrm[k];
         const float lam = fmaf((float)(k - P.kc), P.au, P.bu);
-        const float delta = fmaf(n.x, qx, fmaf(n.y, qy, -(lam * n.z)));
+        const float delta = fmaf(nk.x, qx, fmaf(nk.y, qy, -(lam * nk.z)));
         acc = fmaf(chord_2d(delta, trp[k]), rview[k], acc);
     }
     return acc;
