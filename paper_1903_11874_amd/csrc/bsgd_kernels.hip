@@ -24,6 +24,27 @@ constexpr int WG = 256;
 constexpr float SHADOW_EPS = 1e-3f;  // candidate-range margin of the voxel shadow, in pixels
 constexpr int BP_AHEAD = 3;          // 2D back projection: candidates whose gathers are issued together
 
+// Workgroups go to the 8 XCDs round-robin (workgroup id mod 8), and each XCD has its
+// own L2. Renumbering so that consecutive logical workgroups run on one XCD keeps the
+// workgroups of one column block (same image tile, same work records) in one L2:
+// logical = first logical id of XCD (id mod 8) + (id div 8). A bijection of [0, n).
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_local(int id, int n)
+{
+    const int per = n / N_XCD, rem = n % N_XCD;
+    const int x = id % N_XCD, s = id / N_XCD;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + s;
+}
+
+// The (x, y) of a 2D grid in the renumbered order (x fastest, as dispatched).
+__device__ __forceinline__ void xcd_grid2(int& bx, int& by)
+{
+    const int gx = (int)gridDim.x;
+    const int l = xcd_local((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+    bx = l % gx;
+    by = l / gx;
+}
+
 __device__ __forceinline__ void block_dims(const DevGeom& G, const BlockInfo& B, int (&nb)[3], float (&h)[3],
                                            float (&vs)[3])
 {
@@ -409,7 +430,8 @@ __global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __re
                                                  const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
                                                  float* __restrict__ z)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (WG / 64) + (threadIdx.x >> 6));
+    const int wg = xcd_local((int)blockIdx.x, (int)gridDim.x);
+    const int wave = __builtin_amdgcn_readfirstlane(wg * (WG / 64) + (threadIdx.x >> 6));
     fp_global_body<DIM>(G, work, L, blocks_sel, x, z, wave, threadIdx.x & 63);
 }
 
@@ -518,7 +540,9 @@ __global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* 
 {
     extern __shared__ float xs[];
     __shared__ FpLds sh;
-    fp_lds_body<DIM>(G, work, L, blocks_sel, x, z, chunk, blockIdx.x, blockIdx.y, xs, sh);
+    int bx, by;
+    xcd_grid2(bx, by);
+    fp_lds_body<DIM>(G, work, L, blocks_sel, x, z, chunk, bx, by, xs, sh);
 }
 
 // ------------------------------------------------------------ solver: residual rebuild
@@ -652,7 +676,9 @@ __global__ __launch_bounds__(TPB) void k_resid(DevGeom G, const int32_t* __restr
                                                   float* __restrict__ r_sel)
 {
     extern __shared__ int4 rc[];
-    resid_body<TPB>(G, S_, L, y, z, r_sel, blockIdx.x, blockIdx.y, rc);
+    int bx, by;
+    xcd_grid2(bx, by);
+    resid_body<TPB>(G, S_, L, y, z, r_sel, bx, by, rc);
 }
 
 // ------------------------------------------------------------ solver: back projection + step
@@ -761,7 +787,9 @@ __global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __rest
                                                 long long n_vox)
 {
     __shared__ float part[BP_SPLIT][BP_VOX];
-    bp_step_body<DIM>(G, S_, work, L, r_sel, ghat, gsum, x, mu, n_vox, blockIdx.x, blockIdx.y, part);
+    int bx, by;
+    xcd_grid2(bx, by);
+    bp_step_body<DIM>(G, S_, work, L, r_sel, ghat, gsum, x, mu, n_vox, bx, by, part);
 }
 
 // ------------------------------------------------------------ batched solves
@@ -786,7 +814,7 @@ __global__ __launch_bounds__(WG) void k_fp_batch(const BatchArgs A)
 {
     extern __shared__ float xs[];
     __shared__ FpLds sh;
-    const int id = A.id0 + (int)blockIdx.x;
+    const int id = A.id0 + xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 0, id));
     const BatchEntry& B = A.e[e];
     const int local = id - B.base[0];
@@ -805,7 +833,7 @@ template <int TPB>
 __global__ __launch_bounds__(TPB) void k_resid_batch(const BatchArgs A)
 {
     extern __shared__ int4 rc[];
-    const int id = blockIdx.x;
+    const int id = xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 1, id));
     const BatchEntry& B = A.e[e];
     const int local = id - B.base[1];
@@ -817,7 +845,7 @@ template <int DIM>
 __global__ __launch_bounds__(WG) void k_bp_batch(const BatchArgs A)
 {
     __shared__ float part[BP_SPLIT][BP_VOX];
-    const int id = blockIdx.x;
+    const int id = xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 2, id));
     const BatchEntry& B = A.e[e];
     const int local = id - B.base[2];
