@@ -77,7 +77,30 @@ def schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w)
     return per_it
 
 
-def measure(geom, spec, solver, n_vox, warmup, steps, n_prof):
+def profiled_traffic(workload_name, kernel_key):
+    """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy kernel), or None when the kernel
+    sources changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        src = b"".join(open(os.path.join(ROOT, "paper_1903_11874_amd", "csrc", n), "rb").read()
+                       for n in ("bsgd_kernels.hip", "bsgd_device.h", "bsgd_kernels.h"))
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != t.get("source_sha256"):
+        return None
+    per = t.get("workloads", {}).get(workload_name, {})
+    names = {"back_project_step": ["k_bp_step"], "forward_project": ["k_fp_pairs_lds", "k_fp_pairs"]}[kernel_key]
+    for n in names:
+        if n in per:
+            return per[n]
+    return None
+
+
+def measure(geom, spec, solver, n_vox, warmup, steps, n_prof, workload_name):
     """Warm-up epochs, a timed region of `steps` epochs (captured HIP graphs, no
     events), then an event-timed eager region of `n_prof` epochs for per-kernel
     averages; exact update counts from the schedules; roofline of the dominant kernel."""
@@ -132,7 +155,8 @@ def measure(geom, spec, solver, n_vox, warmup, steps, n_prof):
     alg_bytes = bytes_fp if dominant == "forward_project" else bytes_bp
     achieved = alg_bytes / (avg_ms[dominant] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(workload_name, dominant),
+                "traffic_unit": "bytes per dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms[dominant]}
 
     return {"elapsed": elapsed, "value": value, "updates": updates, "roofline": roofline,
@@ -160,7 +184,7 @@ def cone_bench(steps, warmup, n_prof):
     x = torch.zeros(n_vox, dtype=torch.float32, device="cuda")
     solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed, tv_lambda=wl.solver.tv_lambda,
                     tv_inner_iters=wl.solver.tv_inner_iters)
-    m = measure(geom, spec, solver, n_vox, warmup, steps, n_prof)
+    m = measure(geom, spec, solver, n_vox, warmup, steps, n_prof, wl.name)
     T = solver.epoch_iters
     return {"workload": wl.description, "metric": "FP+BP ray-voxel updates/s", "value": m["value"],
             "unit": "updates/s", "steps": steps, "ms_per_step": m["elapsed"] / steps * 1e3,
@@ -308,7 +332,7 @@ def main():
     log(f"alpha M = {solver.rows_per_iter}, gamma N = {solver.blocks_per_iter}, epoch = {T} iterations")
 
     m = measure(geom, spec, solver, n_vox, args.warmup, args.steps,
-                args.profile_steps if args.profile_steps > 0 else args.steps)
+                args.profile_steps if args.profile_steps > 0 else args.steps, wl.name)
     elapsed, value, updates, roofline, avg_ms, times = (m["elapsed"], m["value"], m["updates"], m["roofline"],
                                                         m["kernels_avg_ms"], m["times"])
     r0, r1, n_prof, t2, t3 = m["r0"], m["r1"], m["n_prof"], m["t2"], m["t3"]
