@@ -180,7 +180,12 @@ bsgd_status bsgd_back_project(const bsgd_geometry* geom, const float* y, float* 
  *   consecutive EUDs and ||r|| = ||y - sum_j z^j||; once three norms and two thetas
  *   exist: three decreasing norms -> mu *= 1 + eps; three increasing norms and
  *   (|theta - theta_prev| > t1 or theta < t2) -> mu *= 1 - delta. Costs one
- *   synchronisation every M iterations; not available in bsgd_step_batch. */
+ *   synchronisation every M iterations; not available in bsgd_step_batch.
+ * im_until: with importance sampling (Algorithm 2), only iterations k < im_until draw
+ *   sub-detectors; iterations k >= im_until use every ray of the selected row blocks
+ *   (plain Algorithm 1), the unbiased tail Sec. II-A recommends for the last iterations
+ *   (sampled g_hat entries bias the fixed point; the plain tail converges to the
+ *   least-squares solution). 0 = sample in every iteration. */
 typedef struct {
     int32_t rows_per_iter;
     int32_t blocks_per_iter;
@@ -195,7 +200,7 @@ typedef struct {
     int32_t check_every;
     int32_t flags;                /* BSGD_FLAG_* */
     int32_t auto_mu;              /* 1: automatic step length (Algorithm 3) */
-    int32_t reserved;
+    int32_t im_until;             /* first iteration without importance sampling; 0 = none */
     double mu_eps, mu_delta;      /* Algorithm 3 epsilon, delta; 0 = 0.05, 0.4 */
     double mu_t1, mu_t2;          /* Algorithm 3 thresholds t1, t2; 0 = 0.1, 0.5 */
 } bsgd_options;

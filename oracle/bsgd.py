@@ -173,9 +173,13 @@ def rows_for_pair(p: Problem, i: int, j: int, k: int, seed: int, q, draws_out=No
 
 def iterate(p: Problem, st: State, y: np.ndarray, mu: float, rows_per_iter: int,
             blocks_per_iter: int, seed: int, q=None, tv_lambda: float = 0.0,
-            tv_iters: int = 20, trace: Optional[list] = None):
-    """One BSGD iteration (Algorithm 1 / 2 / 4) in place on ``st``."""
+            tv_iters: int = 20, trace: Optional[list] = None, im_until: Optional[int] = None):
+    """One BSGD iteration (Algorithm 1 / 2 / 4) in place on ``st``. With ``im_until``,
+    iterations k >= im_until run without importance sampling (all rays of the selected
+    row blocks): the unbiased tail that Sec. II-A recommends for the last iterations."""
     k = st.k
+    if im_until is not None and k >= im_until:
+        q = None
     R = rng.choose(seed, rng.STREAM_ROWS, k, p.M, rows_per_iter)
     C = rng.choose(seed, rng.STREAM_BLOCKS, k, p.N, blocks_per_iter)
     draws = {} if trace is not None else None
@@ -228,13 +232,14 @@ class AutoMu:
 
 def run(p: Problem, y: np.ndarray, mu: float, rows_per_iter: int, blocks_per_iter: int,
         n_iters: int, seed: int, q=None, x0=None, tv_lambda: float = 0.0, tv_iters: int = 20,
-        trace: Optional[list] = None, callback=None, auto_mu: Optional[AutoMu] = None) -> State:
+        trace: Optional[list] = None, callback=None, auto_mu: Optional[AutoMu] = None,
+        im_until: Optional[int] = None) -> State:
     st = initial_state(p, y, x0)
     eud = np.zeros(p.A.shape[1])
     prev_eud = None
     r_hist, theta_hist = [], []
     for _ in range(n_iters):
-        iterate(p, st, y, mu, rows_per_iter, blocks_per_iter, seed, q, tv_lambda, tv_iters, trace)
+        iterate(p, st, y, mu, rows_per_iter, blocks_per_iter, seed, q, tv_lambda, tv_iters, trace, im_until)
         if auto_mu is not None:
             eud += st.gsum
             if st.k % p.M == 0:

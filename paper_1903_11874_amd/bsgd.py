@@ -61,7 +61,7 @@ class Options(ctypes.Structure):
         ("tv_inner_iters", ctypes.c_int32), ("mu", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("tv_lambda", ctypes.c_double), ("tv_every", ctypes.c_int32), ("max_effective_epochs", ctypes.c_int32),
         ("tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("flags", ctypes.c_int32),
-        ("auto_mu", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mu_eps", ctypes.c_double),
+        ("auto_mu", ctypes.c_int32), ("im_until", ctypes.c_int32), ("mu_eps", ctypes.c_double),
         ("mu_delta", ctypes.c_double), ("mu_t1", ctypes.c_double), ("mu_t2", ctypes.c_double),
     ]
 
@@ -289,13 +289,14 @@ FLAG_EAGER = 1
 
 def make_options(rows_per_iter=0, blocks_per_iter=0, node_count=0, mu=0.0, seed=0, tv_lambda=0.0,
                  tv_inner_iters=20, tv_every=0, max_effective_epochs=0, tol=0.0, check_every=0,
-                 eager=False, auto_mu=False, mu_eps=0.0, mu_delta=0.0, mu_t1=0.0, mu_t2=0.0) -> Options:
+                 eager=False, auto_mu=False, mu_eps=0.0, mu_delta=0.0, mu_t1=0.0, mu_t2=0.0,
+                 im_until=0) -> Options:
     o = Options()
     o.rows_per_iter, o.blocks_per_iter, o.node_count = rows_per_iter, blocks_per_iter, node_count
     o.tv_inner_iters, o.mu, o.seed, o.tv_lambda, o.tv_every = tv_inner_iters, mu, seed, tv_lambda, tv_every
     o.max_effective_epochs, o.tol, o.check_every = max_effective_epochs, tol, check_every
     o.flags = FLAG_EAGER if eager else 0
-    o.auto_mu, o.reserved = (1 if auto_mu else 0), 0
+    o.auto_mu, o.im_until = (1 if auto_mu else 0), int(im_until)
     o.mu_eps, o.mu_delta, o.mu_t1, o.mu_t2 = mu_eps, mu_delta, mu_t1, mu_t2
     return o
 

@@ -856,6 +856,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     if (o->tv_lambda > 0 && o->tv_inner_iters < 1) return fail(BSGD_E_INVALID_ARG, "tv_inner_iters must be >= 1");
     if (o->tv_every < 0 || o->max_effective_epochs < 0 || o->check_every < 0 || !(o->tol >= 0.0))
         return fail(BSGD_E_INVALID_ARG, "negative option");
+    if (o->im_until < 0) return fail(BSGD_E_INVALID_ARG, "im_until must be >= 0");
     if (o->auto_mu && (!(o->mu_eps >= 0) || !(o->mu_delta >= 0 && o->mu_delta < 1) || !(o->mu_t1 >= 0) ||
                        !(o->mu_t2 >= 0) || !(o->mu > 0)))
         return fail(BSGD_E_INVALID_ARG, "auto_mu needs mu > 0, eps >= 0, 0 <= delta < 1, t1, t2 >= 0");
@@ -990,7 +991,8 @@ static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32
 {
     const bsgd_geometry* g = s->g;
     hipError_t e = timed(s, KID_DRAW, [&] {
-        return launch_plan(g->dg, dsched, s->L, n_iters, s->o.seed, s->im ? g->d_q.as<uint32_t>() : nullptr, ddraws,
+        return launch_plan(g->dg, dsched, s->L, n_iters, s->o.seed, s->im ? g->d_q.as<uint32_t>() : nullptr,
+                           (int64_t)s->o.im_until, ddraws,
                            dwork, st);
     });
     if (e != hipSuccess) return e;
@@ -1201,7 +1203,7 @@ static bsgd_status prepare_iterations(bsgd_solver* s, int n_iters, hipStream_t s
     s->last_n = n_iters;
     HIP_TRY(s->stage.upload(s->sched.p, sched_bytes, st));
     HIP_TRY(launch_plan(g->dg, s->sched.as<int32_t>(), s->L, n_iters, s->o.seed,
-                        s->im ? g->d_q.as<uint32_t>() : nullptr, s->im ? s->draws.as<int8_t>() : nullptr,
+                        s->im ? g->d_q.as<uint32_t>() : nullptr, (int64_t)s->o.im_until, s->im ? s->draws.as<int8_t>() : nullptr,
                         s->work.as<PairWork>(), st));
     return BSGD_OK;
 }

@@ -90,7 +90,7 @@ hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStrea
 // iterations: draws [n][maxv][B] (may be NULL), work [n][B][maxv]. The iteration
 // counter of each record is read from the schedule.
 hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, uint64_t seed,
-                       const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st);
+                       const uint32_t* q, int64_t im_until, int8_t* draws, PairWork* work, hipStream_t st);
 
 // blocks_sel: the iteration's selected blocks (device, inside its schedule record).
 hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,

@@ -308,8 +308,8 @@ __global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict
 // export; records [it][block slot][view slot] so that a block's views are contiguous.
 __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restrict__ sched, SchedLayout L,
                                              int n_iters, unsigned long long seed,
-                                             const uint32_t* __restrict__ q, int8_t* __restrict__ draws,
-                                             PairWork* __restrict__ work)
+                                             const uint32_t* __restrict__ q, long long im_until,
+                                             int8_t* __restrict__ draws, PairWork* __restrict__ work)
 {
     const int64_t per_it = (int64_t)L.maxv * L.B;
     const int64_t gid = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -333,7 +333,8 @@ __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restric
         const int v = S_[L.off_views() + a];
         const int j = S_[L.off_blocks() + b];
         int sd = -2;
-        if (q) {
+        const uint64_t kit = (uint64_t)(uint32_t)S_[L.off_k()] | ((uint64_t)(uint32_t)S_[L.off_k() + 1] << 32);
+        if (q && (im_until <= 0 || (long long)kit < im_until)) {
             unsigned long long total = 0;
             for (int t = 0; t < G.S; ++t) total += q[((int64_t)v * G.S + t) * G.N + j];
             sd = DRAW_SKIP;
@@ -352,6 +353,8 @@ __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restric
                 }
             }
             dr = (int8_t)sd;
+        } else if (q) {
+            dr = (int8_t)-2;  // unbiased tail: every ray of the view
         }
         if (sd != DRAW_SKIP) {
             const PairInfo P = G.pairs[(int64_t)v * G.N + j];
@@ -1082,12 +1085,12 @@ hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStrea
 }
 
 hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, uint64_t seed,
-                       const uint32_t* q, int8_t* draws, PairWork* work, hipStream_t st)
+                       const uint32_t* q, int64_t im_until, int8_t* draws, PairWork* work, hipStream_t st)
 {
     const int64_t n = (int64_t)n_iters * L.maxv * L.B;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_plan, dim3(grid1(n)), dim3(WG), 0, st, G, sched, L, n_iters, (unsigned long long)seed, q,
-                       draws, work);
+                       (long long)im_until, draws, work);
     return hipGetLastError();
 }
 

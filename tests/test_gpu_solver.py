@@ -28,7 +28,7 @@ def _mu(A, scale):
     return float(np.float32(scale / (2.0 * lipschitz(A))))
 
 
-def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed=3):
+def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed=3, im_until=0):
     import torch
     from paper_1903_11874_amd import Geometry, Solver
     dev = require_gpu()
@@ -37,23 +37,26 @@ def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed
     mu = _mu(A, mu_scale)
     q = im_table(p, im) if im else None
     trace = []
-    st = run(p, y64, mu, R, B, n_iter, seed, q=q, tv_lambda=tv_lambda, trace=trace)
+    st = run(p, y64, mu, R, B, n_iter, seed, q=q, tv_lambda=tv_lambda, trace=trace, im_until=im_until or None)
     geom = Geometry(g.with_(im_mode=im or "none"), im_table=q)
     yd = torch.tensor(y32, device=dev)
     xd = torch.zeros(A.shape[1], dtype=torch.float32, device=dev)
     solver = Solver(geom, yd, xd, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=seed, tv_lambda=tv_lambda,
-                    tv_inner_iters=20)
+                    tv_inner_iters=20, im_until=im_until)
     rn = solver.step(n_iter, residual=True)
     return p, st, trace, solver, xd, rn
 
 
-def _check_schedule(p, trace, solver):
+def _check_schedule(p, trace, solver, tail_from=None):
     rows, blocks, draws = solver.last_schedule()
     assert rows.shape[0] == len(trace)
     for it, t in enumerate(trace):
         assert list(rows[it]) == t["rows"], it
         assert list(blocks[it]) == t["blocks"], it
-        if t["draws"]:
+        if tail_from is not None and it >= tail_from:
+            n_views = sum(len(p.groups[i]) for i in t["rows"])
+            assert np.all(draws[it, :n_views, :] == -2), it  # every ray, no sampling
+        elif t["draws"]:
             views = [v for i in t["rows"] for v in p.groups[i]]
             for a, v in enumerate(views):
                 for b, j in enumerate(t["blocks"]):
@@ -66,6 +69,17 @@ def test_trajectory_plain(name, R, B):
     log(f"trajectory plain {name} R={R} B={B}")
     p, st, trace, solver, xd, rn = _pair(SMALL[name], 60, R, B, seed=7)
     _check_schedule(p, trace, solver)
+    assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
+    assert abs(rn - np.linalg.norm(st.r)) <= TOL * np.linalg.norm(st.r)
+
+
+@pytest.mark.parametrize("name", ["fan", "cone"])
+def test_trajectory_importance_sampled_unbiased_tail(name):
+    """Importance sampling for the first 20 iterations, every ray afterwards (the
+    unbiased tail): same iterates and draws as the oracle."""
+    log(f"trajectory IM + unbiased tail {name}")
+    p, st, trace, solver, xd, rn = _pair(SMALL[name], 45, 2, 3, seed=13, im="colnorm", im_until=20)
+    _check_schedule(p, trace, solver, tail_from=20)
     assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
     assert abs(rn - np.linalg.norm(st.r)) <= TOL * np.linalg.norm(st.r)
 

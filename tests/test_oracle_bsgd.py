@@ -165,3 +165,24 @@ def test_auto_mu_shrinks_a_diverging_step_and_grows_a_small_one():
     assert small.mu_history[-1] > 0.02 / (2 * L)         # steady decrease grows the step
     # no change before three residual norms and two thetas exist (k < 3M)
     assert small.mu_history[0] == small.mu_history[1] == 0.02 / (2 * L)
+
+
+def test_unbiased_tail_removes_the_importance_sampling_bias():
+    """Sec. II-A: importance sampling biases BSGD (g_hat holds gradients over the sampled
+    rows only), so its iterates stall short of the least-squares solution; running the
+    last iterations without sampling (im_until) restores convergence to it."""
+    p = _e1_problem(M=4, bx=2, by=2, su=3, im="colnorm")
+    r = np.random.Generator(np.random.PCG64(5))
+    y = p.A @ r.uniform(size=p.A.shape[1]) + 0.01 * r.normal(size=p.A.shape[0])
+    x_lsq = np.linalg.lstsq(p.A.toarray(), y, rcond=None)[0]
+    q = im_table(p, "colnorm")
+    mu = 0.5 / (2 * lipschitz(p.A))
+    im_only, tail = [], []
+    run(p, y, mu, 1, 2, 6000, seed=3, q=q,
+        callback=lambda st: im_only.append(ds(st.x, x_lsq)) if st.k % 1500 == 0 else None)
+    run(p, y, mu, 1, 2, 6000, seed=3, q=q, im_until=3000,
+        callback=lambda st: tail.append(ds(st.x, x_lsq)) if st.k % 1500 == 0 else None)
+    assert im_only[:2] == tail[:2]                   # identical until the switch
+    assert im_only[3] > 0.5 * im_only[2]             # sampling alone has nearly stalled
+    assert tail[3] < 0.25 * im_only[3]               # the plain tail keeps converging
+    assert tail[3] < 0.5 * tail[2]
