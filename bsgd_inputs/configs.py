@@ -176,3 +176,27 @@ SERVING_SIDES = (128, 256, 384, 512, 768, 1024)
 
 def workload(name: str) -> Workload:
     return WORKLOADS[name]
+
+
+# The paper's 2D convergence-study setups (Sec. III-A to III-D and the TV comparison of
+# Sec. III-E), with image and detector pixels of size 1 as the paper states for its 2D work.
+STUDY_2D = {
+    # 16x16 image, source and detector both 50 from the centre, 30 bins, 10 degree steps
+    # over a full turn: A is 1080 x 256. Data SNR 17.5 dB.
+    "e1": dict(nx=16, n_views=36, angle_span=2 * math.pi, nu=30, sod=50.0, sdd=100.0,
+               n_shapes=6, phantom_seed=5, snr_db=17.5, noise_seed=8),
+    # 64x64 image, source and detector both 100 from the centre, 180 bins, 1 degree steps
+    # over half a turn: A is 32400 x 4096. Data SNR 28.8 dB.
+    "e6": dict(nx=64, n_views=180, angle_span=math.pi, nu=180, sod=100.0, sdd=200.0,
+               n_shapes=10, phantom_seed=21, snr_db=28.8, noise_seed=8),
+}
+
+
+def study_geometry(name: str, n_row_blocks: int, bx: int, by: int,
+                   partition_seed: int = 3) -> GeometrySpec:
+    """Fan-beam geometry of a 2D study setup cut into n_row_blocks x (bx by) blocks."""
+    d = STUDY_2D[name]
+    return GeometrySpec(kind="fan2d", nx=d["nx"], ny=d["nx"], nz=1, vx=1.0, vy=1.0, vz=1.0,
+                        n_views=d["n_views"], angle_span=d["angle_span"], nu=d["nu"], nv=1,
+                        du=1.0, dv=1.0, sod=d["sod"], sdd=d["sdd"], bx=bx, by=by, bz=1,
+                        n_row_blocks=n_row_blocks, partition_seed=partition_seed)

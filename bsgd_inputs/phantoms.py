@@ -118,6 +118,14 @@ def add_gaussian_noise(y: np.ndarray, rel_sigma: float, seed: int) -> np.ndarray
     return y + rng.normal(0.0, sigma, size=y.shape)
 
 
+def add_gaussian_noise_snr(y: np.ndarray, snr_db: float, seed: int) -> np.ndarray:
+    """y + e with white Gaussian e scaled so that 20 log10(||y|| / ||e||) = snr_db."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    e = rng.normal(size=y.shape)
+    e *= np.linalg.norm(y) / (np.linalg.norm(e) * 10.0 ** (snr_db / 20.0))
+    return y + e
+
+
 def poisson_log_noise(y: np.ndarray, incident: float, seed: int) -> np.ndarray:
     """Transmission noise on line integrals y.
 

@@ -62,3 +62,32 @@ def oracle_matrix(g: GeometrySpec):
 def oracle_problem(g: GeometrySpec):
     from oracle.bsgd import Problem
     return Problem.build(g, oracle_matrix(g))
+
+
+@functools.lru_cache(maxsize=4)
+def oracle_study(name: str):
+    """A 2D study setup of the paper on the oracle: (problem with one block, y, x_true,
+    x_lsq, ||A||_2^2), y = A x_true + white noise at the setup's data SNR; x_lsq (dense
+    least squares) only for the 16x16 setup, else None."""
+    from bsgd_inputs.configs import STUDY_2D, study_geometry
+    from bsgd_inputs.phantoms import add_gaussian_noise_snr, ellipse_phantom_2d
+    from oracle.bsgd import lipschitz
+    d = STUDY_2D[name]
+    p = oracle_problem(study_geometry(name, 1, 1, 1))
+    x_true = ellipse_phantom_2d(d["nx"], d["nx"], d["n_shapes"], d["phantom_seed"]).ravel()
+    y = add_gaussian_noise_snr(p.A @ x_true, d["snr_db"], d["noise_seed"])
+    x_lsq = np.linalg.lstsq(p.A.toarray(), y, rcond=None)[0] if name == "e1" else None
+    return p, y, x_true, x_lsq, lipschitz(p.A)
+
+
+def oracle_ds_curve(p, y, x_lsq, R, B, mu, n_products, n_points=8, seed=1, **kw):
+    """The oracle's DS = ||x - x_lsq|| at n_points equally spaced iteration counts, as
+    (products, DS) pairs; 2 R B products per iteration."""
+    from oracle.bsgd import ds, run
+    per = 2 * R * B
+    iters = max(n_products // per, n_points)
+    marks = {round(iters * (i + 1) / n_points) for i in range(n_points)}
+    out = []
+    run(p, y, mu, R, B, iters, seed=seed, callback=lambda st: out.append((st.k * per, ds(st.x, x_lsq)))
+        if st.k in marks else None, **kw)
+    return out
