@@ -174,7 +174,7 @@ bsgd_status bsgd_back_project(const bsgd_geometry* geom, const float* y, float* 
  *   (one epoch = round(1/(alpha gamma)) iterations), or earlier when tol > 0 and the
  *   relative normal-equation residual ||A^T(y - A x)|| / ||A^T y|| <= tol, checked
  *   every check_every epochs (0 = every epoch).
- * flags: BSGD_FLAG_EAGER (below).
+ * flags: BSGD_FLAG_EAGER, BSGD_FLAG_SUBDET_MEMORY (below); other bits are rejected.
  * auto_mu: Algorithm 3 (Sec. II-A). Every M iterations the g of the last M iterations
  *   are summed into an effective update direction (EUD), theta is the cosine of two
  *   consecutive EUDs and ||r|| = ||y - sum_j z^j||; once three norms and two thetas
@@ -209,6 +209,18 @@ typedef struct {
  * effective epoch (graphs are used when a bsgd_step call covers whole epochs from an
  * epoch boundary and per-kernel profiling is off). Results are identical. */
 #define BSGD_FLAG_EAGER 1
+
+/* Keep the gradient memory per (view, sub-detector, column block) instead of per
+ * (row block, column block) (the unbiased form of Algorithm 2, Sec. II-A). A pair
+ * refreshes the memories of the (view, sub-detector) parts whose rays it used, and
+ * g is the sum of all memories; without importance sampling the iterates equal
+ * Algorithm 1's (a row block's part memories sum to its g_hat). With sampling, a
+ * drawn sub-detector no longer stands for its whole view, so at a fixed point g is
+ * the full gradient 2 A^T (y - A x) and the iteration reaches the least-squares
+ * solution. Stored as each ray's residual at its last refresh (z layout, z_floats
+ * floats, plus as many for the changes) instead of the M x c floats of g_hat.
+ * Not available in bsgd_step_batch. */
+#define BSGD_FLAG_SUBDET_MEMORY 2
 
 /* Create a solver for y (device [n_views][nv][nu], must stay valid and unchanged while
  * the solver lives) and x (device [nz][ny][nx], the initial image, updated in place by
@@ -256,7 +268,10 @@ bsgd_status bsgd_solver_counts(const bsgd_solver* s, int64_t* iters_done, int32_
 bsgd_status bsgd_solver_last_schedule(const bsgd_solver* s, int32_t* n_out, int32_t* rows,
                                       int32_t* blocks, int16_t* draws, size_t draws_bytes);
 
-/* Copy solver state to caller device memory: which = 0 g [c], 1 g_hat [M][c], 2 z (compact, z_floats). */
+/* Copy solver state to caller device memory: which = 0 g [c], 1 g_hat [M][c], 2 z (compact,
+ * z_floats), 3 the residual snapshots of BSGD_FLAG_SUBDET_MEMORY (z layout, z_floats; the
+ * memory of (view, sub-detector, block) is 2 (A_part^J)^T of its part of them). Asking for
+ * g_hat with that flag, or for 3 without it, is BSGD_E_INVALID_ARG. */
 bsgd_status bsgd_solver_state(const bsgd_solver* s, int32_t which, float* out, size_t bytes);
 
 /* Per-kernel time accounting with HIP events on the solver's stream (off by default).

@@ -148,6 +148,7 @@ class State:
     gsum: np.ndarray    # [c]
     r: np.ndarray       # [r]
     k: int = 0
+    mem: Optional[np.ndarray] = None   # [views][S][c] per-sub-detector gradient memory
 
 
 def initial_state(p: Problem, y: np.ndarray, x0: Optional[np.ndarray] = None) -> State:
@@ -157,40 +158,72 @@ def initial_state(p: Problem, y: np.ndarray, x0: Optional[np.ndarray] = None) ->
                  r=np.array(y, dtype=np.float64))
 
 
-def rows_for_pair(p: Problem, i: int, j: int, k: int, seed: int, q, draws_out=None):
+def parts_for_pair(p: Problem, i: int, j: int, k: int, seed: int, q, draws_out=None):
+    """The rays of row block i that pair (i, j) uses at iteration k, as ((view,
+    sub-detector), rays) parts: every sub-detector of every view without sampling,
+    one drawn sub-detector per view with it (Algorithm 2), none for a view whose
+    weights are all zero."""
     g = p.g
-    if q is None:
-        return geo.rays_of_group(g, p.groups[i])
     parts = []
     for v in p.groups[i]:
-        s = draw_subdetector(seed, k, v, j, q[v, :, j])
-        if draws_out is not None:
-            draws_out[(v, j)] = s
-        if s >= 0:
-            parts.append(geo.subdetector_rays(g, v, s))
+        if q is None:
+            subs = range(g.su * g.sv)
+        else:
+            s = draw_subdetector(seed, k, v, j, q[v, :, j])
+            if draws_out is not None:
+                draws_out[(v, j)] = s
+            subs = [s] if s >= 0 else []
+        for s in subs:
+            parts.append(((v, s), geo.subdetector_rays(g, v, s)))
+    return parts
+
+
+def rows_for_pair(p: Problem, i: int, j: int, k: int, seed: int, q, draws_out=None):
+    if q is None:
+        return geo.rays_of_group(p.g, p.groups[i])
+    parts = [rows for _, rows in parts_for_pair(p, i, j, k, seed, q, draws_out)]
     return np.concatenate(parts) if parts else np.zeros(0, dtype=np.int64)
 
 
 def iterate(p: Problem, st: State, y: np.ndarray, mu: float, rows_per_iter: int,
             blocks_per_iter: int, seed: int, q=None, tv_lambda: float = 0.0,
-            tv_iters: int = 20, trace: Optional[list] = None, im_until: Optional[int] = None):
+            tv_iters: int = 20, trace: Optional[list] = None, im_until: Optional[int] = None,
+            subdet_memory: bool = False):
     """One BSGD iteration (Algorithm 1 / 2 / 4) in place on ``st``. With ``im_until``,
     iterations k >= im_until run without importance sampling (all rays of the selected
-    row blocks): the unbiased tail that Sec. II-A recommends for the last iterations."""
+    row blocks): the unbiased tail that Sec. II-A recommends for the last iterations.
+
+    With ``subdet_memory`` the gradient memory is kept per (view, sub-detector, column
+    block) instead of per (row block, column block): a pair refreshes the memories of
+    the (view, sub-detector) parts it used, 2 (A_part^J)^T r_part, and g is the sum of
+    all memories. Without sampling this is Algorithm 1 (the memories of a row block's
+    parts sum to its g_hat); with sampling, a drawn sub-detector no longer replaces the
+    whole row block's gradient, so g at a fixed point is the full gradient (unbiased IM)."""
     k = st.k
     if im_until is not None and k >= im_until:
         q = None
     R = rng.choose(seed, rng.STREAM_ROWS, k, p.M, rows_per_iter)
     C = rng.choose(seed, rng.STREAM_BLOCKS, k, p.N, blocks_per_iter)
     draws = {} if trace is not None else None
-    pairs = [(i, j, rows_for_pair(p, i, j, k, seed, q, draws)) for i in R for j in C]
+    pairs = [(i, j, parts_for_pair(p, i, j, k, seed, q, draws)) for i in R for j in C]
+    pairs = [(i, j, parts, geo.rays_of_group(p.g, p.groups[i]) if q is None else
+              np.concatenate([r for _, r in parts]) if parts else np.zeros(0, dtype=np.int64))
+             for i, j, parts in pairs]
     x_frozen = st.x.copy()
-    for i, j, rows in pairs:
+    for i, j, _, rows in pairs:
         st.z[j][rows] = p.A_cols[j][rows] @ x_frozen[p.blocks[j]]
     st.r = y - st.z.sum(axis=0)
-    for i, j, rows in pairs:
-        st.ghat[i][p.blocks[j]] = 2.0 * (p.A_cols[j][rows].T @ st.r[rows])
-    st.gsum = st.ghat.sum(axis=0)
+    if subdet_memory:
+        if st.mem is None:
+            st.mem = np.zeros((p.g.n_views, p.g.su * p.g.sv, p.A.shape[1]))
+        for i, j, parts, _ in pairs:
+            for (v, s), rows in parts:
+                st.mem[v, s, p.blocks[j]] = 2.0 * (p.A_cols[j][rows].T @ st.r[rows])
+        st.gsum = st.mem.sum(axis=(0, 1))
+    else:
+        for i, j, _, rows in pairs:
+            st.ghat[i][p.blocks[j]] = 2.0 * (p.A_cols[j][rows].T @ st.r[rows])
+        st.gsum = st.ghat.sum(axis=0)
     for j in C:
         st.x[p.blocks[j]] += mu * st.gsum[p.blocks[j]]
     st.k += 1
@@ -233,13 +266,14 @@ class AutoMu:
 def run(p: Problem, y: np.ndarray, mu: float, rows_per_iter: int, blocks_per_iter: int,
         n_iters: int, seed: int, q=None, x0=None, tv_lambda: float = 0.0, tv_iters: int = 20,
         trace: Optional[list] = None, callback=None, auto_mu: Optional[AutoMu] = None,
-        im_until: Optional[int] = None) -> State:
+        im_until: Optional[int] = None, subdet_memory: bool = False) -> State:
     st = initial_state(p, y, x0)
     eud = np.zeros(p.A.shape[1])
     prev_eud = None
     r_hist, theta_hist = [], []
     for _ in range(n_iters):
-        iterate(p, st, y, mu, rows_per_iter, blocks_per_iter, seed, q, tv_lambda, tv_iters, trace, im_until)
+        iterate(p, st, y, mu, rows_per_iter, blocks_per_iter, seed, q, tv_lambda, tv_iters, trace, im_until,
+                subdet_memory)
         if auto_mu is not None:
             eud += st.gsum
             if st.k % p.M == 0:

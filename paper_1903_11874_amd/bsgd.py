@@ -285,17 +285,18 @@ class Geometry:
 
 
 FLAG_EAGER = 1
+FLAG_SUBDET_MEMORY = 2
 
 
 def make_options(rows_per_iter=0, blocks_per_iter=0, node_count=0, mu=0.0, seed=0, tv_lambda=0.0,
                  tv_inner_iters=20, tv_every=0, max_effective_epochs=0, tol=0.0, check_every=0,
                  eager=False, auto_mu=False, mu_eps=0.0, mu_delta=0.0, mu_t1=0.0, mu_t2=0.0,
-                 im_until=0) -> Options:
+                 im_until=0, subdet_memory=False) -> Options:
     o = Options()
     o.rows_per_iter, o.blocks_per_iter, o.node_count = rows_per_iter, blocks_per_iter, node_count
     o.tv_inner_iters, o.mu, o.seed, o.tv_lambda, o.tv_every = tv_inner_iters, mu, seed, tv_lambda, tv_every
     o.max_effective_epochs, o.tol, o.check_every = max_effective_epochs, tol, check_every
-    o.flags = FLAG_EAGER if eager else 0
+    o.flags = (FLAG_EAGER if eager else 0) | (FLAG_SUBDET_MEMORY if subdet_memory else 0)
     o.auto_mu, o.im_until = (1 if auto_mu else 0), int(im_until)
     o.mu_eps, o.mu_delta, o.mu_t1, o.mu_t2 = mu_eps, mu_delta, mu_t1, mu_t2
     return o
@@ -365,9 +366,10 @@ class Solver:
 
     def state(self, which: str):
         import torch
-        idx = {"g": 0, "ghat": 1, "z": 2}[which]
+        idx = {"g": 0, "ghat": 1, "z": 2, "rho": 3}[which]
         g = self.geom.spec
-        n = {0: g.nx * g.ny * g.nz, 1: g.n_row_blocks * g.nx * g.ny * g.nz, 2: self.geom.info["z_floats"]}[idx]
+        n = {0: g.nx * g.ny * g.nz, 1: g.n_row_blocks * g.nx * g.ny * g.nz, 2: self.geom.info["z_floats"],
+             3: self.geom.info["z_floats"]}[idx]
         out = torch.empty(max(n, 1), device=self.x.device, dtype=torch.float32)
         _check(load_library().bsgd_solver_state(self._h, idx, _dev_ptr(out), out.numel() * 4))
         return out[:n]

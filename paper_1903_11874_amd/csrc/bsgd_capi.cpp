@@ -745,9 +745,10 @@ struct bsgd_solver {
     hipStream_t st = nullptr;
     int R = 1, B = 1, T = 1, tv_every = 1, maxv = 1;
     int64_t k = 0;
-    bool failed = false, im = false;
+    bool failed = false, im = false, subdet = false;
     SchedLayout L{};
     DevBuf z, ghat, gsum, r_sel, sched, draws, work, partials, norm_out, tv_p, tv_a, tv_b;
+    DevBuf rho, delta;  // sub-detector memory: residual snapshots and their changes (z layout)
     int sched_cap = 0;
     Staging stage;
     // one captured epoch (T iterations) replayed per epoch
@@ -857,6 +858,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     if (o->tv_every < 0 || o->max_effective_epochs < 0 || o->check_every < 0 || !(o->tol >= 0.0))
         return fail(BSGD_E_INVALID_ARG, "negative option");
     if (o->im_until < 0) return fail(BSGD_E_INVALID_ARG, "im_until must be >= 0");
+    if (o->flags & ~(BSGD_FLAG_EAGER | BSGD_FLAG_SUBDET_MEMORY)) return fail(BSGD_E_INVALID_ARG, "unknown flag");
     if (o->auto_mu && (!(o->mu_eps >= 0) || !(o->mu_delta >= 0 && o->mu_delta < 1) || !(o->mu_t1 >= 0) ||
                        !(o->mu_t2 >= 0) || !(o->mu > 0)))
         return fail(BSGD_E_INVALID_ARG, "auto_mu needs mu > 0, eps >= 0, 0 <= delta < 1, t1, t2 >= 0");
@@ -878,6 +880,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     s->L.maxv = s->maxv;
     s->L.stride = SchedLayout::stride_for(R, B, s->maxv);
     s->graphs = (o->flags & BSGD_FLAG_EAGER) == 0;
+    s->subdet = (o->flags & BSGD_FLAG_SUBDET_MEMORY) != 0;
     const int64_t per_view = (int64_t)g->d.nu * g->d.nv;
     auto cleanup = [&](bsgd_status e) {
         delete s;
@@ -891,7 +894,12 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
                                 hipGetErrorString(e_)));                                           \
     } while (0)
     S_TRY(s->z.alloc((size_t)g->z_floats * sizeof(float)));
-    S_TRY(s->ghat.alloc((size_t)g->M * g->n_vox * sizeof(float)));
+    if (s->subdet) {
+        S_TRY(s->rho.alloc((size_t)g->z_floats * sizeof(float)));
+        S_TRY(s->delta.alloc((size_t)g->z_floats * sizeof(float)));
+    } else {
+        S_TRY(s->ghat.alloc((size_t)g->M * g->n_vox * sizeof(float)));
+    }
     S_TRY(s->gsum.alloc((size_t)g->n_vox * sizeof(float)));
     S_TRY(s->r_sel.alloc((size_t)s->maxv * per_view * sizeof(float)));
     const int n_part = (int)(((per_view + 255) / 256) * g->d.n_views);
@@ -921,7 +929,10 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
         S_TRY(s->tv_b.alloc(nb));
     }
     S_TRY(launch_fill(s->z.as<float>(), 0.0f, g->z_floats, st));
-    S_TRY(launch_fill(s->ghat.as<float>(), 0.0f, (int64_t)g->M * g->n_vox, st));
+    if (s->subdet)
+        S_TRY(launch_fill(s->rho.as<float>(), 0.0f, g->z_floats, st));
+    else
+        S_TRY(launch_fill(s->ghat.as<float>(), 0.0f, (int64_t)g->M * g->n_vox, st));
     S_TRY(launch_fill(s->gsum.as<float>(), 0.0f, g->n_vox, st));
 #undef S_TRY
     *out = s;
@@ -1004,12 +1015,17 @@ static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32
             return launch_fp_pairs(g->dg, wk, s->L, rec + s->L.off_blocks(), s->x, s->z.as<float>(), st);
         });
         if (e != hipSuccess) return e;
-        e = timed(s, KID_RESID,
-                  [&] { return launch_resid(g->dg, rec, s->L, s->y, s->z.as<float>(), s->r_sel.as<float>(), st); });
+        e = timed(s, KID_RESID, [&] {
+            hipError_t e2 = launch_resid(g->dg, rec, s->L, s->y, s->z.as<float>(), s->r_sel.as<float>(), st);
+            if (e2 == hipSuccess && s->subdet)
+                e2 = launch_subdet_delta(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->rho.as<float>(),
+                                         s->delta.as<float>(), st);
+            return e2;
+        });
         if (e != hipSuccess) return e;
         e = timed(s, KID_BP, [&] {
-            return launch_bp_step(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->ghat.as<float>(), s->gsum.as<float>(),
-                                  s->x, s->mu_dev.as<float>(), g->n_vox, st);
+            return launch_bp_step(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->subdet ? s->delta.as<float>() : nullptr,
+                                  s->ghat.as<float>(), s->gsum.as<float>(), s->x, s->mu_dev.as<float>(), g->n_vox, st);
         });
         if (e != hipSuccess) return e;
         if (s->auto_mu) {
@@ -1221,6 +1237,7 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         if (s->st != st) return fail(BSGD_E_INVALID_ARG, "solver %d was created on another stream", i);
         if (s->g->dim != dim) return fail(BSGD_E_INVALID_ARG, "a batch mixes 2D and 3D solves");
         if (s->auto_mu) return fail(BSGD_E_UNSUPPORTED, "solver %d tunes its step length; step it alone", i);
+        if (s->subdet) return fail(BSGD_E_UNSUPPORTED, "solver %d keeps sub-detector memories; step it alone", i);
         for (int j = 0; j < i; ++j)
             if (solvers[j] == s) return fail(BSGD_E_INVALID_ARG, "solver %d appears twice", i);
     }
@@ -1353,10 +1370,15 @@ extern "C" bsgd_status bsgd_solver_state(const bsgd_solver* s, int32_t which, fl
         src = &s->gsum;
         need = (size_t)s->g->n_vox * sizeof(float);
     } else if (which == 1) {
+        if (s->subdet) return fail(BSGD_E_INVALID_ARG, "a solver with sub-detector memories keeps no g_hat");
         src = &s->ghat;
         need = (size_t)s->g->M * s->g->n_vox * sizeof(float);
     } else if (which == 2) {
         src = &s->z;
+        need = (size_t)s->g->z_floats * sizeof(float);
+    } else if (which == 3) {
+        if (!s->subdet) return fail(BSGD_E_INVALID_ARG, "the solver keeps no sub-detector memories");
+        src = &s->rho;
         need = (size_t)s->g->z_floats * sizeof(float);
     } else {
         return fail(BSGD_E_INVALID_ARG, "unknown state %d", which);

@@ -99,9 +99,15 @@ hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayou
 hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const float* y,
                         const float* z, float* r_sel, hipStream_t st);
 
+// delta == NULL: per-row-block memories ghat (Algorithm 1); else the sub-detector memory
+// form, reading the residual changes `delta` (z layout) and leaving ghat alone.
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
-                          const float* r_sel, float* ghat, float* gsum, float* x, const float* mu, int64_t n_vox,
-                          hipStream_t st);
+                          const float* r_sel, const float* delta, float* ghat, float* gsum, float* x,
+                          const float* mu, int64_t n_vox, hipStream_t st);
+
+// delta = r - rho and rho = r over every selected pair's pixel range (z layout).
+hipError_t launch_subdet_delta(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
+                               const float* r_sel, float* rho, float* delta, hipStream_t st);
 
 // Standalone projectors over a device view list (views[n_sel]); block < 0 = all blocks.
 hipError_t launch_fp_full(const DevGeom& G, const int32_t* views, int n_sel, int block, const float* x,

@@ -125,11 +125,12 @@ __device__ __forceinline__ float fp_ray_block(const DevGeom& G, int view, float 
 
 // Back projection of one view into one voxel: sum over candidate rays of a_ij r_i.
 // Candidates are the pixels inside the voxel's shadow (corner projections plus a
-// margin), clipped to [k0, k1) x [l0, l1).
+// margin), clipped to [k0, k1) x [l0, l1); ray (k, l) reads rview[l * rstride + k].
 template <int DIM, class Anchor>
 __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float c, float s, const Anchor& P,
                                                const int (&li)[3], const float (&h)[3], const float (&vs)[3],
-                                               int k0, int k1, int l0, int l1, const float* __restrict__ rview)
+                                               int k0, int k1, int l0, int l1, const float* __restrict__ rview,
+                                               int rstride)
 {
     const float hvx = 0.5f * vs[0], hvy = 0.5f * vs[1];
     const float qx = plane_pos(li[0], vs[0], h[0]) + hvx;
@@ -188,7 +189,7 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float
             Ray R;
             make_ray<DIM>(G, view, c, s, P, k, l, R);
             const float dt = voxel_dt<DIM>(R, li, h, vs);
-            if (dt > 0.0f) acc = fmaf(dt * R.len, rview[(int64_t)l * G.nu + k], acc);
+            if (dt > 0.0f) acc = fmaf(dt * R.len, rview[(int64_t)l * rstride + k], acc);
         }
     }
     return acc;
@@ -718,11 +719,15 @@ __device__ __forceinline__ bool tile_voxel(const BlockInfo& B, int tile, int vl,
 
 // For each selected row block i: g_hat^i_new = 2 (A_{rows(i,j)}^{J_j})^T r;
 // g += sum_i (g_hat^i_new - g_hat^i_old); g_hat^i = g_hat^i_new; then x += mu g.
-// A voxel's update reads only r, so voxels are independent (no atomics).
-template <int DIM>
+// With SUB (gradient memory per (view, sub-detector, block), kept as the residual each
+// ray had when its pair last ran): g += 2 (A_{rows}^{J_j})^T d with d = r - rho the
+// change of those residuals, read from `src` in the z layout of each pair (k_subdet_delta
+// wrote it); no g_hat. A voxel's update reads only r (or d), so voxels are independent
+// (no atomics).
+template <int DIM, bool SUB>
 __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __restrict__ S_,
                                              const PairWork* __restrict__ work, SchedLayout L,
-                                             const float* __restrict__ r_sel, float* __restrict__ ghat,
+                                             const float* __restrict__ src, float* __restrict__ ghat,
                                              float* __restrict__ gsum, float* __restrict__ x,
                                              const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
                                              float (&part)[BP_SPLIT][BP_VOX])
@@ -750,12 +755,12 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
             for (int a = a0 + grp; a < a1; a += BP_SPLIT) {
                 const PairWork W = wb[a];
                 if (W.k1 <= W.k0) continue;
+                const float* rv = SUB ? src + W.zbase : src + (int64_t)a * per_view;
                 if (DIM == 2)
-                    acc += bp_voxel_view_2d(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1,
-                                            r_sel + (int64_t)a * per_view);
+                    acc += bp_voxel_view_2d(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, rv);
                 else
-                    acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
-                                              r_sel + (int64_t)a * per_view);
+                    acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1, rv,
+                                              SUB ? W.zw : G.nu);
             }
         }
         part[grp][vl] = acc;
@@ -764,11 +769,15 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
             float sum = part[0][vl];
 #pragma unroll
             for (int q = 1; q < BP_SPLIT; ++q) sum += part[q][vl];
-            const int i = S_[L.off_rows() + ri];
-            const float gnew = 2.0f * sum;
-            float* gp = ghat + (int64_t)i * n_vox + vox;
-            dg += gnew - *gp;
-            *gp = gnew;
+            if (SUB) {
+                dg += 2.0f * sum;
+            } else {
+                const int i = S_[L.off_rows() + ri];
+                const float gnew = 2.0f * sum;
+                float* gp = ghat + (int64_t)i * n_vox + vox;
+                dg += gnew - *gp;
+                *gp = gnew;
+            }
         }
         __syncthreads();
     }
@@ -779,12 +788,9 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
     }
 }
 
-// For each selected row block i: g_hat^i_new = 2 (A_{rows(i,j)}^{J_j})^T r;
-// g += sum_i (g_hat^i_new - g_hat^i_old); g_hat^i = g_hat^i_new; then x += mu g.
-// A voxel's update reads only r, so voxels are independent (no atomics).
-template <int DIM>
+template <int DIM, bool SUB>
 __global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
-                                                SchedLayout L, const float* __restrict__ r_sel,
+                                                SchedLayout L, const float* __restrict__ src,
                                                 float* __restrict__ ghat, float* __restrict__ gsum,
                                                 float* __restrict__ x, const float* __restrict__ mu,
                                                 long long n_vox)
@@ -792,7 +798,33 @@ __global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __rest
     __shared__ float part[BP_SPLIT][BP_VOX];
     int bx, by;
     xcd_grid2(bx, by);
-    bp_step_body<DIM>(G, S_, work, L, r_sel, ghat, gsum, x, mu, n_vox, bx, by, part);
+    bp_step_body<DIM, SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
+}
+
+// Sub-detector gradient memory: one workgroup per (view slot, block slot) pair. Over the
+// pair's pixel range, d = r - rho (the change of each ray's residual since the pair's
+// view, sub-detector and block last ran) and rho = r, both in the pair's z layout. A
+// (view, block) pair occurs at most once per iteration, so no two workgroups share a
+// pixel.
+__global__ __launch_bounds__(WG) void k_subdet_delta(DevGeom G, const int32_t* __restrict__ S_,
+                                                     const PairWork* __restrict__ work, SchedLayout L,
+                                                     const float* __restrict__ r_sel, float* __restrict__ rho,
+                                                     float* __restrict__ delta)
+{
+    const int a = blockIdx.x, b = blockIdx.y;
+    if (a >= S_[0]) return;
+    const PairWork W = work[(int64_t)b * L.maxv + a];
+    const int w = W.k1 - W.k0, hgt = W.l1 - W.l0;
+    if (w <= 0 || hgt <= 0) return;
+    const float* rv = r_sel + (int64_t)a * G.nu * G.nv;
+    const int n = w * hgt;
+    for (int t = threadIdx.x; t < n; t += WG) {
+        const int k = W.k0 + t % w, l = W.l0 + t / w;
+        const int64_t zi = W.zbase + (int64_t)l * W.zw + k;
+        const float rr = rv[(int64_t)l * G.nu + k];
+        delta[zi] = rr - rho[zi];
+        rho[zi] = rr;
+    }
 }
 
 // ------------------------------------------------------------ batched solves
@@ -854,7 +886,7 @@ __global__ __launch_bounds__(WG) void k_bp_batch(const BatchArgs A)
     const int local = id - B.base[2];
     const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
     const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
-    bp_step_body<DIM>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
+    bp_step_body<DIM, false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
                       local / B.gx[2], part);
 }
 
@@ -915,7 +947,7 @@ __global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __rest
                 acc += bp_voxel_view_2d(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, y + (int64_t)a * per_view);
             else
                 acc += bp_voxel_view<DIM>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
-                                          y + (int64_t)a * per_view);
+                                          y + (int64_t)a * per_view, G.nu);
         }
     }
     part[grp][vl] = acc;
@@ -1211,16 +1243,34 @@ static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int 
 }
 
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
-                          const float* r_sel, float* ghat, float* gsum, float* x, const float* mu, int64_t n_vox,
-                          hipStream_t st)
+                          const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, const float* mu,
+                          int64_t n_vox, hipStream_t st)
 {
     const int tiles = max_tiles(G, nullptr, G.dim);
-    if (G.dim == 3)
-        hipLaunchKernelGGL(k_bp_step<3>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, work_it, L, r_sel, ghat,
-                           gsum, x, mu, (long long)n_vox);
-    else
-        hipLaunchKernelGGL(k_bp_step<2>, dim3(tiles, L.B), dim3(WG), 0, st, G, sched_it, work_it, L, r_sel, ghat,
-                           gsum, x, mu, (long long)n_vox);
+    const dim3 grid(tiles, L.B), blk(WG);
+    const long long nv = (long long)n_vox;
+    if (delta) {
+        if (G.dim == 3)
+            hipLaunchKernelGGL((k_bp_step<3, true>), grid, blk, 0, st, G, sched_it, work_it, L, delta, ghat, gsum, x,
+                               mu, nv);
+        else
+            hipLaunchKernelGGL((k_bp_step<2, true>), grid, blk, 0, st, G, sched_it, work_it, L, delta, ghat, gsum, x,
+                               mu, nv);
+    } else if (G.dim == 3) {
+        hipLaunchKernelGGL((k_bp_step<3, false>), grid, blk, 0, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
+                           mu, nv);
+    } else {
+        hipLaunchKernelGGL((k_bp_step<2, false>), grid, blk, 0, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
+                           mu, nv);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_subdet_delta(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
+                               const float* r_sel, float* rho, float* delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_subdet_delta, dim3(L.maxv, L.B), dim3(WG), 0, st, G, sched_it, work_it, L, r_sel, rho,
+                       delta);
     return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ def _mu(A, scale):
     return float(np.float32(scale / (2.0 * lipschitz(A))))
 
 
-def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed=3, im_until=0):
+def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed=3, im_until=0, subdet=False,
+          eager=False):
     import torch
     from paper_1903_11874_amd import Geometry, Solver
     dev = require_gpu()
@@ -37,12 +38,13 @@ def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed
     mu = _mu(A, mu_scale)
     q = im_table(p, im) if im else None
     trace = []
-    st = run(p, y64, mu, R, B, n_iter, seed, q=q, tv_lambda=tv_lambda, trace=trace, im_until=im_until or None)
+    st = run(p, y64, mu, R, B, n_iter, seed, q=q, tv_lambda=tv_lambda, trace=trace, im_until=im_until or None,
+             subdet_memory=subdet)
     geom = Geometry(g.with_(im_mode=im or "none"), im_table=q)
     yd = torch.tensor(y32, device=dev)
     xd = torch.zeros(A.shape[1], dtype=torch.float32, device=dev)
     solver = Solver(geom, yd, xd, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=seed, tv_lambda=tv_lambda,
-                    tv_inner_iters=20, im_until=im_until)
+                    tv_inner_iters=20, im_until=im_until, subdet_memory=subdet, eager=eager)
     rn = solver.step(n_iter, residual=True)
     return p, st, trace, solver, xd, rn
 
@@ -92,6 +94,42 @@ def test_trajectory_importance_sampled(name, R, B, im):
     _check_schedule(p, trace, solver)
     assert any(s >= 0 for t in trace for s in t["draws"].values())
     assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
+
+
+@pytest.mark.parametrize("name,R,B,im,tv", [("fan", 2, 3, "colnorm", 0.0), ("cone", 1, 4, "colnorm", 0.0),
+                                            ("cone", 2, 2, "uniform", 0.0), ("parallel", 1, 2, None, 0.5),
+                                            ("fan_wide", 1, 2, None, 0.0)])
+def test_trajectory_subdetector_memory(name, R, B, im, tv):
+    """Gradient memory per (view, sub-detector, block): same iterates, g and residual
+    norm as the oracle's per-part memories, over whole graph-replayed epochs."""
+    g = SMALL[name]
+    log(f"trajectory sub-detector memory {name} R={R} B={B} im={im} tv={tv}")
+    n = 2 * tv_period(g.n_row_blocks, g.n_blocks, R, B) + 5
+    p, st, trace, solver, xd, rn = _pair(g, n, R, B, seed=17, im=im, tv_lambda=tv, subdet=True)
+    _check_schedule(p, trace, solver)
+    assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
+    assert rel_l2(solver.state("g").double().cpu().numpy(), st.gsum) <= 1e-4
+    assert abs(rn - np.linalg.norm(st.r)) <= TOL * np.linalg.norm(st.r)
+    rho = solver.state("rho")
+    assert rho.numel() == solver.geom.info["z_floats"] and bool(rho.abs().sum() > 0)
+
+
+def test_subdetector_memory_graphs_equal_eager_and_batch_refuses_it():
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver, step_batch
+    from paper_1903_11874_amd.bsgd import BsgdError
+    g = SMALL["fan"]
+    T = tv_period(g.n_row_blocks, g.n_blocks, 1, 3)
+    log("sub-detector memory: graphs vs eager")
+    xs = []
+    for eager in (False, True):
+        _, _, _, solver, xd, _ = _pair(g, 3 * T, 1, 3, seed=19, im="colnorm", subdet=True, eager=eager)
+        xs.append(xd.cpu().numpy())
+        with pytest.raises(BsgdError):
+            solver.state("ghat")
+        with pytest.raises(BsgdError):
+            step_batch([solver], 1)
+    assert np.array_equal(xs[0], xs[1])
 
 
 @pytest.mark.parametrize("name", ["parallel", "cone"])

@@ -186,3 +186,42 @@ def test_unbiased_tail_removes_the_importance_sampling_bias():
     assert im_only[3] > 0.5 * im_only[2]             # sampling alone has nearly stalled
     assert tail[3] < 0.25 * im_only[3]               # the plain tail keeps converging
     assert tail[3] < 0.5 * tail[2]
+
+
+@pytest.mark.parametrize("su", [1, 3])
+def test_subdetector_memory_without_sampling_is_algorithm_1(su):
+    """The memories of a row block's (view, sub-detector) parts sum to its g_hat, so
+    without sampling the per-part memory reproduces Algorithm 1."""
+    p = _e1_problem(M=4, bx=2, by=2, su=su)
+    r = np.random.Generator(np.random.PCG64(6))
+    y = p.A @ r.uniform(size=p.A.shape[1]) + 0.05 * r.normal(size=p.A.shape[0])
+    mu = 0.5 / (2 * lipschitz(p.A))
+    a = run(p, y, mu, 2, 2, 150, seed=3)
+    b = run(p, y, mu, 2, 2, 150, seed=3, subdet_memory=True)
+    assert np.allclose(a.x, b.x, rtol=1e-12, atol=1e-13)
+    assert np.allclose(a.gsum, b.gsum, rtol=1e-12, atol=1e-12)
+    assert np.allclose(b.mem.sum(axis=(0, 1)), b.gsum, rtol=1e-12, atol=1e-12)
+    # a full sweep at mu = 0 refreshes every memory at x0: g = 2 A^T (y - A x0)
+    x0 = r.uniform(size=p.A.shape[1])
+    st = initial_state(p, y, x0)
+    iterate(p, st, y, 0.0, p.M, p.N, seed=3, subdet_memory=True)
+    assert np.allclose(st.gsum, 2.0 * p.A.T @ (y - p.A @ x0), rtol=1e-12, atol=1e-12)
+
+
+def test_subdetector_memory_removes_the_importance_sampling_bias():
+    """Sec. II-A: with g_hat overwritten by the sampled rows' gradient, importance
+    sampling stalls short of the least-squares solution; with one memory per
+    (view, sub-detector, block) the sampled iteration itself converges to it."""
+    p = _e1_problem(M=4, bx=2, by=2, su=3, im="colnorm")
+    r = np.random.Generator(np.random.PCG64(5))
+    y = p.A @ r.uniform(size=p.A.shape[1]) + 0.01 * r.normal(size=p.A.shape[0])
+    x_lsq = np.linalg.lstsq(p.A.toarray(), y, rcond=None)[0]
+    q = im_table(p, "colnorm")
+    mu = 1.0 / (2 * lipschitz(p.A))
+    lit, mem = [], []
+    run(p, y, mu, 1, 2, 6000, seed=3, q=q,
+        callback=lambda st: lit.append(ds(st.x, x_lsq)) if st.k % 1000 == 0 else None)
+    run(p, y, mu, 1, 2, 6000, seed=3, q=q, subdet_memory=True,
+        callback=lambda st: mem.append(ds(st.x, x_lsq)) if st.k % 1000 == 0 else None)
+    assert lit[5] > 0.9 * lit[4]                     # the literal form has stalled
+    assert mem[5] < 0.6 * mem[4] and mem[5] < 0.1 * lit[5]
