@@ -166,6 +166,7 @@ struct bsgd_geometry {
     std::vector<float2> rayv;
     std::vector<float> kspan;
     DevBuf d_cs, d_pairs, d_blocks, d_q, d_all_views, d_views, d_raydir, d_rayv, d_raynorm, d_raytrap, d_kspan;
+    DevBuf d_cov_off, d_cov_idx;
     Staging stage;
     DevGeom dg{};
 };
@@ -425,6 +426,55 @@ static void build_tables(bsgd_geometry* g)
     }
 }
 
+// Pixel-major index of z (DevGeom::cov_off / cov_idx): for every ray, the z slots of the
+// column blocks whose footprint holds its pixel, blocks ascending. Built per view from
+// the footprint rectangles (counting, prefix sum, fill) and uploaded view by view.
+static bsgd_status upload_cover_index(bsgd_geometry* g, hipStream_t st)
+{
+    const bsgd_geometry_desc& d = g->d;
+    if (g->z_floats >= ((int64_t)1 << 32)) return BSGD_OK;  // rectangle tests instead
+    const int64_t per_view = (int64_t)d.nu * d.nv;
+    const int64_t n_rays = per_view * d.n_views;
+    HIP_TRY(g->d_cov_off.alloc((size_t)(n_rays + 1) * sizeof(uint32_t)));
+    HIP_TRY(g->d_cov_idx.alloc((size_t)std::max<int64_t>(g->z_floats, 1) * sizeof(uint32_t)));
+    std::vector<uint32_t> off((size_t)per_view + 1), fill((size_t)per_view), idx;
+    uint32_t base = 0;
+    for (int v = 0; v < d.n_views; ++v) {
+        std::fill(off.begin(), off.end(), 0u);
+        const PairInfo* pv = g->pairs.data() + (size_t)v * g->N;
+        for (int j = 0; j < g->N; ++j)
+            for (int l = pv[j].v0; l < pv[j].v1; ++l)
+                for (int k = pv[j].u0; k < pv[j].u1; ++k) off[(size_t)l * d.nu + k + 1] += 1;
+        off[0] = base;
+        for (int64_t q = 0; q < per_view; ++q) off[q + 1] += off[q];
+        const uint32_t n_v = off[per_view] - base;
+        idx.resize(std::max<uint32_t>(n_v, 1));
+        for (int64_t q = 0; q < per_view; ++q) fill[q] = off[q] - base;
+        for (int j = 0; j < g->N; ++j) {
+            const PairInfo& P = pv[j];
+            const int w = P.u1 - P.u0;
+            for (int l = P.v0; l < P.v1; ++l)
+                for (int k = P.u0; k < P.u1; ++k)
+                    idx[fill[(size_t)l * d.nu + k]++] =
+                        (uint32_t)(P.zoff + (int64_t)(l - P.v0) * w + (k - P.u0));
+        }
+        // synchronous copies: the host vectors are reused for the next view
+        HIP_TRY(hipMemcpy(g->d_cov_off.as<uint32_t>() + (size_t)v * per_view, off.data(),
+                          (size_t)per_view * sizeof(uint32_t), hipMemcpyHostToDevice));
+        if (n_v)
+            HIP_TRY(hipMemcpy(g->d_cov_idx.as<uint32_t>() + base, idx.data(), (size_t)n_v * sizeof(uint32_t),
+                              hipMemcpyHostToDevice));
+        base += n_v;
+    }
+    HIP_TRY(hipMemcpy(g->d_cov_off.as<uint32_t>() + n_rays, &base, sizeof(uint32_t), hipMemcpyHostToDevice));
+    if ((int64_t)base != g->z_floats) return fail(BSGD_E_STATE, "z index covers %u of %lld slots", base,
+                                                  (long long)g->z_floats);
+    (void)st;
+    g->dg.cov_off = g->d_cov_off.as<uint32_t>();
+    g->dg.cov_idx = g->d_cov_idx.as<uint32_t>();
+    return BSGD_OK;
+}
+
 static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
 {
     const bsgd_geometry_desc& d = g->d;
@@ -507,7 +557,9 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.raynorm = g->raynorm.empty() ? nullptr : g->d_raynorm.as<float4>();
     G.raytrap = g->raytrap.empty() ? nullptr : g->d_raytrap.as<float4>();
     G.kspan = g->kspan.empty() ? nullptr : g->d_kspan.as<float>();
-    return BSGD_OK;
+    G.cov_off = nullptr;
+    G.cov_idx = nullptr;
+    return upload_cover_index(g, st);
 }
 
 static bsgd_status compute_im(bsgd_geometry* g, hipStream_t st)

@@ -84,6 +84,12 @@ struct DevGeom {
     const float4* raynorm;     // [n_views][nu]: nx, ny, xi, unused
     const float4* raytrap;     // [n_views][nu]: w1, w2, lmax, slope
     const float* kspan;        // [n_views]
+    // Pixel-major index of z: ray p = view * nu * nv + l * nu + k has the z slots
+    // cov_idx[cov_off[p] .. cov_off[p + 1]), one per column block whose footprint holds
+    // the pixel, blocks ascending. NULL when z has 2^32 or more slots (the residual
+    // rebuild then tests the footprint rectangles itself).
+    const uint32_t* cov_off;   // [n_views * nu * nv + 1]
+    const uint32_t* cov_idx;   // [z_floats]
 };
 
 // Sub-detector s covers u in [k0, k1), v in [l0, l1).

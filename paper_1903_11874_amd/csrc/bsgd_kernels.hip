@@ -613,6 +613,29 @@ __device__ __forceinline__ float resid_ray(const DevGeom& G, int v, int k, int l
     return acc;
 }
 
+// r = y - sum_j z^j for ray p through the pixel-major z index, blocks ascending (the
+// order of resid_ray, so both give the same bits). The index entries and z values of U
+// blocks are gathered back to back.
+template <int U>
+__device__ __forceinline__ float resid_ray_idx(const DevGeom& G, int64_t p, const float* __restrict__ y,
+                                               const float* __restrict__ z)
+{
+    const uint32_t o0 = G.cov_off[p], o1 = G.cov_off[p + 1];
+    float acc = y[p];
+    for (uint32_t e = o0; e < o1; e += U) {
+        uint32_t id[U];
+        float val[U];
+#pragma unroll
+        for (int c = 0; c < U; ++c) id[c] = (e + c < o1) ? G.cov_idx[e + c] : 0u;
+#pragma unroll
+        for (int c = 0; c < U; ++c) val[c] = (e + c < o1) ? z[id[c]] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < U; ++c)
+            if (e + c < o1) acc -= val[c];
+    }
+    return acc;
+}
+
 // Stage view v's footprint rectangles and z offsets, then the group bounding
 // rectangles (empty footprints ignored; an empty group gets an empty rectangle).
 __device__ __forceinline__ void stage_rects(const DevGeom& G, int v, int4* rc, long long* zo, int4* grc)
@@ -651,6 +674,7 @@ __device__ __forceinline__ void stage_rects(const DevGeom& G, int v, int4* rc, l
 // res_batch candidate offsets per thread.
 __host__ __device__ inline size_t resid_lds_bytes(const DevGeom& G, int threads)
 {
+    if (G.cov_off) return 0;  // the pixel-major index needs no staging
     return (size_t)G.N * (sizeof(int4) + sizeof(long long)) + (size_t)res_groups(G) * sizeof(int4) +
            (size_t)threads * res_batch(threads) * sizeof(long long);
 }
@@ -666,8 +690,14 @@ __device__ __forceinline__ void resid_body(const DevGeom& G, const int32_t* __re
     const int a = by;
     if (a >= S_[0]) return;
     const int v = S_[L.off_views() + a];
-    stage_rects(G, v, rc, zo, grc);
     const int per_view = G.nu * G.nv;
+    if (G.cov_off) {  // uniform: the index replaces the rectangle tests
+        const int ray = bx * TPB + threadIdx.x;
+        if (ray < per_view)
+            r_sel[(int64_t)a * per_view + ray] = resid_ray_idx<8>(G, (int64_t)v * per_view + ray, y, z);
+        return;
+    }
+    stage_rects(G, v, rc, zo, grc);
     const int ray = bx * TPB + threadIdx.x;
     if (ray >= per_view) return;
     const int k = ray % G.nu, l = ray / G.nu;
@@ -973,13 +1003,21 @@ __global__ __launch_bounds__(WG) void k_resid_sumsq(DevGeom G, const float* __re
     long long* zo = reinterpret_cast<long long*>(grc + res_groups(G));
     long long* cand = zo + G.N + threadIdx.x * res_batch(WG);
     const int v = blockIdx.y;
-    stage_rects(G, v, rc, zo, grc);
     const int per_view = G.nu * G.nv;
     const int ray = blockIdx.x * WG + threadIdx.x;
     double val = 0.0;
-    if (ray < per_view) {
-        const float r = resid_ray<res_batch(WG)>(G, v, ray % G.nu, ray / G.nu, y, z, rc, zo, grc, cand, per_view, ray);
-        val = (double)r * (double)r;
+    if (G.cov_off) {
+        if (ray < per_view) {
+            const float r = resid_ray_idx<8>(G, (int64_t)v * per_view + ray, y, z);
+            val = (double)r * (double)r;
+        }
+    } else {
+        stage_rects(G, v, rc, zo, grc);
+        if (ray < per_view) {
+            const float r = resid_ray<res_batch(WG)>(G, v, ray % G.nu, ray / G.nu, y, z, rc, zo, grc, cand, per_view,
+                                                     ray);
+            val = (double)r * (double)r;
+        }
     }
     const double s = block_sum(val, lds);
     if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
