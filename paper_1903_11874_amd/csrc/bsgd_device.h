@@ -478,6 +478,21 @@ __device__ __forceinline__ float voxel_dt(const Ray& R, const int (&ix)[3], cons
     return fmaxf(tx - te, 0.0f);
 }
 
+// One axis of voxel_dt's slab test for a ray with coordinate p and reciprocal
+// direction inv on that axis through voxel index i: narrows [te, tx], or clears hit
+// when the ray runs parallel to the axis outside the voxel.
+__device__ __forceinline__ void slab_axis(float p, float inv, int i, float v, float h, float& te, float& tx, bool& hit)
+{
+    if (!axis_fixed(inv)) {
+        const float t0 = plane_t(i, v, h, p, inv);
+        const float t1 = plane_t(i + 1, v, h, p, inv);
+        te = fmaxf(te, fminf(t0, t1));
+        tx = fminf(tx, fmaxf(t0, t1));
+    } else if (!(plane_pos(i, v, h) <= p && p < plane_pos(i + 1, v, h))) {
+        hit = false;
+    }
+}
+
 // Exact length of a line through an axis-aligned rectangle (2D voxel) as a function
 // of the signed distance delta of the rectangle centre from the line: lmax on the
 // plateau |delta| <= w1, falling linearly to 0 at |delta| = w2 (a trapezoid).

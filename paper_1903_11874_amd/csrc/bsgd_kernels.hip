@@ -123,6 +123,14 @@ __device__ __forceinline__ float fp_ray_block(const DevGeom& G, int view, float 
     return acc * R.len;
 }
 
+// Load base[byte_off / sizeof(T)] with a 32-bit byte offset (a uniform base stays in
+// scalar registers; the offset is one vector register).
+template <class T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t byte_off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // Back projection of one view into one voxel: sum over candidate rays of a_ij r_i.
 // Candidates are the pixels inside the voxel's shadow (corner projections plus a
 // margin), clipped to [k0, k1) x [l0, l1); ray (k, l) reads rview[l * rstride + k].
@@ -183,13 +191,30 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float
         llo = max(l0, (int)ceilf(fminf(fmaxf(lmin - SHADOW_EPS, (float)l0), (float)l1)));
         lhi = min(l1 - 1, (int)floorf(fmaxf(fminf(lmax + SHADOW_EPS, (float)l1), (float)l0 - 1.0f)));
     }
+    // The slab test of voxel_dt factorised: the x and y slabs depend on the pixel
+    // column k only, the z slab on the row l only (min and max are exact, so the
+    // lengths are those of make_ray + voxel_dt bit for bit).
+    const float4* rd = G.raydir + (int64_t)view * G.nu;
     float acc = 0.0f;
-    for (int l = llo; l <= lhi; ++l) {
-        for (int k = klo; k <= khi; ++k) {
-            Ray R;
-            make_ray<DIM>(G, view, c, s, P, k, l, R);
-            const float dt = voxel_dt<DIM>(R, li, h, vs);
-            if (dt > 0.0f) acc = fmaf(dt * R.len, rview[(int64_t)l * rstride + k], acc);
+    for (int k = klo; k <= khi; ++k) {
+        const float lu = fmaf((float)(k - P.kc), P.au, P.bu);
+        const float4 T = ld_off(rd, (uint32_t)k * 16u);
+        float te = -INFINITY, tx = INFINITY;
+        bool hit = true;
+        slab_axis(-lu * s, T.x, li[0], vs[0], h[0], te, tx, hit);
+        slab_axis(lu * c, T.y, li[1], vs[1], h[1], te, tx, hit);
+        if (!hit) continue;
+        for (int l = llo; l <= lhi; ++l) {
+            float te3 = te, tx3 = tx, len = T.z;
+            if (DIM == 3) {
+                const float2 V = G.rayv[l];
+                bool hz = true;
+                slab_axis(fmaf((float)(l - P.lc), P.av, P.bv), V.x, li[2], vs[2], h[2], te3, tx3, hz);
+                if (!hz) continue;
+                len = __builtin_amdgcn_sqrtf(T.z + V.y);
+            }
+            const float dt = fmaxf(tx3 - te3, 0.0f);
+            if (dt > 0.0f) acc = fmaf(dt * len, ld_off(rview, ((uint32_t)l * (uint32_t)rstride + (uint32_t)k) * 4u), acc);
         }
     }
     return acc;
@@ -217,37 +242,43 @@ __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, fl
         kc = fmaf(G.sdd * w * rdep, inv_du, ku);
         span = G.kspan[view] * rdep;
     }
-    const int klo = max(k0, (int)ceilf(fminf(fmaxf(kc - span - SHADOW_EPS, (float)k0), (float)k1)));
+    // the float clamp keeps the conversions in range and klo >= k0
+    const int klo = (int)ceilf(fminf(fmaxf(kc - span - SHADOW_EPS, (float)k0), (float)k1));
     const int khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kc + span + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
     const float4* nrm = G.raynorm + (int64_t)view * G.nu;
     const float4* trp = G.raytrap + (int64_t)view * G.nu;
     // the first BP_AHEAD candidates' gathers are issued together, each only by the
     // lanes whose range holds it, then consumed in ascending k; wider ranges continue
-    // in a loop
+    // in a loop. Offsets are 32-bit bytes from the view's (wave-uniform) rows, so each
+    // gather takes a scalar base and one vector offset.
     float4 n[BP_AHEAD], t[BP_AHEAD];
     float r[BP_AHEAD];
 #pragma unroll
     for (int i = 0; i < BP_AHEAD; ++i) {
         if (klo + i <= khi) {
-            n[i] = nrm[klo + i];
-            t[i] = trp[klo + i];
-            r[i] = rview[klo + i];
+            const uint32_t kk = (uint32_t)(klo + i);
+            n[i] = ld_off(nrm, kk * 16u);
+            t[i] = ld_off(trp, kk * 16u);
+            r[i] = ld_off(rview, kk * 4u);
         }
     }
+    // lateral offset of candidate klo + i: lam0 + i au (lam0 that of klo)
+    const float lam0 = fmaf((float)(klo - P.kc), P.au, P.bu);
     float acc = 0.0f;
 #pragma unroll
     for (int i = 0; i < BP_AHEAD; ++i) {
         if (klo + i <= khi) {
-            const float lam = fmaf((float)(klo + i - P.kc), P.au, P.bu);
+            const float lam = fmaf((float)i, P.au, lam0);
             const float delta = fmaf(n[i].x, qx, fmaf(n[i].y, qy, -(lam * n[i].z)));
             acc = fmaf(chord_2d(delta, t[i]), r[i], acc);
         }
     }
     for (int k = klo + BP_AHEAD; k <= khi; ++k) {
-        const float4 nk = nrm[k];
-        const float lam = fmaf((float)(k - P.kc), P.au, P.bu);
+        const uint32_t kk = (uint32_t)k;
+        const float4 nk = ld_off(nrm, kk * 16u);
+        const float lam = fmaf((float)(k - klo), P.au, lam0);
         const float delta = fmaf(nk.x, qx, fmaf(nk.y, qy, -(lam * nk.z)));
-        acc = fmaf(chord_2d(delta, trp[k]), rview[k], acc);
+        acc = fmaf(chord_2d(delta, ld_off(trp, kk * 16u)), ld_off(rview, kk * 4u), acc);
     }
     return acc;
 }
