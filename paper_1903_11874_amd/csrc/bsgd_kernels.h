@@ -132,7 +132,8 @@ hipError_t launch_add(float* a, const float* b, int64_t n, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partials, int* n_partials, hipStream_t st);
 
 // TV proximal step of BSGD-TV on x (in place): iters fast-gradient-projection steps.
-// p, ra, rb: device [dim][n_vox] scratch.
+// p: device [dim + 1][n_vox] scratch (the dual iterate, then the primal point u);
+// ra, rb: device [dim][n_vox] scratch.
 hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float* p, float* ra, float* rb,
                           hipStream_t st);
 

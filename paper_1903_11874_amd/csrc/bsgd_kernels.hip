@@ -1124,22 +1124,35 @@ __device__ __forceinline__ float div_adj(const float* __restrict__ q, int64_t nv
     return r;
 }
 
-// One FGP step on the dual: p_new = P_ball(r + step D(b - w D^T r)); r_out = p_new + coef (p_new - p).
+// FGP step, first half: the primal point of the current dual iterate,
+// u = b - w D^T r (one thread per voxel).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_fgp_iter(const float* __restrict__ b, const float* __restrict__ rin,
-                                                 float* __restrict__ rout, float* __restrict__ p, int nx, int ny,
-                                                 int nz, float w, float step, float coef)
+__global__ __launch_bounds__(WG) void k_fgp_u(const float* __restrict__ b, const float* __restrict__ rin,
+                                              float* __restrict__ u, int nx, int ny, int nz, float w)
 {
     const int64_t nvox = (int64_t)nx * ny * nz;
     const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (o >= nvox) return;
     const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
-    const float uc = b[o] - w * div_adj<DIM>(rin, nvox, X, Y, Z, nx, ny, nz);
+    u[o] = b[o] - w * div_adj<DIM>(rin, nvox, X, Y, Z, nx, ny, nz);
+}
+
+// FGP step, second half: p_new = P_ball(r + step D u); r_out = p_new + coef (p_new - p),
+// with D the backward differences (zero across the low boundary).
+template <int DIM>
+__global__ __launch_bounds__(WG) void k_fgp_dual(const float* __restrict__ u, const float* __restrict__ rin,
+                                                 float* __restrict__ rout, float* __restrict__ p, int nx, int ny,
+                                                 int nz, float step, float coef)
+{
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (o >= nvox) return;
+    const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
+    const float uc = u[o];
     float g[3] = {0.0f, 0.0f, 0.0f};
-    if (X >= 1) g[0] = uc - (b[o - 1] - w * div_adj<DIM>(rin, nvox, X - 1, Y, Z, nx, ny, nz));
-    if (Y >= 1) g[1] = uc - (b[o - nx] - w * div_adj<DIM>(rin, nvox, X, Y - 1, Z, nx, ny, nz));
-    if (DIM == 3 && Z >= 1)
-        g[2] = uc - (b[o - (int64_t)nx * ny] - w * div_adj<DIM>(rin, nvox, X, Y, Z - 1, nx, ny, nz));
+    if (X >= 1) g[0] = uc - u[o - 1];
+    if (Y >= 1) g[1] = uc - u[o - nx];
+    if (DIM == 3 && Z >= 1) g[2] = uc - u[o - (int64_t)nx * ny];
     float q[3];
     float n2 = 0.0f;
 #pragma unroll
@@ -1443,15 +1456,19 @@ hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float*
     double tk = 1.0;
     float* rin = ra;
     float* rout = rb;
+    float* u = p + (int64_t)dim * nvox;  // p holds (dim + 1) nvox floats
     for (int it = 0; it < iters; ++it) {
         const double tn = (1.0 + sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
         const float coef = (float)((tk - 1.0) / tn);
-        if (dim == 3)
-            hipLaunchKernelGGL(k_fgp_iter<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, rout, p, G.nx, G.ny, G.nz,
-                               w, step, coef);
-        else
-            hipLaunchKernelGGL(k_fgp_iter<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, rout, p, G.nx, G.ny, G.nz,
-                               w, step, coef);
+        if (dim == 3) {
+            hipLaunchKernelGGL(k_fgp_u<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, w);
+            hipLaunchKernelGGL(k_fgp_dual<3>, dim3(grid1(nvox)), dim3(WG), 0, st, u, rin, rout, p, G.nx, G.ny, G.nz,
+                               step, coef);
+        } else {
+            hipLaunchKernelGGL(k_fgp_u<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, w);
+            hipLaunchKernelGGL(k_fgp_dual<2>, dim3(grid1(nvox)), dim3(WG), 0, st, u, rin, rout, p, G.nx, G.ny, G.nz,
+                               step, coef);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         tk = tn;
