@@ -953,7 +953,8 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
         S_TRY(s->ghat.alloc((size_t)g->M * g->n_vox * sizeof(float)));
     }
     S_TRY(s->gsum.alloc((size_t)g->n_vox * sizeof(float)));
-    S_TRY(s->r_sel.alloc((size_t)s->maxv * per_view * sizeof(float)));
+    // 2D: one {w2, slope, lmax, r} record per selected ray; 3D: the residual
+    S_TRY(s->r_sel.alloc((size_t)s->maxv * per_view * (g->dim == 2 ? 4 : 1) * sizeof(float)));
     const int n_part = (int)(((per_view + 255) / 256) * g->d.n_views);
     S_TRY(s->partials.alloc((size_t)std::max(n_part, 4096) * sizeof(double)));
     S_TRY(s->norm_out.alloc(4 * sizeof(double)));

@@ -503,6 +503,13 @@ __device__ __forceinline__ float chord_2d(float delta, const float4& trap)
     return __builtin_amdgcn_fmed3f((trap.y - fabsf(delta)) * trap.w, 0.0f, trap.z);
 }
 
+// chord_2d on a per-ray record {w2, slope, lmax, r}: the same operations on the same
+// values, so the same bits.
+__device__ __forceinline__ float chord_2d_rec(float delta, const float4& rec)
+{
+    return __builtin_amdgcn_fmed3f((rec.x - fabsf(delta)) * rec.y, 0.0f, rec.z);
+}
+
 // SplitMix64 output function and the counter-based draws (same definition as the
 // host runtime's selection streams).
 __device__ __forceinline__ uint64_t mix64(uint64_t z)

@@ -48,7 +48,7 @@ struct BatchEntry {
     float* z;
     float* ghat;
     float* gsum;
-    float* r_sel;
+    float* r_sel;          // 2D: {w2, slope, lmax, r} per selected ray; 3D: r
     const float* mu;  // device scalar (the current step length)
     int fp_chunk;
     int fp_lds;
@@ -71,6 +71,7 @@ struct BatchArgs {
     int it;   // iteration index into every entry's records
     int id0;  // workgroup id of this launch's first workgroup (phase 0 classes)
 };
+static_assert(sizeof(BatchArgs) <= 4096, "batched kernel arguments must fit the 4 KB argument segment");
 
 // A contiguous range of phase-0 workgroups whose entries share one LDS size.
 struct FpLaunchClass {

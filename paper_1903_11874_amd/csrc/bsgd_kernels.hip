@@ -222,11 +222,15 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float
 
 // 2D back projection of one view into one voxel with the closed-form chord: the
 // candidate rays are those whose pixel lies within kspan / depth of the projection
-// of the voxel centre; each contributes chord_2d(delta) * r.
-template <class Anchor>
+// of the voxel centre; each contributes chord_2d(delta) * r. PACKED: src is the
+// view's row of per-ray records {w2, slope, lmax, r} (the trapezoid of the ray's
+// chord and its residual, written by the residual rebuild), so a candidate takes two
+// gathers (normal, record) instead of three; otherwise src is the view's residuals
+// and the trapezoid comes from the static table. Same arithmetic either way.
+template <bool PACKED, class Anchor>
 __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, float c, float s, const Anchor& P,
                                                   const int (&li)[3], const float (&h)[3], const float (&vs)[3],
-                                                  int k0, int k1, const float* __restrict__ rview)
+                                                  int k0, int k1, const float* __restrict__ src)
 {
     const float qx = plane_pos(li[0], vs[0], h[0]) + 0.5f * vs[0];
     const float qy = plane_pos(li[1], vs[1], h[1]) + 0.5f * vs[1];
@@ -247,6 +251,7 @@ __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, fl
     const int khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kc + span + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
     const float4* nrm = G.raynorm + (int64_t)view * G.nu;
     const float4* trp = G.raytrap + (int64_t)view * G.nu;
+    const float4* rec = reinterpret_cast<const float4*>(src);
     // the first BP_AHEAD candidates' gathers are issued together, each only by the
     // lanes whose range holds it, then consumed in ascending k; wider ranges continue
     // in a loop. Offsets are 32-bit bytes from the view's (wave-uniform) rows, so each
@@ -258,8 +263,12 @@ __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, fl
         if (klo + i <= khi) {
             const uint32_t kk = (uint32_t)(klo + i);
             n[i] = ld_off(nrm, kk * 16u);
-            t[i] = ld_off(trp, kk * 16u);
-            r[i] = ld_off(rview, kk * 4u);
+            if constexpr (PACKED) {
+                t[i] = ld_off(rec, kk * 16u);
+            } else {
+                t[i] = ld_off(trp, kk * 16u);
+                r[i] = ld_off(src, kk * 4u);
+            }
         }
     }
     // lateral offset of candidate klo + i: lam0 + i au (lam0 that of klo)
@@ -270,7 +279,10 @@ __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, fl
         if (klo + i <= khi) {
             const float lam = fmaf((float)i, P.au, lam0);
             const float delta = fmaf(n[i].x, qx, fmaf(n[i].y, qy, -(lam * n[i].z)));
-            acc = fmaf(chord_2d(delta, t[i]), r[i], acc);
+            if constexpr (PACKED)
+                acc = fmaf(chord_2d_rec(delta, t[i]), t[i].w, acc);
+            else
+                acc = fmaf(chord_2d(delta, t[i]), r[i], acc);
         }
     }
     for (int k = klo + BP_AHEAD; k <= khi; ++k) {
@@ -278,7 +290,12 @@ __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, fl
         const float4 nk = ld_off(nrm, kk * 16u);
         const float lam = fmaf((float)(k - klo), P.au, lam0);
         const float delta = fmaf(nk.x, qx, fmaf(nk.y, qy, -(lam * nk.z)));
-        acc = fmaf(chord_2d(delta, ld_off(trp, kk * 16u)), ld_off(rview, kk * 4u), acc);
+        if constexpr (PACKED) {
+            const float4 tk = ld_off(rec, kk * 16u);
+            acc = fmaf(chord_2d_rec(delta, tk), tk.w, acc);
+        } else {
+            acc = fmaf(chord_2d(delta, ld_off(trp, kk * 16u)), ld_off(src, kk * 4u), acc);
+        }
     }
     return acc;
 }
@@ -710,6 +727,18 @@ __host__ __device__ inline size_t resid_lds_bytes(const DevGeom& G, int threads)
            (size_t)threads * res_batch(threads) * sizeof(long long);
 }
 
+// Residual of selected ray slot q (ray p of the geometry): a float in 3D; in 2D the
+// record {w2, slope, lmax, r} the back projector gathers in one load.
+__device__ __forceinline__ void store_resid(const DevGeom& G, float* __restrict__ r_sel, int64_t q, int64_t p, float r)
+{
+    if (G.dim == 2) {
+        const float4 t = G.raytrap[p];
+        reinterpret_cast<float4*>(r_sel)[q] = make_float4(t.y, t.w, t.z, r);
+    } else {
+        r_sel[q] = r;
+    }
+}
+
 template <int TPB>
 __device__ __forceinline__ void resid_body(const DevGeom& G, const int32_t* __restrict__ S_, SchedLayout L,
                                            const float* __restrict__ y, const float* __restrict__ z,
@@ -725,14 +754,16 @@ __device__ __forceinline__ void resid_body(const DevGeom& G, const int32_t* __re
     if (G.cov_off) {  // uniform: the index replaces the rectangle tests
         const int ray = bx * TPB + threadIdx.x;
         if (ray < per_view)
-            r_sel[(int64_t)a * per_view + ray] = resid_ray_idx<8>(G, (int64_t)v * per_view + ray, y, z);
+            store_resid(G, r_sel, (int64_t)a * per_view + ray, (int64_t)v * per_view + ray,
+                        resid_ray_idx<8>(G, (int64_t)v * per_view + ray, y, z));
         return;
     }
     stage_rects(G, v, rc, zo, grc);
     const int ray = bx * TPB + threadIdx.x;
     if (ray >= per_view) return;
     const int k = ray % G.nu, l = ray / G.nu;
-    r_sel[(int64_t)a * per_view + ray] = resid_ray<res_batch(TPB)>(G, v, k, l, y, z, rc, zo, grc, cand, per_view, ray);
+    store_resid(G, r_sel, (int64_t)a * per_view + ray, (int64_t)v * per_view + ray,
+                resid_ray<res_batch(TPB)>(G, v, k, l, y, z, rc, zo, grc, cand, per_view, ray));
 }
 
 template <int TPB>
@@ -816,12 +847,14 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
             for (int a = a0 + grp; a < a1; a += BP_SPLIT) {
                 const PairWork W = wb[a];
                 if (W.k1 <= W.k0) continue;
-                const float* rv = SUB ? src + W.zbase : src + (int64_t)a * per_view;
-                if (DIM == 2)
-                    acc += bp_voxel_view_2d(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, rv);
+                if (DIM == 2 && SUB)
+                    acc += bp_voxel_view_2d<false>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, src + W.zbase);
+                else if (DIM == 2)
+                    acc += bp_voxel_view_2d<true>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1,
+                                                  src + (int64_t)a * per_view * 4);
                 else
-                    acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1, rv,
-                                              SUB ? W.zw : G.nu);
+                    acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
+                                              SUB ? src + W.zbase : src + (int64_t)a * per_view, SUB ? W.zw : G.nu);
             }
         }
         part[grp][vl] = acc;
@@ -877,12 +910,13 @@ __global__ __launch_bounds__(WG) void k_subdet_delta(DevGeom G, const int32_t* _
     const PairWork W = work[(int64_t)b * L.maxv + a];
     const int w = W.k1 - W.k0, hgt = W.l1 - W.l0;
     if (w <= 0 || hgt <= 0) return;
-    const float* rv = r_sel + (int64_t)a * G.nu * G.nv;
+    const int64_t row = (int64_t)a * G.nu * G.nv;
     const int n = w * hgt;
     for (int t = threadIdx.x; t < n; t += WG) {
         const int k = W.k0 + t % w, l = W.l0 + t / w;
         const int64_t zi = W.zbase + (int64_t)l * W.zw + k;
-        const float rr = rv[(int64_t)l * G.nu + k];
+        const int64_t q = row + (int64_t)l * G.nu + k;
+        const float rr = G.dim == 2 ? reinterpret_cast<const float4*>(r_sel)[q].w : r_sel[q];
         delta[zi] = rr - rho[zi];
         rho[zi] = rr;
     }
@@ -1005,7 +1039,7 @@ __global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __rest
             if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
             const float2 cs = G.cs[v];
             if (DIM == 2)
-                acc += bp_voxel_view_2d(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, y + (int64_t)a * per_view);
+                acc += bp_voxel_view_2d<false>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, y + (int64_t)a * per_view);
             else
                 acc += bp_voxel_view<DIM>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
                                           y + (int64_t)a * per_view, G.nu);
