@@ -194,10 +194,20 @@ def test_node_count_rule_and_errors():
     assert (s.rows_per_iter, s.blocks_per_iter) == (1, 3)
     s = Solver(geom, y, x, node_count=18, mu=1e-4, seed=1)
     assert (s.rows_per_iter, s.blocks_per_iter) == (2, 9)
-    for bad in (dict(node_count=10), dict(rows_per_iter=6, blocks_per_iter=1), dict(rows_per_iter=1)):
+    for bad in (dict(node_count=10), dict(rows_per_iter=6, blocks_per_iter=1), dict(rows_per_iter=1),
+                dict(node_count=3, im_until=-1)):
         with pytest.raises(BsgdError) as e:
             Solver(geom, y, x, mu=1e-4, **bad)
         assert e.value.status == 1
+    # an unknown flag bit is rejected before any device work
+    s = Solver(geom, y, x, node_count=3, mu=1e-4, seed=1)
+    s.options.flags = 4
+    from paper_1903_11874_amd.bsgd import load_library, _dev_ptr, _stream_ptr
+    import ctypes
+    h = ctypes.c_void_p()
+    st = load_library().bsgd_solver_create(geom.handle, _dev_ptr(y), _dev_ptr(x), ctypes.byref(s.options),
+                                           _stream_ptr(None), ctypes.byref(h))
+    assert st == 1 and h.value is None
 
 
 def test_solve_matches_stepping():

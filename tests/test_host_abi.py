@@ -91,3 +91,12 @@ def test_null_arguments(lib):
     assert lib.bsgd_solver_kernel_times(None, None, None) == 1
     lib.bsgd_geometry_destroy(None)
     lib.bsgd_solver_destroy(None)
+
+
+def test_flag_constants_match_header():
+    from paper_1903_11874_amd import bsgd
+    text = open(HEADER).read()
+    defs = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"#define\s+(BSGD_FLAG_[A-Z_]+)\s+(\d+)", text))
+    assert defs == {"BSGD_FLAG_EAGER": bsgd.FLAG_EAGER, "BSGD_FLAG_SUBDET_MEMORY": bsgd.FLAG_SUBDET_MEMORY}
+    o = bsgd.make_options(eager=True, subdet_memory=True)
+    assert o.flags == bsgd.FLAG_EAGER | bsgd.FLAG_SUBDET_MEMORY
