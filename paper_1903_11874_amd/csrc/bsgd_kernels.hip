@@ -356,16 +356,17 @@ __global__ __launch_bounds__(WG) void k_geom_stats(DevGeom G, double* __restrict
 // write the pair's work record. Draws are stored [it][view slot][block slot] for
 // export; records [it][block slot][view slot] so that a block's views are contiguous.
 __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restrict__ sched, SchedLayout L,
-                                             int n_iters, unsigned long long seed,
+                                             int it0, unsigned long long seed,
                                              const uint32_t* __restrict__ q, long long im_until,
                                              int8_t* __restrict__ draws, PairWork* __restrict__ work)
 {
-    const int64_t per_it = (int64_t)L.maxv * L.B;
-    const int64_t gid = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (gid >= per_it * n_iters) return;
-    const int it = (int)(gid / per_it);
-    const int rem = (int)(gid % per_it);
-    const int b = rem / L.maxv, a = rem % L.maxv;
+    // x: (block slot, view slot) of one iteration; y: iteration it0 + blockIdx.y
+    const int per_it = L.maxv * L.B;
+    const int rem = (int)blockIdx.x * WG + (int)threadIdx.x;
+    if (rem >= per_it) return;
+    const int it = it0 + (int)blockIdx.y;
+    const int64_t gid = (int64_t)it * per_it + rem;
+    const int b = rem / L.maxv, a = rem - b * L.maxv;
     const int32_t* S_ = sched + (int64_t)it * L.stride;
     PairWork W;
     W.k0 = W.k1 = W.l0 = W.l1 = 0;
@@ -755,7 +756,7 @@ __device__ __forceinline__ void resid_body(const DevGeom& G, const int32_t* __re
         const int ray = bx * TPB + threadIdx.x;
         if (ray < per_view)
             store_resid(G, r_sel, (int64_t)a * per_view + ray, (int64_t)v * per_view + ray,
-                        resid_ray_idx<8>(G, (int64_t)v * per_view + ray, y, z));
+                        resid_ray_idx<16>(G, (int64_t)v * per_view + ray, y, z));
         return;
     }
     stage_rects(G, v, rc, zo, grc);
@@ -1073,7 +1074,7 @@ __global__ __launch_bounds__(WG) void k_resid_sumsq(DevGeom G, const float* __re
     double val = 0.0;
     if (G.cov_off) {
         if (ray < per_view) {
-            const float r = resid_ray_idx<8>(G, (int64_t)v * per_view + ray, y, z);
+            const float r = resid_ray_idx<16>(G, (int64_t)v * per_view + ray, y, z);
             val = (double)r * (double)r;
         }
     } else {
@@ -1235,11 +1236,16 @@ hipError_t launch_geom_stats(const DevGeom& G, double* w, int64_t* nnz, hipStrea
 hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, int n_iters, uint64_t seed,
                        const uint32_t* q, int64_t im_until, int8_t* draws, PairWork* work, hipStream_t st)
 {
-    const int64_t n = (int64_t)n_iters * L.maxv * L.B;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plan, dim3(grid1(n)), dim3(WG), 0, st, G, sched, L, n_iters, (unsigned long long)seed, q,
-                       (long long)im_until, draws, work);
-    return hipGetLastError();
+    const int64_t per_it = (int64_t)L.maxv * L.B;
+    if (n_iters <= 0 || per_it == 0) return hipSuccess;
+    for (int it0 = 0; it0 < n_iters; it0 += 65535) {
+        const int n = std::min(65535, n_iters - it0);
+        hipLaunchKernelGGL(k_plan, dim3(grid1(per_it), n), dim3(WG), 0, st, G, sched, L, it0,
+                           (unsigned long long)seed, q, (long long)im_until, draws, work);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Floats of the largest block's LDS copy in the forward projector (2D rows padded).
