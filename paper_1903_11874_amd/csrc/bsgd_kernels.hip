@@ -22,7 +22,7 @@ namespace {
 
 constexpr int WG = 256;
 constexpr float SHADOW_EPS = 1e-3f;  // candidate-range margin of the voxel shadow, in pixels
-constexpr int BP_AHEAD = 3;          // 2D back projection: candidates whose gathers are issued together
+constexpr int BP_AHEAD = 2;          // 2D back projection: candidates whose gathers are issued together
 
 // Workgroups go to the 8 XCDs round-robin (workgroup id mod 8), and each XCD has its
 // own L2. Renumbering so that consecutive logical workgroups run on one XCD keeps the
