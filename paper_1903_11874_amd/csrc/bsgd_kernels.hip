@@ -780,10 +780,14 @@ __global__ __launch_bounds__(TPB) void k_resid(DevGeom G, const int32_t* __restr
 
 // ------------------------------------------------------------ solver: back projection + step
 
-// 64 voxels per workgroup, each voxel's views interleaved over BP_SPLIT threads and
+// 64 voxels per workgroup, each voxel's views interleaved over bp_split(DIM) threads and
 // summed in a fixed order through LDS.
 constexpr int BP_VOX = 64;
-constexpr int BP_SPLIT = WG / BP_VOX;
+// views of a voxel split over this many waves: two in 2D (cheap per-view work, many
+// views), one in 3D (measured: 2D 30.5 us at 2 against 30.9 at 4 and 36.1 at 1 on the
+// 512^2 fan; 3D 355 us at 1 against 372 at 2 and 402 at 4 on the 256^3 cone)
+__host__ __device__ constexpr int bp_split(int dim) { return dim == 3 ? 1 : 2; }
+__host__ __device__ constexpr int bp_wg(int dim) { return BP_VOX * bp_split(dim); }
 
 template <int DIM>
 struct Tile;
@@ -823,7 +827,7 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
                                              const float* __restrict__ src, float* __restrict__ ghat,
                                              float* __restrict__ gsum, float* __restrict__ x,
                                              const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
-                                             float (&part)[BP_SPLIT][BP_VOX])
+                                             float (&part)[bp_split(DIM)][BP_VOX])
 {
     const int b = by;
     const int j = S_[L.off_blocks() + b];
@@ -845,7 +849,7 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
         const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
         float acc = 0.0f;
         if (valid) {
-            for (int a = a0 + grp; a < a1; a += BP_SPLIT) {
+            for (int a = a0 + grp; a < a1; a += bp_split(DIM)) {
                 const PairWork W = wb[a];
                 if (W.k1 <= W.k0) continue;
                 if (DIM == 2 && SUB)
@@ -863,7 +867,7 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
         if (grp == 0 && valid) {
             float sum = part[0][vl];
 #pragma unroll
-            for (int q = 1; q < BP_SPLIT; ++q) sum += part[q][vl];
+            for (int q = 1; q < bp_split(DIM); ++q) sum += part[q][vl];
             if (SUB) {
                 dg += 2.0f * sum;
             } else {
@@ -884,13 +888,13 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
 }
 
 template <int DIM, bool SUB>
-__global__ __launch_bounds__(WG) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
+__global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
                                                 SchedLayout L, const float* __restrict__ src,
                                                 float* __restrict__ ghat, float* __restrict__ gsum,
                                                 float* __restrict__ x, const float* __restrict__ mu,
                                                 long long n_vox)
 {
-    __shared__ float part[BP_SPLIT][BP_VOX];
+    __shared__ float part[bp_split(DIM)][BP_VOX];
     int bx, by;
     xcd_grid2(bx, by);
     bp_step_body<DIM, SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
@@ -973,9 +977,9 @@ __global__ __launch_bounds__(TPB) void k_resid_batch(const BatchArgs A)
 }
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_bp_batch(const BatchArgs A)
+__global__ __launch_bounds__(bp_wg(DIM)) void k_bp_batch(const BatchArgs A)
 {
-    __shared__ float part[BP_SPLIT][BP_VOX];
+    __shared__ float part[bp_split(DIM)][BP_VOX];
     const int id = xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 2, id));
     const BatchEntry& B = A.e[e];
@@ -1015,11 +1019,11 @@ __global__ __launch_bounds__(WG) void k_fp_full(DevGeom G, const int32_t* __rest
 }
 
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __restrict__ views, int n_sel, int j0,
+__global__ __launch_bounds__(bp_wg(DIM)) void k_bp_full(DevGeom G, const int32_t* __restrict__ views, int n_sel, int j0,
                                                 const float* __restrict__ y, float* __restrict__ x, float scale,
                                                 int accumulate)
 {
-    __shared__ float part[BP_SPLIT][BP_VOX];
+    __shared__ float part[bp_split(DIM)][BP_VOX];
     const int j = j0 + blockIdx.y;
     const BlockInfo B = G.blocks[j];
     int nb[3];
@@ -1034,7 +1038,7 @@ __global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __rest
     const int per_view = G.nu * G.nv;
     float acc = 0.0f;
     if (valid) {
-        for (int a = grp; a < n_sel; a += BP_SPLIT) {
+        for (int a = grp; a < n_sel; a += bp_split(DIM)) {
             const int v = views[a];
             const PairInfo P = G.pairs[(int64_t)v * G.N + j];
             if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
@@ -1051,7 +1055,7 @@ __global__ __launch_bounds__(WG) void k_bp_full(DevGeom G, const int32_t* __rest
     if (grp == 0 && valid) {
         float sum = part[0][vl];
 #pragma unroll
-        for (int q = 1; q < BP_SPLIT; ++q) sum += part[q][vl];
+        for (int q = 1; q < bp_split(DIM); ++q) sum += part[q][vl];
         const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
         const float val = scale * sum;
         x[vox] = accumulate ? x[vox] + val : val;
@@ -1333,9 +1337,9 @@ hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], co
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dim == 3)
-        hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(WG), 0, st, A);
+        hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(bp_wg(3)), 0, st, A);
     else
-        hipLaunchKernelGGL(k_bp_batch<2>, dim3(wgs[2]), dim3(WG), 0, st, A);
+        hipLaunchKernelGGL(k_bp_batch<2>, dim3(wgs[2]), dim3(bp_wg(2)), 0, st, A);
     return hipGetLastError();
 }
 
@@ -1369,7 +1373,7 @@ hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairW
                           int64_t n_vox, hipStream_t st)
 {
     const int tiles = max_tiles(G, nullptr, G.dim);
-    const dim3 grid(tiles, L.B), blk(WG);
+    const dim3 grid(tiles, L.B), blk(bp_wg(G.dim));
     const long long nv = (long long)n_vox;
     if (delta) {
         if (G.dim == 3)
@@ -1417,10 +1421,10 @@ hipError_t launch_bp_full(const DevGeom& G, const int32_t* views, int n_sel, int
     const int tiles = max_tiles(G, nullptr, G.dim);
     const int j0 = block < 0 ? 0 : block, nj = block < 0 ? G.N : 1;
     if (G.dim == 3)
-        hipLaunchKernelGGL(k_bp_full<3>, dim3(tiles, nj), dim3(WG), 0, st, G, views, n_sel, j0, y, x, scale,
+        hipLaunchKernelGGL(k_bp_full<3>, dim3(tiles, nj), dim3(bp_wg(3)), 0, st, G, views, n_sel, j0, y, x, scale,
                            accumulate);
     else
-        hipLaunchKernelGGL(k_bp_full<2>, dim3(tiles, nj), dim3(WG), 0, st, G, views, n_sel, j0, y, x, scale,
+        hipLaunchKernelGGL(k_bp_full<2>, dim3(tiles, nj), dim3(bp_wg(2)), 0, st, G, views, n_sel, j0, y, x, scale,
                            accumulate);
     return hipGetLastError();
 }
