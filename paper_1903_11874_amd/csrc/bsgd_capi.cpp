@@ -541,8 +541,9 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.rayv = g->d_rayv.as<float2>();
     G.fp_chunk = 3;
     G.fp_split = 1;
-    // waves per pair of the global-memory forward projector: about three 64-pixel
-    // rounds per wave at the mean footprint area
+    // waves per pair of the global-memory forward projector: one per 48 pixels of the
+    // mean footprint (about one 64-pixel round per wave; more, shorter waves hide the
+    // gather latency of the walk better), at most 64
     {
         double area = 0.0;
         int64_t cnt = 0;
@@ -552,7 +553,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
                 ++cnt;
             }
         const double mean = cnt ? area / (double)cnt : 0.0;
-        G.fp_wpp = (int)std::min(16.0, std::max(1.0, std::floor(mean / 192.0)));
+        G.fp_wpp = (int)std::min(64.0, std::max(1.0, std::floor(mean / 48.0)));
     }
     G.raynorm = g->raynorm.empty() ? nullptr : g->d_raynorm.as<float4>();
     G.raytrap = g->raytrap.empty() ? nullptr : g->d_raytrap.as<float4>();
