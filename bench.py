@@ -80,14 +80,14 @@ def schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w)
 def profiled_traffic(workload_name, kernel_key):
     """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy kernel), or None when the kernel
-    sources changed since those counters were taken."""
+    or launch sources changed since those counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
         src = b"".join(open(os.path.join(ROOT, "paper_1903_11874_amd", "csrc", n), "rb").read()
-                       for n in ("bsgd_kernels.hip", "bsgd_device.h", "bsgd_kernels.h"))
+                       for n in ("bsgd_kernels.hip", "bsgd_device.h", "bsgd_kernels.h", "bsgd_capi.cpp"))
     except OSError:
         return None
     if hashlib.sha256(src).hexdigest() != t.get("source_sha256"):
