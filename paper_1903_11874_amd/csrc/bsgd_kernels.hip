@@ -300,6 +300,98 @@ __device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, fl
     return acc;
 }
 
+// Candidate pixel range [klo, khi] of a 2D voxel centre (qx, qy), block-local, in one
+// view (as in bp_voxel_view_2d): pixels within kc -/+ span of the centre's projection,
+// clipped to [k0, k1).
+template <class Anchor>
+__device__ __forceinline__ void bp2d_range(const DevGeom& G, int view, float c, float s, const Anchor& P, float qx,
+                                           float qy, int k0, int k1, int& klo, int& khi)
+{
+    const float w = fmaf(qy, c, -(qx * s)) + P.cu;
+    const float ku = 0.5f * (float)(G.nu - 1);
+    const float inv_du = __builtin_amdgcn_rcpf(G.du);
+    float kc, span;
+    if (G.kind == KIND_PARALLEL_2D) {
+        kc = fmaf(w, inv_du, ku);
+        span = G.kspan[view];
+    } else {
+        const float rdep = __builtin_amdgcn_rcpf(P.depth - fmaf(qx, c, qy * s));
+        kc = fmaf(G.sdd * w * rdep, inv_du, ku);
+        span = G.kspan[view] * rdep;
+    }
+    klo = (int)ceilf(fminf(fmaxf(kc - span - SHADOW_EPS, (float)k0), (float)k1));
+    khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kc + span + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
+}
+
+// 2D back projection of one view into two x-adjacent voxels (li and li + one voxel in
+// x; the second only when b_ok): the candidates of both are walked once, so each
+// candidate's ray normal and {w2, slope, lmax, r} record (PACKED) or trapezoid and
+// residual are gathered once for two voxels. A candidate outside a voxel's own range
+// lies outside its chord's support (the range is conservative), so it adds an exact
+// zero.
+template <bool PACKED, class Anchor>
+__device__ __forceinline__ void bp_voxel_pair_view_2d(const DevGeom& G, int view, float c, float s, const Anchor& P,
+                                                      const int (&li)[3], bool b_ok, const float (&h)[3],
+                                                      const float (&vs)[3], int k0, int k1,
+                                                      const float* __restrict__ src, float& acc_a, float& acc_b)
+{
+    const float qxa = plane_pos(li[0], vs[0], h[0]) + 0.5f * vs[0];
+    const float qxb = plane_pos(li[0] + 1, vs[0], h[0]) + 0.5f * vs[0];
+    const float qy = plane_pos(li[1], vs[1], h[1]) + 0.5f * vs[1];
+    int lo, hi;
+    bp2d_range(G, view, c, s, P, qxa, qy, k0, k1, lo, hi);
+    if (b_ok) {
+        int lob, hib;
+        bp2d_range(G, view, c, s, P, qxb, qy, k0, k1, lob, hib);
+        if (lob <= hib) {
+            lo = lo <= hi ? min(lo, lob) : lob;
+            hi = max(hi, hib);
+        }
+    }
+    const float4* nrm = G.raynorm + (int64_t)view * G.nu;
+    const float4* trp = G.raytrap + (int64_t)view * G.nu;
+    const float4* rec = reinterpret_cast<const float4*>(src);
+    float4 n[BP_AHEAD], t[BP_AHEAD];
+    float r[BP_AHEAD];
+#pragma unroll
+    for (int i = 0; i < BP_AHEAD; ++i) {
+        if (lo + i <= hi) {
+            const uint32_t kk = (uint32_t)(lo + i);
+            n[i] = ld_off(nrm, kk * 16u);
+            if constexpr (PACKED) {
+                t[i] = ld_off(rec, kk * 16u);
+            } else {
+                t[i] = ld_off(trp, kk * 16u);
+                r[i] = ld_off(src, kk * 4u);
+            }
+        }
+    }
+    const float lam0 = fmaf((float)(lo - P.kc), P.au, P.bu);
+    auto add = [&](const float4& nk, const float4& tk, float rk, float lam) {
+        const float base = fmaf(nk.y, qy, -(lam * nk.z));
+        const float da = fmaf(nk.x, qxa, base), db = fmaf(nk.x, qxb, base);
+        if constexpr (PACKED) {
+            acc_a = fmaf(chord_2d_rec(da, tk), tk.w, acc_a);
+            acc_b = fmaf(chord_2d_rec(db, tk), tk.w, acc_b);
+        } else {
+            acc_a = fmaf(chord_2d(da, tk), rk, acc_a);
+            acc_b = fmaf(chord_2d(db, tk), rk, acc_b);
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < BP_AHEAD; ++i)
+        if (lo + i <= hi) add(n[i], t[i], PACKED ? 0.0f : r[i], fmaf((float)i, P.au, lam0));
+    for (int k = lo + BP_AHEAD; k <= hi; ++k) {
+        const uint32_t kk = (uint32_t)k;
+        const float4 nk = ld_off(nrm, kk * 16u);
+        const float lam = fmaf((float)(k - lo), P.au, lam0);
+        if constexpr (PACKED)
+            add(nk, ld_off(rec, kk * 16u), 0.0f, lam);
+        else
+            add(nk, ld_off(trp, kk * 16u), ld_off(src, kk * 4u), lam);
+    }
+}
+
 // ------------------------------------------------------------ geometry statistics
 
 // One wave per (view, block) pair: for every sub-detector s, w = sum over its rays
@@ -783,10 +875,11 @@ __global__ __launch_bounds__(TPB) void k_resid(DevGeom G, const int32_t* __restr
 // 64 voxels per workgroup, each voxel's views interleaved over bp_split(DIM) threads and
 // summed in a fixed order through LDS.
 constexpr int BP_VOX = 64;
-// views of a voxel split over this many waves: two in 2D (cheap per-view work, many
-// views), one in 3D (measured: 2D 30.5 us at 2 against 30.9 at 4 and 36.1 at 1 on the
-// 512^2 fan; 3D 355 us at 1 against 372 at 2 and 402 at 4 on the 256^3 cone)
-__host__ __device__ constexpr int bp_split(int dim) { return dim == 3 ? 1 : 2; }
+// views of a voxel split over this many waves: four in 2D (where each lane carries two
+// voxels), one in 3D. Measured on the 512^2 fan (2D back projection per iteration): one
+// voxel per lane 36.1 / 30.5 / 30.9 us at 1 / 2 / 4 waves; two voxels per lane 29.4 /
+// 24.0 / 24.6 us at 2 / 4 / 8 waves. On the 256^3 cone (3D): 355 / 372 / 402 us at 1 / 2 / 4.
+__host__ __device__ constexpr int bp_split(int dim) { return dim == 3 ? 1 : 4; }
 __host__ __device__ constexpr int bp_wg(int dim) { return BP_VOX * bp_split(dim); }
 
 template <int DIM>
@@ -821,14 +914,113 @@ __device__ __forceinline__ bool tile_voxel(const BlockInfo& B, int tile, int vl,
 // change of those residuals, read from `src` in the z layout of each pair (k_subdet_delta
 // wrote it); no g_hat. A voxel's update reads only r (or d), so voxels are independent
 // (no atomics).
+// 2D solver tiles: 16 x 8 voxels per wave, each lane two x-adjacent voxels.
+constexpr int PAIR_TX = 16, PAIR_TY = 8;
+
+// Lane vl's voxel pair in pair tile `tile` of block B: a at li, b one voxel further in x.
+__device__ __forceinline__ void pair_tile_voxels(const BlockInfo& B, int tile, int vl, int (&li)[3], bool& tile_ok,
+                                                 bool& a_ok, bool& b_ok)
+{
+    const int tx_n = (B.nbx + PAIR_TX - 1) / PAIR_TX, ty_n = (B.nby + PAIR_TY - 1) / PAIR_TY;
+    tile_ok = tile < tx_n * ty_n;
+    li[0] = (tile % tx_n) * PAIR_TX + 2 * (vl % (PAIR_TX / 2));
+    li[1] = (tile / tx_n) * PAIR_TY + vl / (PAIR_TX / 2);
+    li[2] = 0;
+    a_ok = tile_ok && li[0] < B.nbx && li[1] < B.nby;
+    b_ok = a_ok && li[0] + 1 < B.nbx;
+}
+
+// bp_step_body for 2D: each lane two x-adjacent voxels (bp_voxel_pair_view_2d), the
+// same per-voxel update for both.
+template <bool SUB>
+__device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t* __restrict__ S_,
+                                                const PairWork* __restrict__ work, SchedLayout L,
+                                                const float* __restrict__ src, float* __restrict__ ghat,
+                                                float* __restrict__ gsum, float* __restrict__ x,
+                                                const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
+                                                float (&part)[bp_split(2)][2][BP_VOX])
+{
+    const int b = by;
+    const int j = S_[L.off_blocks() + b];
+    const BlockInfo B = G.blocks[j];
+    int nb[3];
+    float h[3], vs[3];
+    block_dims(G, B, nb, h, vs);
+    const int vl = threadIdx.x % BP_VOX;
+    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
+    int li[3];
+    bool tile_ok, a_ok, b_ok;
+    pair_tile_voxels(B, bx, vl, li, tile_ok, a_ok, b_ok);
+    if (!tile_ok) return;  // uniform over the workgroup
+    const int64_t vox = ((int64_t)(B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
+    const int per_view = G.nu;
+    const PairWork* wb = work + (int64_t)b * L.maxv;
+    float dga = 0.0f, dgb = 0.0f;
+    for (int ri = 0; ri < L.R; ++ri) {
+        const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
+        float acc_a = 0.0f, acc_b = 0.0f;
+        if (a_ok) {
+            for (int a = a0 + grp; a < a1; a += bp_split(2)) {
+                const PairWork W = wb[a];
+                if (W.k1 <= W.k0) continue;
+                if (SUB)
+                    bp_voxel_pair_view_2d<false>(G, W.view, W.c, W.s, W, li, b_ok, h, vs, W.k0, W.k1, src + W.zbase,
+                                                 acc_a, acc_b);
+                else
+                    bp_voxel_pair_view_2d<true>(G, W.view, W.c, W.s, W, li, b_ok, h, vs, W.k0, W.k1,
+                                                src + (int64_t)a * per_view * 4, acc_a, acc_b);
+            }
+        }
+        part[grp][0][vl] = acc_a;
+        part[grp][1][vl] = acc_b;
+        __syncthreads();
+        if (grp == 0 && a_ok) {
+            float sa = part[0][0][vl], sb = part[0][1][vl];
+#pragma unroll
+            for (int q = 1; q < bp_split(2); ++q) {
+                sa += part[q][0][vl];
+                sb += part[q][1][vl];
+            }
+            if (SUB) {
+                dga += 2.0f * sa;
+                dgb += 2.0f * sb;
+            } else {
+                const int i = S_[L.off_rows() + ri];
+                float* gp = ghat + (int64_t)i * n_vox + vox;
+                const float ga = 2.0f * sa;
+                dga += ga - gp[0];
+                gp[0] = ga;
+                if (b_ok) {
+                    const float gb = 2.0f * sb;
+                    dgb += gb - gp[1];
+                    gp[1] = gb;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (grp == 0 && a_ok) {
+        const float mu = *mu_ptr;
+        const float gva = gsum[vox] + dga;
+        gsum[vox] = gva;
+        x[vox] = fmaf(mu, gva, x[vox]);
+        if (b_ok) {
+            const float gvb = gsum[vox + 1] + dgb;
+            gsum[vox + 1] = gvb;
+            x[vox + 1] = fmaf(mu, gvb, x[vox + 1]);
+        }
+    }
+}
+
 template <int DIM, bool SUB>
 __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __restrict__ S_,
                                              const PairWork* __restrict__ work, SchedLayout L,
                                              const float* __restrict__ src, float* __restrict__ ghat,
                                              float* __restrict__ gsum, float* __restrict__ x,
                                              const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
-                                             float (&part)[bp_split(DIM)][BP_VOX])
+                                             float (&part)[bp_split(DIM)][1][BP_VOX])
 {
+    static_assert(DIM == 3, "2D uses bp_step_body_2d");
     const int b = by;
     const int j = S_[L.off_blocks() + b];
     const BlockInfo B = G.blocks[j];
@@ -852,22 +1044,16 @@ __device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __
             for (int a = a0 + grp; a < a1; a += bp_split(DIM)) {
                 const PairWork W = wb[a];
                 if (W.k1 <= W.k0) continue;
-                if (DIM == 2 && SUB)
-                    acc += bp_voxel_view_2d<false>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, src + W.zbase);
-                else if (DIM == 2)
-                    acc += bp_voxel_view_2d<true>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1,
-                                                  src + (int64_t)a * per_view * 4);
-                else
-                    acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
-                                              SUB ? src + W.zbase : src + (int64_t)a * per_view, SUB ? W.zw : G.nu);
+                acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
+                                          SUB ? src + W.zbase : src + (int64_t)a * per_view, SUB ? W.zw : G.nu);
             }
         }
-        part[grp][vl] = acc;
+        part[grp][0][vl] = acc;
         __syncthreads();
         if (grp == 0 && valid) {
-            float sum = part[0][vl];
+            float sum = part[0][0][vl];
 #pragma unroll
-            for (int q = 1; q < bp_split(DIM); ++q) sum += part[q][vl];
+            for (int q = 1; q < bp_split(DIM); ++q) sum += part[q][0][vl];
             if (SUB) {
                 dg += 2.0f * sum;
             } else {
@@ -894,10 +1080,13 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t
                                                 float* __restrict__ x, const float* __restrict__ mu,
                                                 long long n_vox)
 {
-    __shared__ float part[bp_split(DIM)][BP_VOX];
+    __shared__ float part[bp_split(DIM)][DIM == 2 ? 2 : 1][BP_VOX];
     int bx, by;
     xcd_grid2(bx, by);
-    bp_step_body<DIM, SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
+    if constexpr (DIM == 2)
+        bp_step_body_2d<SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
+    else
+        bp_step_body<DIM, SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
 }
 
 // Sub-detector gradient memory: one workgroup per (view slot, block slot) pair. Over the
@@ -979,15 +1168,19 @@ __global__ __launch_bounds__(TPB) void k_resid_batch(const BatchArgs A)
 template <int DIM>
 __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_batch(const BatchArgs A)
 {
-    __shared__ float part[bp_split(DIM)][BP_VOX];
+    __shared__ float part[bp_split(DIM)][DIM == 2 ? 2 : 1][BP_VOX];
     const int id = xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 2, id));
     const BatchEntry& B = A.e[e];
     const int local = id - B.base[2];
     const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
     const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
-    bp_step_body<DIM, false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
-                      local / B.gx[2], part);
+    if constexpr (DIM == 2)
+        bp_step_body_2d<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
+                               local / B.gx[2], part);
+    else
+        bp_step_body<DIM, false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
+                                 local / B.gx[2], part);
 }
 
 // ------------------------------------------------------------ standalone projectors
@@ -1293,6 +1486,7 @@ size_t fp_lds_bytes_for(const DevGeom& G)
 size_t resid_lds_bytes_for(const DevGeom& G) { return resid_lds_bytes(G, res_wg(G.dim)); }
 
 static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int dim);
+static int step_tiles(const DevGeom& G);
 
 void batch_grids(BatchEntry& e)
 {
@@ -1308,7 +1502,7 @@ void batch_grids(BatchEntry& e)
         e.gx[0] = (int)(((int64_t)L.maxv * L.B * std::max(1, G.fp_wpp) + 3) / 4);
     }
     e.gx[1] = (G.nu * G.nv + res_wg(G.dim) - 1) / res_wg(G.dim);
-    e.gx[2] = max_tiles(G, nullptr, G.dim);
+    e.gx[2] = step_tiles(G);
 }
 
 hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], const FpLaunchClass* fp_classes,
@@ -1368,11 +1562,19 @@ static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int 
     return ((mbx + Tile<2>::X - 1) / Tile<2>::X) * ((mby + Tile<2>::Y - 1) / Tile<2>::Y);
 }
 
+// Workgroups per block of the solver's back projection: 2D pair tiles, 3D tiles.
+static int step_tiles(const DevGeom& G)
+{
+    if (G.dim == 3) return max_tiles(G, nullptr, 3);
+    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by;
+    return ((mbx + PAIR_TX - 1) / PAIR_TX) * ((mby + PAIR_TY - 1) / PAIR_TY);
+}
+
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
                           const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, const float* mu,
                           int64_t n_vox, hipStream_t st)
 {
-    const int tiles = max_tiles(G, nullptr, G.dim);
+    const int tiles = step_tiles(G);
     const dim3 grid(tiles, L.B), blk(bp_wg(G.dim));
     const long long nv = (long long)n_vox;
     if (delta) {
