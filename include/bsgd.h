@@ -125,7 +125,7 @@ typedef enum {
 bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* out, size_t bytes);
 
 /* Launch-shape tuning of a geometry. fp_views_per_group: views whose rays one
- * workgroup of the LDS-staged forward projector walks, in [1, 16] (default 3); it
+ * workgroup of the LDS-staged forward projector walks, in [1, 16] (default 12); it
  * does not change any result. fp_ray_split: lanes that share one ray of a 2D forward
  * projection through a block, 1, 2 or 4 (default 1): the chord is cut into that many
  * equal parameter segments, walked in parallel and summed in a fixed order, so

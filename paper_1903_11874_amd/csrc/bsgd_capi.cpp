@@ -539,7 +539,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.blocks = g->d_blocks.as<BlockInfo>();
     G.raydir = g->d_raydir.as<float4>();
     G.rayv = g->d_rayv.as<float2>();
-    G.fp_chunk = 3;
+    G.fp_chunk = 12;
     G.fp_split = 1;
     // waves per pair of the global-memory forward projector: one per 48 pixels of the
     // mean footprint (about one 64-pixel round per wave; more, shorter waves hide the

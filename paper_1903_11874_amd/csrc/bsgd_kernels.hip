@@ -581,6 +581,7 @@ __global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __re
 }
 
 constexpr int FP_MAX_CHUNK = 16;
+constexpr int FP_LDS_WG = 1024;  // threads per workgroup of the single-solve LDS forward projector
 constexpr int FP_LDS_MAX_FLOATS = 16384;  // block copies up to 64 KB are staged in LDS; larger blocks read x from global memory
 
 // Workgroup per (view chunk, block slot): the block's image tile is copied to LDS
@@ -591,7 +592,7 @@ struct FpLds {
     int off[FP_MAX_CHUNK + 1];
 };
 
-template <int DIM>
+template <int DIM, int TPB>
 __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __restrict__ work, SchedLayout L,
                                             const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
                                             float* __restrict__ z, int chunk, int bx, int by, float* xs, FpLds& sh)
@@ -608,14 +609,14 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
     const int rs = B.nbx + (DIM == 2 ? 1 : 0);
     const int plane = rs * B.nby;
     const int nvox_b = B.nbx * B.nby * B.nbz;
-    for (int i = threadIdx.x; i < nvox_b; i += WG) {
+    for (int i = threadIdx.x; i < nvox_b; i += TPB) {
         const int ix = i % B.nbx, iy = (i / B.nbx) % B.nby, iz = i / (B.nbx * B.nby);
         xs[iz * plane + iy * rs + ix] = x[((int64_t)(B.z0 + iz) * G.ny + (B.y0 + iy)) * (int64_t)G.nx + (B.x0 + ix)];
     }
     // the walk may step one pixel past an x face with a length of a few ulps; that
     // read lands in the padding column, which must hold a finite value
     if (DIM == 2)
-        for (int iy = threadIdx.x; iy < B.nby; iy += WG) xs[iy * rs + B.nbx] = 0.0f;
+        for (int iy = threadIdx.x; iy < B.nby; iy += TPB) xs[iy * rs + B.nbx] = 0.0f;
     __syncthreads();
     if (threadIdx.x == 0) {
         int off = 0;
@@ -639,9 +640,9 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
         // every thread runs every round (items past the end are dead lanes), so the
         // walk's wave-uniform trip count and the shuffles see all 64 lanes
         const int n_items = total << lg;
-        const int rounds = (n_items + WG - 1) / WG;
+        const int rounds = (n_items + TPB - 1) / TPB;
         for (int rd = 0; rd < rounds; ++rd) {
-            const int item = rd * WG + (int)threadIdx.x;
+            const int item = rd * TPB + (int)threadIdx.x;
             const bool on = item < n_items;
             const int ray = on ? (item >> lg) : 0, seg = item & (S - 1);
             int q = 0;
@@ -662,7 +663,7 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
         }
         return;
     }
-    for (int item = threadIdx.x; item < total; item += WG) {
+    for (int item = threadIdx.x; item < total; item += TPB) {
         int q = 0;
         while (sh.off[q + 1] <= item) ++q;
         const PairWork& W = sh.pw[q];
@@ -679,7 +680,7 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
 // once and every ray of the chunk's pairs walks it there. Work items are the rays
 // of all pairs of the chunk, flattened.
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
+__global__ __launch_bounds__(FP_LDS_WG) void k_fp_pairs_lds(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
                                                      const int32_t* __restrict__ blocks_sel,
                                                      const float* __restrict__ x, float* __restrict__ z, int chunk)
 {
@@ -687,7 +688,7 @@ __global__ __launch_bounds__(WG) void k_fp_pairs_lds(DevGeom G, const PairWork* 
     __shared__ FpLds sh;
     int bx, by;
     xcd_grid2(bx, by);
-    fp_lds_body<DIM>(G, work, L, blocks_sel, x, z, chunk, bx, by, xs, sh);
+    fp_lds_body<DIM, FP_LDS_WG>(G, work, L, blocks_sel, x, z, chunk, bx, by, xs, sh);
 }
 
 // ------------------------------------------------------------ solver: residual rebuild
@@ -1133,8 +1134,11 @@ __device__ __forceinline__ int find_entry(const BatchEntry* E, int n, int phase,
     return lo;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(WG) void k_fp_batch(const BatchArgs A)
+// TPB: FP_LDS_WG for the LDS-staged entries' launch classes, WG for the global-memory
+// class (whose per-entry grid counts WG / 64 waves per workgroup); a class never mixes
+// the two (their LDS sizes differ).
+template <int DIM, int TPB>
+__global__ __launch_bounds__(TPB) void k_fp_batch(const BatchArgs A)
 {
     extern __shared__ float xs[];
     __shared__ FpLds sh;
@@ -1144,11 +1148,12 @@ __global__ __launch_bounds__(WG) void k_fp_batch(const BatchArgs A)
     const int local = id - B.base[0];
     const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
     const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
-    if (B.fp_lds) {
-        fp_lds_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, B.fp_chunk, local % B.gx[0],
-                         local / B.gx[0], xs, sh);
-    } else {
-        const int wave = __builtin_amdgcn_readfirstlane(local * (WG / 64) + (threadIdx.x >> 6));
+    if (TPB == FP_LDS_WG) {
+        if (B.fp_lds)
+            fp_lds_body<DIM, TPB>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, B.fp_chunk, local % B.gx[0],
+                                  local / B.gx[0], xs, sh);
+    } else if (!B.fp_lds) {
+        const int wave = __builtin_amdgcn_readfirstlane(local * (TPB / 64) + (threadIdx.x >> 6));
         fp_global_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, wave, threadIdx.x & 63);
     }
 }
@@ -1461,10 +1466,10 @@ hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayou
         const unsigned gx = (unsigned)((L.maxv + chunk - 1) / chunk);
         const size_t lds = (size_t)tile * sizeof(float);
         if (G.dim == 3)
-            hipLaunchKernelGGL(k_fp_pairs_lds<3>, dim3(gx, L.B), dim3(WG), lds, st, G, work_it, L, blocks_sel, x, z,
+            hipLaunchKernelGGL(k_fp_pairs_lds<3>, dim3(gx, L.B), dim3(FP_LDS_WG), lds, st, G, work_it, L, blocks_sel, x, z,
                                chunk);
         else
-            hipLaunchKernelGGL(k_fp_pairs_lds<2>, dim3(gx, L.B), dim3(WG), lds, st, G, work_it, L, blocks_sel, x, z,
+            hipLaunchKernelGGL(k_fp_pairs_lds<2>, dim3(gx, L.B), dim3(FP_LDS_WG), lds, st, G, work_it, L, blocks_sel, x, z,
                                chunk);
         return hipGetLastError();
     }
@@ -1516,10 +1521,16 @@ hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], co
         const FpLaunchClass& k = fp_classes[c];
         if (k.wgs <= 0) continue;
         A.id0 = k.wg0;
-        if (dim == 3)
-            hipLaunchKernelGGL(k_fp_batch<3>, dim3(k.wgs), dim3(WG), k.lds_bytes, st, A);
-        else
-            hipLaunchKernelGGL(k_fp_batch<2>, dim3(k.wgs), dim3(WG), k.lds_bytes, st, A);
+        if (k.lds_bytes > 0) {
+            if (dim == 3)
+                hipLaunchKernelGGL((k_fp_batch<3, FP_LDS_WG>), dim3(k.wgs), dim3(FP_LDS_WG), k.lds_bytes, st, A);
+            else
+                hipLaunchKernelGGL((k_fp_batch<2, FP_LDS_WG>), dim3(k.wgs), dim3(FP_LDS_WG), k.lds_bytes, st, A);
+        } else if (dim == 3) {
+            hipLaunchKernelGGL((k_fp_batch<3, WG>), dim3(k.wgs), dim3(WG), 0, st, A);
+        } else {
+            hipLaunchKernelGGL((k_fp_batch<2, WG>), dim3(k.wgs), dim3(WG), 0, st, A);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -9,7 +9,7 @@ from typing import Dict, Sequence, Tuple
 
 from .bsgd import Geometry, Solver
 
-VIEWS = (1, 2, 3, 4, 6, 8, 12)
+VIEWS = (1, 2, 3, 4, 6, 8, 12, 16)
 SPLITS = (1, 2, 4)
 
 
