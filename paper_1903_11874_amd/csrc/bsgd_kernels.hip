@@ -1198,30 +1198,56 @@ __global__ __launch_bounds__(WG) void k_fp_full(DevGeom G, const int32_t* __rest
     const int a = blockIdx.y;
     const int per_view = G.nu * G.nv;
     const int ray = blockIdx.x * WG + threadIdx.x;
-    if (a >= n_sel || ray >= per_view) return;
+    if (a >= n_sel) return;
     const int v = views[a];
-    const int k = ray % G.nu, l = ray / G.nu;
     const float2 cs = G.cs[v];
     const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
     float acc = 0.0f;
-    for (int j = j0; j < j1; ++j) {
-        const PairInfo P = G.pairs[(int64_t)v * G.N + j];
-        if (k >= P.u0 && k < P.u1 && l >= P.v0 && l < P.v1) {
+    if (DIM == 2) {
+        // every lane of the wave takes part in each block's wave-uniform walk (lanes
+        // past the view's pixels or outside the footprint are dead)
+        const bool on = ray < per_view;
+        const int k = on ? ray : 0;
+        for (int j = j0; j < j1; ++j) {
+            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
             const BlockInfo B = G.blocks[j];
-            const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
-            acc += fp_ray_block<DIM>(G, v, cs.x, cs.y, P, B, k, l, xb, sy, sz);
+            int nb[3];
+            float h[3], vs[3];
+            block_dims(G, B, nb, h, vs);
+            Ray R;
+            make_ray<2>(G, v, cs.x, cs.y, P, k, 0, R);
+            float tlo = 0.0f, thi = 0.0f;
+            const bool hit = on && k >= P.u0 && k < P.u1 && slab_2d(R, nb, h, vs, tlo, thi);
+            const float* xb = x + (int64_t)B.y0 * G.nx + B.x0;
+            const float s = walk_2d_range_wave(R, nb, h, vs, (int)sy, tlo, thi, hit,
+                                               [&](unsigned off) { return xb[off]; });
+            if (hit) acc += s * R.len;
+        }
+        if (!on) return;
+    } else {
+        if (ray >= per_view) return;
+        const int k = ray % G.nu, l = ray / G.nu;
+        for (int j = j0; j < j1; ++j) {
+            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+            if (k >= P.u0 && k < P.u1 && l >= P.v0 && l < P.v1) {
+                const BlockInfo B = G.blocks[j];
+                const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
+                acc += fp_ray_block<DIM>(G, v, cs.x, cs.y, P, B, k, l, xb, sy, sz);
+            }
         }
     }
     float* dst = y + (int64_t)a * per_view + ray;
     *dst = accumulate ? *dst + acc : acc;
 }
 
+// Standalone back projection into block j0 + blockIdx.y: 3D one voxel per lane (tiles
+// of 64), 2D two x-adjacent voxels per lane (pair tiles, as the solver's).
 template <int DIM>
 __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_full(DevGeom G, const int32_t* __restrict__ views, int n_sel, int j0,
                                                 const float* __restrict__ y, float* __restrict__ x, float scale,
                                                 int accumulate)
 {
-    __shared__ float part[bp_split(DIM)][BP_VOX];
+    __shared__ float part[bp_split(DIM)][DIM == 2 ? 2 : 1][BP_VOX];
     const int j = j0 + blockIdx.y;
     const BlockInfo B = G.blocks[j];
     int nb[3];
@@ -1230,11 +1256,15 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_full(DevGeom G, const int32_t
     const int vl = threadIdx.x % BP_VOX;
     const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
     int li[3];
-    bool tile_ok;
-    const bool valid = tile_voxel<DIM>(B, blockIdx.x, vl, li, tile_ok);
+    bool tile_ok, valid, b_ok = false;
+    if (DIM == 2) {
+        pair_tile_voxels(B, blockIdx.x, vl, li, tile_ok, valid, b_ok);
+    } else {
+        valid = tile_voxel<DIM>(B, blockIdx.x, vl, li, tile_ok);
+    }
     if (!tile_ok) return;
     const int per_view = G.nu * G.nv;
-    float acc = 0.0f;
+    float acc = 0.0f, acc_b = 0.0f;
     if (valid) {
         for (int a = grp; a < n_sel; a += bp_split(DIM)) {
             const int v = views[a];
@@ -1242,21 +1272,31 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_full(DevGeom G, const int32_t
             if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
             const float2 cs = G.cs[v];
             if (DIM == 2)
-                acc += bp_voxel_view_2d<false>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, y + (int64_t)a * per_view);
+                bp_voxel_pair_view_2d<false>(G, v, cs.x, cs.y, P, li, b_ok, h, vs, P.u0, P.u1,
+                                             y + (int64_t)a * per_view, acc, acc_b);
             else
                 acc += bp_voxel_view<DIM>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
                                           y + (int64_t)a * per_view, G.nu);
         }
     }
-    part[grp][vl] = acc;
+    constexpr int IB = DIM == 2 ? 1 : 0;  // slot of the second voxel's partial sums (2D)
+    part[grp][0][vl] = acc;
+    part[grp][IB][vl] = DIM == 2 ? acc_b : acc;
     __syncthreads();
     if (grp == 0 && valid) {
-        float sum = part[0][vl];
+        float sum = part[0][0][vl], sum_b = part[0][IB][vl];
 #pragma unroll
-        for (int q = 1; q < bp_split(DIM); ++q) sum += part[q][vl];
+        for (int q = 1; q < bp_split(DIM); ++q) {
+            sum += part[q][0][vl];
+            sum_b += part[q][IB][vl];
+        }
         const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
         const float val = scale * sum;
         x[vox] = accumulate ? x[vox] + val : val;
+        if (DIM == 2 && b_ok) {
+            const float vb = scale * sum_b;
+            x[vox + 1] = accumulate ? x[vox + 1] + vb : vb;
+        }
     }
 }
 
@@ -1631,7 +1671,7 @@ hipError_t launch_fp_full(const DevGeom& G, const int32_t* views, int n_sel, int
 hipError_t launch_bp_full(const DevGeom& G, const int32_t* views, int n_sel, int block, const float* y, float* x,
                           float scale, int accumulate, hipStream_t st)
 {
-    const int tiles = max_tiles(G, nullptr, G.dim);
+    const int tiles = step_tiles(G);
     const int j0 = block < 0 ? 0 : block, nj = block < 0 ? G.N : 1;
     if (G.dim == 3)
         hipLaunchKernelGGL(k_bp_full<3>, dim3(tiles, nj), dim3(bp_wg(3)), 0, st, G, views, n_sel, j0, y, x, scale,
