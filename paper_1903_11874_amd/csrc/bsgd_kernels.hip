@@ -1198,42 +1198,18 @@ __global__ __launch_bounds__(WG) void k_fp_full(DevGeom G, const int32_t* __rest
     const int a = blockIdx.y;
     const int per_view = G.nu * G.nv;
     const int ray = blockIdx.x * WG + threadIdx.x;
-    if (a >= n_sel) return;
+    if (a >= n_sel || ray >= per_view) return;
     const int v = views[a];
+    const int k = ray % G.nu, l = ray / G.nu;
     const float2 cs = G.cs[v];
     const int64_t sy = G.nx, sz = (int64_t)G.nx * G.ny;
     float acc = 0.0f;
-    if (DIM == 2) {
-        // every lane of the wave takes part in each block's wave-uniform walk (lanes
-        // past the view's pixels or outside the footprint are dead)
-        const bool on = ray < per_view;
-        const int k = on ? ray : 0;
-        for (int j = j0; j < j1; ++j) {
-            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+    for (int j = j0; j < j1; ++j) {
+        const PairInfo P = G.pairs[(int64_t)v * G.N + j];
+        if (k >= P.u0 && k < P.u1 && l >= P.v0 && l < P.v1) {
             const BlockInfo B = G.blocks[j];
-            int nb[3];
-            float h[3], vs[3];
-            block_dims(G, B, nb, h, vs);
-            Ray R;
-            make_ray<2>(G, v, cs.x, cs.y, P, k, 0, R);
-            float tlo = 0.0f, thi = 0.0f;
-            const bool hit = on && k >= P.u0 && k < P.u1 && slab_2d(R, nb, h, vs, tlo, thi);
-            const float* xb = x + (int64_t)B.y0 * G.nx + B.x0;
-            const float s = walk_2d_range_wave(R, nb, h, vs, (int)sy, tlo, thi, hit,
-                                               [&](unsigned off) { return xb[off]; });
-            if (hit) acc += s * R.len;
-        }
-        if (!on) return;
-    } else {
-        if (ray >= per_view) return;
-        const int k = ray % G.nu, l = ray / G.nu;
-        for (int j = j0; j < j1; ++j) {
-            const PairInfo P = G.pairs[(int64_t)v * G.N + j];
-            if (k >= P.u0 && k < P.u1 && l >= P.v0 && l < P.v1) {
-                const BlockInfo B = G.blocks[j];
-                const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
-                acc += fp_ray_block<DIM>(G, v, cs.x, cs.y, P, B, k, l, xb, sy, sz);
-            }
+            const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
+            acc += fp_ray_block<DIM>(G, v, cs.x, cs.y, P, B, k, l, xb, sy, sz);
         }
     }
     float* dst = y + (int64_t)a * per_view + ray;
