@@ -220,89 +220,9 @@ __device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float
     return acc;
 }
 
-// 2D back projection of one view into one voxel with the closed-form chord: the
-// candidate rays are those whose pixel lies within kspan / depth of the projection
-// of the voxel centre; each contributes chord_2d(delta) * r. PACKED: src is the
-// view's row of per-ray records {w2, slope, lmax, r} (the trapezoid of the ray's
-// chord and its residual, written by the residual rebuild), so a candidate takes two
-// gathers (normal, record) instead of three; otherwise src is the view's residuals
-// and the trapezoid comes from the static table. Same arithmetic either way.
-template <bool PACKED, class Anchor>
-__device__ __forceinline__ float bp_voxel_view_2d(const DevGeom& G, int view, float c, float s, const Anchor& P,
-                                                  const int (&li)[3], const float (&h)[3], const float (&vs)[3],
-                                                  int k0, int k1, const float* __restrict__ src)
-{
-    const float qx = plane_pos(li[0], vs[0], h[0]) + 0.5f * vs[0];
-    const float qy = plane_pos(li[1], vs[1], h[1]) + 0.5f * vs[1];
-    const float w = fmaf(qy, c, -(qx * s)) + P.cu;  // lateral coordinate of the voxel centre
-    const float ku = 0.5f * (float)(G.nu - 1);
-    const float inv_du = __builtin_amdgcn_rcpf(G.du);
-    float kc, span;
-    if (G.kind == KIND_PARALLEL_2D) {
-        kc = fmaf(w, inv_du, ku);
-        span = G.kspan[view];
-    } else {
-        const float rdep = __builtin_amdgcn_rcpf(P.depth - fmaf(qx, c, qy * s));
-        kc = fmaf(G.sdd * w * rdep, inv_du, ku);
-        span = G.kspan[view] * rdep;
-    }
-    // the float clamp keeps the conversions in range and klo >= k0
-    const int klo = (int)ceilf(fminf(fmaxf(kc - span - SHADOW_EPS, (float)k0), (float)k1));
-    const int khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kc + span + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
-    const float4* nrm = G.raynorm + (int64_t)view * G.nu;
-    const float4* trp = G.raytrap + (int64_t)view * G.nu;
-    const float4* rec = reinterpret_cast<const float4*>(src);
-    // the first BP_AHEAD candidates' gathers are issued together, each only by the
-    // lanes whose range holds it, then consumed in ascending k; wider ranges continue
-    // in a loop. Offsets are 32-bit bytes from the view's (wave-uniform) rows, so each
-    // gather takes a scalar base and one vector offset.
-    float4 n[BP_AHEAD], t[BP_AHEAD];
-    float r[BP_AHEAD];
-#pragma unroll
-    for (int i = 0; i < BP_AHEAD; ++i) {
-        if (klo + i <= khi) {
-            const uint32_t kk = (uint32_t)(klo + i);
-            n[i] = ld_off(nrm, kk * 16u);
-            if constexpr (PACKED) {
-                t[i] = ld_off(rec, kk * 16u);
-            } else {
-                t[i] = ld_off(trp, kk * 16u);
-                r[i] = ld_off(src, kk * 4u);
-            }
-        }
-    }
-    // lateral offset of candidate klo + i: lam0 + i au (lam0 that of klo)
-    const float lam0 = fmaf((float)(klo - P.kc), P.au, P.bu);
-    float acc = 0.0f;
-#pragma unroll
-    for (int i = 0; i < BP_AHEAD; ++i) {
-        if (klo + i <= khi) {
-            const float lam = fmaf((float)i, P.au, lam0);
-            const float delta = fmaf(n[i].x, qx, fmaf(n[i].y, qy, -(lam * n[i].z)));
-            if constexpr (PACKED)
-                acc = fmaf(chord_2d_rec(delta, t[i]), t[i].w, acc);
-            else
-                acc = fmaf(chord_2d(delta, t[i]), r[i], acc);
-        }
-    }
-    for (int k = klo + BP_AHEAD; k <= khi; ++k) {
-        const uint32_t kk = (uint32_t)k;
-        const float4 nk = ld_off(nrm, kk * 16u);
-        const float lam = fmaf((float)(k - klo), P.au, lam0);
-        const float delta = fmaf(nk.x, qx, fmaf(nk.y, qy, -(lam * nk.z)));
-        if constexpr (PACKED) {
-            const float4 tk = ld_off(rec, kk * 16u);
-            acc = fmaf(chord_2d_rec(delta, tk), tk.w, acc);
-        } else {
-            acc = fmaf(chord_2d(delta, ld_off(trp, kk * 16u)), ld_off(src, kk * 4u), acc);
-        }
-    }
-    return acc;
-}
-
 // Candidate pixel range [klo, khi] of a 2D voxel centre (qx, qy), block-local, in one
-// view (as in bp_voxel_view_2d): pixels within kc -/+ span of the centre's projection,
-// clipped to [k0, k1).
+// view: the pixels within kc -/+ span of the projection of the centre (kspan / depth for
+// a fan, kspan for parallel rays; kspan bounds the chord's support), clipped to [k0, k1).
 template <class Anchor>
 __device__ __forceinline__ void bp2d_range(const DevGeom& G, int view, float c, float s, const Anchor& P, float qx,
                                            float qy, int k0, int k1, int& klo, int& khi)
@@ -886,10 +806,6 @@ __host__ __device__ constexpr int bp_wg(int dim) { return BP_VOX * bp_split(dim)
 template <int DIM>
 struct Tile;
 template <>
-struct Tile<2> {
-    static constexpr int X = 8, Y = 8, Z = 1;
-};
-template <>
 struct Tile<3> {
     static constexpr int X = 4, Y = 4, Z = 4;
 };
@@ -1233,11 +1149,10 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_full(DevGeom G, const int32_t
     const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
     int li[3];
     bool tile_ok, valid, b_ok = false;
-    if (DIM == 2) {
+    if constexpr (DIM == 2)
         pair_tile_voxels(B, blockIdx.x, vl, li, tile_ok, valid, b_ok);
-    } else {
+    else
         valid = tile_voxel<DIM>(B, blockIdx.x, vl, li, tile_ok);
-    }
     if (!tile_ok) return;
     const int per_view = G.nu * G.nv;
     float acc = 0.0f, acc_b = 0.0f;
@@ -1506,7 +1421,6 @@ size_t fp_lds_bytes_for(const DevGeom& G)
 
 size_t resid_lds_bytes_for(const DevGeom& G) { return resid_lds_bytes(G, res_wg(G.dim)); }
 
-static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int dim);
 static int step_tiles(const DevGeom& G);
 
 void batch_grids(BatchEntry& e)
@@ -1579,21 +1493,14 @@ hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L
     return hipGetLastError();
 }
 
-static int max_tiles(const DevGeom& G, const BlockInfo* host_blocks_unused, int dim)
-{
-    (void)host_blocks_unused;
-    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by, mbz = (G.nz + G.bz - 1) / G.bz;
-    if (dim == 3)
-        return ((mbx + Tile<3>::X - 1) / Tile<3>::X) * ((mby + Tile<3>::Y - 1) / Tile<3>::Y) *
-               ((mbz + Tile<3>::Z - 1) / Tile<3>::Z);
-    return ((mbx + Tile<2>::X - 1) / Tile<2>::X) * ((mby + Tile<2>::Y - 1) / Tile<2>::Y);
-}
 
-// Workgroups per block of the solver's back projection: 2D pair tiles, 3D tiles.
+// Workgroups per block of the back projectors (largest block): 2D pair tiles, 3D tiles.
 static int step_tiles(const DevGeom& G)
 {
-    if (G.dim == 3) return max_tiles(G, nullptr, 3);
-    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by;
+    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by, mbz = (G.nz + G.bz - 1) / G.bz;
+    if (G.dim == 3)
+        return ((mbx + Tile<3>::X - 1) / Tile<3>::X) * ((mby + Tile<3>::Y - 1) / Tile<3>::Y) *
+               ((mbz + Tile<3>::Z - 1) / Tile<3>::Z);
     return ((mbx + PAIR_TX - 1) / PAIR_TX) * ((mby + PAIR_TY - 1) / PAIR_TY);
 }
 
