@@ -225,6 +225,7 @@ def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
     server = Server(max_slots=max_slots)
     mus = {}
     reqs = []
+    truths = {}
     t = 0.0
     for rid in range(n_requests):
         t += rng.exponential(1.0 / rate)
@@ -236,6 +237,7 @@ def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
         if spec not in mus:
             mus[spec] = 0.5 / (2.0 * lipschitz_gpu(geom, spec.nx * spec.ny, iters=15))
         x_true = torch.tensor(phantom_for(spec, 10, 5000 + rid), dtype=torch.float32, device="cuda")
+        truths[rid] = x_true
         y = add_gaussian_noise(geom.forward_project(x_true).double().cpu().numpy(), 0.01, 6000 + rid)
         reqs.append(Request(rid=rid, geometry=spec, y=torch.tensor(y, dtype=torch.float32, device="cuda"),
                             arrival=t, mu=mus[spec], seed=rid, node_count=64, tol=tol, max_epochs=max_epochs,
@@ -248,6 +250,14 @@ def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
     seq = Server(max_slots=1).run_sequential(reqs)
     same = all(torch.equal(a.x, b.x) for a, b in zip(served, seq))
     st_b, st_s = latency_stats(served), latency_stats(seq)
+
+    def snr(results):  # image SNR against each request's phantom, 20 log10(|x_true| / |x_true - x|)
+        v = [float(20.0 * torch.log10(truths[r.rid].double().norm() / (truths[r.rid].double() - r.x.double()).norm()))
+             for r in results]
+        return {"mean_snr_db": float(np.mean(v)), "min_snr_db": float(np.min(v))}
+
+    st_b.update(snr(served))
+    st_s.update(snr(seq))
     return {"requests": n_requests, "rate_per_s": rate, "arrival_span_s": t, "max_slots": max_slots,
             "stop_rule": f"||A^T(y-Ax)||/||A^T y|| <= {tol} checked every 5 epochs, at most {max_epochs} epochs",
             "batched": st_b, "sequential": st_s,
