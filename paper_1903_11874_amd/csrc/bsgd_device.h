@@ -109,6 +109,10 @@ struct Ray {
     float len;     // |d| (mm per unit t)
 };
 
+// steps of the 3D / 2D wave-uniform walks whose loads are issued together
+constexpr int WALK_UNROLL = 8;
+constexpr int WALK2_UNROLL = 4;
+
 __device__ __forceinline__ bool axis_fixed(float inv) { return __builtin_isinf(inv); }
 
 // P is a PairInfo or a PairWork (same anchor fields).
@@ -359,7 +363,31 @@ __device__ __forceinline__ float walk_2d_range_wave(const Ray& R, const int (&nb
     const unsigned last = (unsigned)((nb[1] - 1) * sy + nb[0] - 1);
     int off = iy * sy + ix;
     float t = t0, acc = 0.0f;
-    for (int it = 0; it < n_wave; ++it) {
+    // WALK2_UNROLL steps at a time, as in walk_3d_range_wave: offsets and lengths, then
+    // the loads, then the FMAs in step order
+    int it = 0;
+    for (; it + WALK2_UNROLL <= n_wave; it += WALK2_UNROLL) {
+        unsigned o[WALK2_UNROLL];
+        float dt[WALK2_UNROLL], v[WALK2_UNROLL];
+#pragma unroll
+        for (int u = 0; u < WALK2_UNROLL; ++u) {
+            const bool cx = tx <= ty;
+            const float tm = fminf(fminf(tx, ty), t1);
+            o[u] = min((unsigned)off, last);
+            dt[u] = tm - t;
+            t = tm;
+            off += cx ? dox : doy;
+            mx += cx ? 1.0f : 0.0f;
+            my += cx ? 0.0f : 1.0f;
+            tx = fmaf(mx, ax, tx0);
+            ty = fmaf(my, ay, ty0);
+        }
+#pragma unroll
+        for (int u = 0; u < WALK2_UNROLL; ++u) v[u] = load(o[u]);
+#pragma unroll
+        for (int u = 0; u < WALK2_UNROLL; ++u) acc = fmaf(dt[u], v[u], acc);
+    }
+    for (; it < n_wave; ++it) {
         const bool cx = tx <= ty;
         const float tm = fminf(fminf(tx, ty), t1);
         acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
@@ -430,7 +458,35 @@ __device__ __forceinline__ float walk_3d_range_wave(const Ray& R, const int (&nb
     const unsigned last = (unsigned)((nb[2] - 1) * sz + (nb[1] - 1) * sy + nb[0] - 1);
     int off = iz * sz + iy * sy + ix;
     float t = t0, acc = 0.0f;
-    for (int it = 0; it < n_wave; ++it) {
+    // WALK_UNROLL steps at a time: their voxel offsets and lengths first (the stepping
+    // never depends on loaded values), then the gathers back to back, then the FMAs in
+    // step order (the same sum as one step at a time).
+    int it = 0;
+    for (; it + WALK_UNROLL <= n_wave; it += WALK_UNROLL) {
+        unsigned o[WALK_UNROLL];
+        float dt[WALK_UNROLL], v[WALK_UNROLL];
+#pragma unroll
+        for (int u = 0; u < WALK_UNROLL; ++u) {
+            const bool cx = (tx <= ty) && (tx <= tz);
+            const bool cy = !cx && (ty <= tz);
+            const float tm = fminf(fminf(fminf(tx, ty), tz), t1);
+            o[u] = min((unsigned)off, last);
+            dt[u] = tm - t;
+            t = tm;
+            off += cx ? dox : (cy ? doy : doz);
+            mx += cx ? 1.0f : 0.0f;
+            my += cy ? 1.0f : 0.0f;
+            mz += (cx || cy) ? 0.0f : 1.0f;
+            tx = fmaf(mx, ax, tx0);
+            ty = fmaf(my, ay, ty0);
+            tz = fmaf(mz, az, tz0);
+        }
+#pragma unroll
+        for (int u = 0; u < WALK_UNROLL; ++u) v[u] = load(o[u]);
+#pragma unroll
+        for (int u = 0; u < WALK_UNROLL; ++u) acc = fmaf(dt[u], v[u], acc);
+    }
+    for (; it < n_wave; ++it) {
         const bool cx = (tx <= ty) && (tx <= tz);
         const bool cy = !cx && (ty <= tz);
         const float tm = fminf(fminf(fminf(tx, ty), tz), t1);
