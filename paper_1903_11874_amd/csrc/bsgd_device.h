@@ -306,17 +306,29 @@ __device__ __forceinline__ float walk_2d_range(const Ray& R, const int (&nb)[3],
     int off = iy * sy + ix;
     float t = t0, acc = 0.0f;
     const int max_steps = nb[0] + nb[1] + 2;
-    for (int it = 0; it < max_steps; ++it) {
-        const bool cx = tx <= ty;
-        const float tm = fminf(fminf(tx, ty), t1);
-        acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
-        if (tm >= t1) break;
-        t = tm;
-        off += cx ? dox : doy;
-        mx += cx ? 1.0f : 0.0f;
-        my += cx ? 0.0f : 1.0f;
-        tx = fmaf(mx, ax, tx0);
-        ty = fmaf(my, ay, ty0);
+    // WALK2_UNROLL steps per round, loads issued together; steps past the exit have
+    // zero length (t stays at t1) and clamped offsets, so they add exact zeros
+    for (int it = 0; it < max_steps; it += WALK2_UNROLL) {
+        unsigned o[WALK2_UNROLL];
+        float dt[WALK2_UNROLL], v[WALK2_UNROLL];
+#pragma unroll
+        for (int u = 0; u < WALK2_UNROLL; ++u) {
+            const bool cx = tx <= ty;
+            const float tm = fminf(fminf(tx, ty), t1);
+            o[u] = min((unsigned)off, last);
+            dt[u] = tm - t;
+            t = tm;
+            off += cx ? dox : doy;
+            mx += cx ? 1.0f : 0.0f;
+            my += cx ? 0.0f : 1.0f;
+            tx = fmaf(mx, ax, tx0);
+            ty = fmaf(my, ay, ty0);
+        }
+#pragma unroll
+        for (int u = 0; u < WALK2_UNROLL; ++u) v[u] = load(o[u]);
+#pragma unroll
+        for (int u = 0; u < WALK2_UNROLL; ++u) acc = fmaf(dt[u], v[u], acc);
+        if (t >= t1) break;
     }
     return acc;
 }
