@@ -529,9 +529,32 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
     const int rs = B.nbx + (DIM == 2 ? 1 : 0);
     const int plane = rs * B.nby;
     const int nvox_b = B.nbx * B.nby * B.nbz;
-    for (int i = threadIdx.x; i < nvox_b; i += TPB) {
-        const int ix = i % B.nbx, iy = (i / B.nbx) % B.nby, iz = i / (B.nbx * B.nby);
-        xs[iz * plane + iy * rs + ix] = x[((int64_t)(B.z0 + iz) * G.ny + (B.y0 + iy)) * (int64_t)G.nx + (B.x0 + ix)];
+    if (B.nbx <= TPB) {
+        // row by row: each thread keeps one column and steps over rows (one division
+        // per thread instead of three per element)
+        const int rpp = TPB / B.nbx;  // rows per pass
+        const int col = (int)threadIdx.x % B.nbx, r0 = (int)threadIdx.x / B.nbx;
+        const int rows = B.nby * B.nbz;
+        if (r0 < rpp) {
+            int iy = r0 % B.nby, iz = r0 / B.nby;
+            const int dy = rpp % B.nby, dz = rpp / B.nby;
+            for (int r = r0; r < rows; r += rpp) {
+                xs[iz * plane + iy * rs + col] =
+                    x[((int64_t)(B.z0 + iz) * G.ny + (B.y0 + iy)) * (int64_t)G.nx + (B.x0 + col)];
+                iy += dy;
+                iz += dz;
+                if (iy >= B.nby) {
+                    iy -= B.nby;
+                    ++iz;
+                }
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < nvox_b; i += TPB) {
+            const int ix = i % B.nbx, iy = (i / B.nbx) % B.nby, iz = i / (B.nbx * B.nby);
+            xs[iz * plane + iy * rs + ix] =
+                x[((int64_t)(B.z0 + iz) * G.ny + (B.y0 + iy)) * (int64_t)G.nx + (B.x0 + ix)];
+        }
     }
     // the walk may step one pixel past an x face with a length of a few ulps; that
     // read lands in the padding column, which must hold a finite value
