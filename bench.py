@@ -291,7 +291,7 @@ def main():
                     help="epochs of the event-timed second region (0 = same as --steps)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the hot path has no multi-GPU mode)", file=sys.stderr)
         sys.exit(2)
 
