@@ -588,8 +588,16 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
             const int item = rd * TPB + (int)threadIdx.x;
             const bool on = item < n_items;
             const int ray = on ? (item >> lg) : 0, seg = item & (S - 1);
-            int q = 0;
-            while (q < nch - 1 && sh.off[q + 1] <= ray) ++q;
+            // the pair holding this ray: the largest q with off[q] <= ray (empty pairs,
+            // whose offsets repeat, are passed over), by bisection over the chunk
+            int q = 0, qhi = nch - 1;
+            while (q < qhi) {
+                const int mid = (q + qhi + 1) >> 1;
+                if (sh.off[mid] <= ray)
+                    q = mid;
+                else
+                    qhi = mid - 1;
+            }
             const PairWork& W = sh.pw[q];
             const int k = W.k0 + (ray - sh.off[q]);
             Ray R;
