@@ -255,12 +255,19 @@ class AutoMu:
       ||r||^k < ||r||^{k-M} < ||r||^{k-2M}                   -> mu *= 1 + eps
       ||r||^k > ||r||^{k-M} > ||r||^{k-2M} and
         (|theta^k - theta^{k-M}| > t1 or theta^k < t2)        -> mu *= 1 - delta
-    The paper gives delta = 0.4 (Sec. III-C); eps, t1, t2 are not given (readings)."""
+    The paper gives delta = 0.4 (Sec. III-C); eps, t1, t2 are not given (readings).
+    The residual norms and cosines of every check are recorded beside the step lengths.
+
+    Parity pin: gradient descent on a diagonal two-pixel system, where residuals,
+    EUDs and cosines have closed forms (a hand derivation in the tests), fixes the
+    norms, the cosines, each decision and the EUD reset after every check."""
     eps: float = 0.05
     delta: float = 0.4
     t1: float = 0.1
     t2: float = 0.5
     mu_history: list = field(default_factory=list)
+    r_history: list = field(default_factory=list)
+    theta_history: list = field(default_factory=list)
 
 
 def run(p: Problem, y: np.ndarray, mu: float, rows_per_iter: int, blocks_per_iter: int,
@@ -288,6 +295,8 @@ def run(p: Problem, y: np.ndarray, mu: float, rows_per_iter: int, blocks_per_ite
                     if r0 > r1 > r2 and (abs(th - th_prev) > auto_mu.t1 or th < auto_mu.t2):
                         mu = (1.0 - auto_mu.delta) * mu
                 auto_mu.mu_history.append(mu)
+                auto_mu.r_history = list(r_hist)
+                auto_mu.theta_history = list(theta_hist)
                 prev_eud = eud
                 eud = np.zeros(p.A.shape[1])
         if callback is not None:

@@ -225,3 +225,100 @@ def test_subdetector_memory_removes_the_importance_sampling_bias():
         callback=lambda st: mem.append(ds(st.x, x_lsq)) if st.k % 1000 == 0 else None)
     assert lit[5] > 0.9 * lit[4]                     # the literal form has stalled
     assert mem[5] < 0.6 * mem[4] and mem[5] < 0.1 * lit[5]
+
+
+# ---------------------------------------------------------------- Algorithm 3 by hand
+#
+# Gradient descent (every row and column block selected) on A = diag(1, 2), y = (1, 1),
+# x0 = 0. With D = A A^T = diag(1, 4) the residual obeys r_{k+1} = (I - 2 mu D) r_k, so
+# with a = 1 - 2 mu, b = 1 - 8 mu:  r_k = (a^k, b^k)  and  g_k = 2 A^T r_k = (2 a^k, 4 b^k).
+# The check after iteration k (1-based count k a multiple of M) sees the residual of the
+# last iteration, r_{k-1}, and the EUD = g_{k-M} + ... + g_{k-1}; theta is the cosine of
+# two consecutive EUDs. These closed forms are derived here, not taken from the oracle.
+
+def _diag_problem(M):
+    """Two pixels, two rays (one per view when M = 2, both in one view when M = 1)."""
+    import scipy.sparse as sparse
+    if M == 2:
+        g = GeometrySpec(kind="parallel2d", nx=2, ny=1, nz=1, vx=1.0, vy=1.0, vz=1.0, n_views=2,
+                         angle_span=math.pi, nu=1, nv=1, du=1.0, dv=1.0, n_row_blocks=2, partition_seed=0)
+    else:
+        g = GeometrySpec(kind="parallel2d", nx=2, ny=1, nz=1, vx=1.0, vy=1.0, vz=1.0, n_views=1,
+                         angle_span=math.pi, nu=2, nv=1, du=1.0, dv=1.0, n_row_blocks=1, partition_seed=0)
+    return Problem.build(g, sparse.csr_matrix(np.diag([1.0, 2.0])))
+
+
+def _cos(u, v):
+    return float(np.dot(u, v) / (np.linalg.norm(u) * np.linalg.norm(v)))
+
+
+def test_auto_mu_by_hand_growth_and_eud_reset():
+    """M = 2, mu = 1/16 (a = 7/8, b = 1/2): residual norms fall at every check, so the
+    third check (three norms, two cosines) grows mu by 1 + eps, and so does the
+    fourth, whose EUD holds only the two iterations run with the grown step."""
+    from oracle.bsgd import AutoMu
+    p = _diag_problem(2)
+    y = np.array([1.0, 1.0])
+    mu = 1.0 / 16
+    a, b = 7.0 / 8, 1.0 / 2
+    am = AutoMu(eps=0.05)
+    st = run(p, y, mu, 2, 1, 8, seed=1, auto_mu=am)
+    # checks after 2, 4, 6 iterations: r_1, r_3, r_5 and EUDs g0+g1, g2+g3, g4+g5
+    E = [np.array([2 * a ** (2 * j) * (1 + a), 4 * b ** (2 * j) * (1 + b)]) for j in range(3)]
+    r = [math.hypot(a ** (2 * j + 1), b ** (2 * j + 1)) for j in range(3)]
+    mu1 = mu * 1.05
+    a1, b1 = 1 - 2 * mu1, 1 - 8 * mu1
+    # iterations 6, 7 run with mu1 from r_6 = (a^6, b^6): r_7 = (a1 a^6, b1 b^6), EUD g6 + g7
+    r7 = math.hypot(a1 * a ** 6, b1 * b ** 6)
+    E4 = np.array([2 * a ** 6 * (1 + a1), 4 * b ** 6 * (1 + b1)])
+    assert np.allclose(am.r_history, r + [r7], rtol=1e-13)
+    assert np.allclose(am.theta_history, [_cos(E[1], E[0]), _cos(E[2], E[1]), _cos(E4, E[2])], rtol=1e-13)
+    assert am.mu_history == [mu, mu, mu1, mu1 * 1.05]
+    # and the iterate: x = A^{-1} (y - r_8), r_8 = (a1^2 a^6, b1^2 b^6) ... with mu2 unused yet
+    r8 = np.array([a1 ** 2 * a ** 6, b1 ** 2 * b ** 6])
+    assert np.allclose(st.x, (y - r8) / np.array([1.0, 2.0]), rtol=1e-13)
+
+
+def test_auto_mu_by_hand_shrink_on_rising_norms():
+    """M = 2, mu = 5/16 (a = 3/8, b = -3/2): norms rise, the EUD turns (|theta_3 -
+    theta_2| > t1), so the third check cuts mu by 1 - delta; with the cut step the
+    next norm falls and mu stays."""
+    from oracle.bsgd import AutoMu
+    p = _diag_problem(2)
+    y = np.array([1.0, 1.0])
+    mu = 5.0 / 16
+    a, b = 3.0 / 8, -3.0 / 2
+    am = AutoMu(delta=0.4, t1=0.1, t2=0.5)
+    run(p, y, mu, 2, 1, 8, seed=1, auto_mu=am)
+    E = [np.array([2 * a ** (2 * j) * (1 + a), 4 * b ** (2 * j) * (1 + b)]) for j in range(3)]
+    th2, th3 = _cos(E[1], E[0]), _cos(E[2], E[1])
+    assert abs(th3 - th2) > 0.1 and th3 > 0.5          # the first criterion decides
+    mu1 = 0.6 * mu
+    a1, b1 = 1 - 2 * mu1, 1 - 8 * mu1
+    r = [math.hypot(a ** (2 * j + 1), b ** (2 * j + 1)) for j in range(3)] + \
+        [math.hypot(a1 * a ** 6, b1 * b ** 6)]
+    assert r[0] < r[1] < r[2] and r[3] < r[2]
+    assert np.allclose(am.r_history, r, rtol=1e-13)
+    assert np.allclose(am.theta_history[:2], [th2, th3], rtol=1e-13)
+    assert am.mu_history == [mu, mu, mu1, mu1]
+
+
+@pytest.mark.parametrize("t2,cut", [(0.5, True), (-1.0, False)])
+def test_auto_mu_by_hand_alternating_direction(t2, cut):
+    """M = 1 (a check after every iteration, EUD = the last g), mu = 5/16: g alternates
+    its sign, theta stays near -1 (|theta_2 - theta_1| = 0.156 < t1 = 0.2), so only the
+    second criterion theta < t2 can cut the step."""
+    from oracle.bsgd import AutoMu
+    p = _diag_problem(1)
+    y = np.array([1.0, 1.0])
+    mu = 5.0 / 16
+    a, b = 3.0 / 8, -3.0 / 2
+    am = AutoMu(delta=0.4, t1=0.2, t2=t2)
+    run(p, y, mu, 1, 1, 3, seed=1, auto_mu=am)
+    g = [np.array([2 * a ** k, 4 * b ** k]) for k in range(3)]
+    th = [_cos(g[1], g[0]), _cos(g[2], g[1])]
+    assert th[0] == pytest.approx(-22.5 / math.sqrt(20.0 * 36.5625), rel=1e-13)
+    assert abs(th[1] - th[0]) < 0.2 and th[1] < 0.5
+    assert np.allclose(am.r_history, [math.hypot(a ** k, b ** k) for k in range(3)], rtol=1e-13)
+    assert np.allclose(am.theta_history, th, rtol=1e-13)
+    assert am.mu_history == [mu, mu, 0.6 * mu if cut else mu]
