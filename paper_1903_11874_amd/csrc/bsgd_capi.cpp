@@ -813,6 +813,8 @@ struct bsgd_solver {
     // entry table of batched calls led by this solver
     // step length on the device (read by the back-projection kernel) and Algorithm 3
     DevBuf mu_dev, eud_cur, eud_prev;
+    DevBuf tv_w;             // {w = mu lambda, dual step} of the TV prox, on the device
+    float* tv_w_host = nullptr;
     DevBuf nr_ty, nr_tg;   // normal-residual scratch (bsgd_normal_residual)
     double nr_ref = -1.0;  // ||A^T y||, once computed
     float* mu_host = nullptr;
@@ -842,6 +844,7 @@ struct bsgd_solver {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         if (norm_host) (void)hipHostFree(norm_host);
         if (mu_host) (void)hipHostFree(mu_host);
+        if (tv_w_host) (void)hipHostFree(tv_w_host);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -981,6 +984,11 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
         S_TRY(s->tv_p.alloc(nb + (size_t)g->n_vox * sizeof(float)));  // dual p and primal u
         S_TRY(s->tv_a.alloc(nb));
         S_TRY(s->tv_b.alloc(nb));
+        S_TRY(s->tv_w.alloc(2 * sizeof(float)));
+        S_TRY(hipHostMalloc((void**)&s->tv_w_host, 2 * sizeof(float), hipHostMallocDefault));
+        tv_weight_step(g->dim, o->mu, o->tv_lambda, s->tv_w_host);
+        S_TRY(hipMemcpyAsync(s->tv_w.p, s->tv_w_host, 2 * sizeof(float), hipMemcpyHostToDevice, st));
+        S_TRY(hipStreamSynchronize(st));
     }
     S_TRY(launch_fill(s->z.as<float>(), 0.0f, g->z_floats, st));
     if (s->subdet)
@@ -1086,11 +1094,12 @@ static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32
             e = launch_add(s->eud_cur.as<float>(), s->gsum.as<float>(), g->n_vox, st);
             if (e != hipSuccess) return e;
         }
-        if (s->o.tv_lambda > 0 && (k_first + it + 1) % s->tv_every == 0) {
-            const float w = (float)(s->mu_cur * s->o.tv_lambda);
+        // the prox reads its weight mu lambda from the device (Algorithm 3 may change mu
+        // between replays of a captured epoch); a non-positive weight is the identity
+        if (s->o.tv_lambda > 0 && (s->auto_mu || s->mu_cur > 0) && (k_first + it + 1) % s->tv_every == 0) {
             e = timed(s, KID_TV, [&] {
-                return launch_tv_prox(g->dg, s->x, w, s->o.tv_inner_iters, s->tv_p.as<float>(), s->tv_a.as<float>(),
-                                      s->tv_b.as<float>(), st);
+                return launch_tv_prox(g->dg, s->x, s->tv_w.as<float>(), s->o.tv_inner_iters, s->tv_p.as<float>(),
+                                      s->tv_a.as<float>(), s->tv_b.as<float>(), st);
             });
             if (e != hipSuccess) return e;
         }
@@ -1194,6 +1203,10 @@ static bsgd_status auto_mu_check(bsgd_solver* s)
             s->mu_cur = mu;
             *s->mu_host = (float)mu;
             HIP_TRY(hipMemcpyAsync(s->mu_dev.p, s->mu_host, sizeof(float), hipMemcpyHostToDevice, s->st));
+            if (s->tv_w_host) {
+                tv_weight_step(g->dim, mu, s->o.tv_lambda, s->tv_w_host);
+                HIP_TRY(hipMemcpyAsync(s->tv_w.p, s->tv_w_host, 2 * sizeof(float), hipMemcpyHostToDevice, s->st));
+            }
             HIP_TRY(hipStreamSynchronize(s->st));
         }
     }
@@ -1364,10 +1377,9 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         }
         for (int i = 0; i < n; ++i) {
             bsgd_solver* s = solvers[i];
-            if (s->o.tv_lambda > 0 && (s->k + it + 1) % s->tv_every == 0) {
-                hipError_t he = launch_tv_prox(s->g->dg, s->x, (float)(s->mu_cur * s->o.tv_lambda),
-                                               s->o.tv_inner_iters, s->tv_p.as<float>(), s->tv_a.as<float>(),
-                                               s->tv_b.as<float>(), st);
+            if (s->o.tv_lambda > 0 && s->mu_cur > 0 && (s->k + it + 1) % s->tv_every == 0) {
+                hipError_t he = launch_tv_prox(s->g->dg, s->x, s->tv_w.as<float>(), s->o.tv_inner_iters,
+                                               s->tv_p.as<float>(), s->tv_a.as<float>(), s->tv_b.as<float>(), st);
                 if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "tv: %s", hipGetErrorString(he)));
             }
         }

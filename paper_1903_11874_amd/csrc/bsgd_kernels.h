@@ -133,9 +133,13 @@ hipError_t launch_add(float* a, const float* b, int64_t n, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partials, int* n_partials, hipStream_t st);
 
 // TV proximal step of BSGD-TV on x (in place): iters fast-gradient-projection steps.
-// p: device [dim + 1][n_vox] scratch (the dual iterate, then the primal point u);
-// ra, rb: device [dim][n_vox] scratch.
-hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float* p, float* ra, float* rb,
-                          hipStream_t st);
+// wstep: device {w, step} (prox weight w = mu lambda and the dual step 1/(4 dim w),
+// written by tv_weight_step), read by the kernels at run time so that captured graphs
+// see step-length changes. p: device [dim + 1][n_vox] scratch (the dual iterate, then
+// the primal point u); ra, rb: device [dim][n_vox] scratch.
+hipError_t launch_tv_prox(const DevGeom& G, float* x, const float* wstep, int iters, float* p, float* ra,
+                          float* rb, hipStream_t st);
+// Host values of {w, step} for step length mu and TV weight lambda.
+void tv_weight_step(int dim, double mu, double lambda, float* out);
 
 }  // namespace bsgd

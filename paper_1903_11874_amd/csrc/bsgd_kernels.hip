@@ -1325,13 +1325,17 @@ __device__ __forceinline__ float div_adj(const float* __restrict__ q, int64_t nv
 
 // FGP step, first half: the primal point of the current dual iterate,
 // u = b - w D^T r (one thread per voxel).
+// The prox weight w and the dual step are read from the device ({w, step}), so a
+// captured graph follows step-length changes made between its replays.
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_fgp_u(const float* __restrict__ b, const float* __restrict__ rin,
-                                              float* __restrict__ u, int nx, int ny, int nz, float w)
+                                              float* __restrict__ u, int nx, int ny, int nz,
+                                              const float* __restrict__ wstep)
 {
     const int64_t nvox = (int64_t)nx * ny * nz;
     const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (o >= nvox) return;
+    const float w = wstep[0];
     const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
     u[o] = b[o] - w * div_adj<DIM>(rin, nvox, X, Y, Z, nx, ny, nz);
 }
@@ -1341,11 +1345,12 @@ __global__ __launch_bounds__(WG) void k_fgp_u(const float* __restrict__ b, const
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_fgp_dual(const float* __restrict__ u, const float* __restrict__ rin,
                                                  float* __restrict__ rout, float* __restrict__ p, int nx, int ny,
-                                                 int nz, float step, float coef)
+                                                 int nz, const float* __restrict__ wstep, float coef)
 {
     const int64_t nvox = (int64_t)nx * ny * nz;
     const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (o >= nvox) return;
+    const float step = wstep[1];
     const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
     const float uc = u[o];
     float g[3] = {0.0f, 0.0f, 0.0f};
@@ -1371,11 +1376,12 @@ __global__ __launch_bounds__(WG) void k_fgp_dual(const float* __restrict__ u, co
 
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_fgp_final(float* __restrict__ x, const float* __restrict__ p, int nx, int ny,
-                                                  int nz, float w)
+                                                  int nz, const float* __restrict__ wstep)
 {
     const int64_t nvox = (int64_t)nx * ny * nz;
     const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (o >= nvox) return;
+    const float w = wstep[0];
     const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
     x[o] = x[o] - w * div_adj<DIM>(p, nvox, X, Y, Z, nx, ny, nz);
 }
@@ -1653,17 +1659,23 @@ hipError_t launch_fill(float* a, float v, int64_t n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float* p, float* ra, float* rb,
+void tv_weight_step(int dim, double mu, double lambda, float* out)
+{
+    const float w = (float)(mu * lambda);
+    out[0] = w;
+    out[1] = w > 0.0f ? (float)(1.0 / (4.0 * dim * (double)w)) : 0.0f;
+}
+
+hipError_t launch_tv_prox(const DevGeom& G, float* x, const float* wstep, int iters, float* p, float* ra, float* rb,
                           hipStream_t st)
 {
-    if (w <= 0.0f || iters <= 0) return hipSuccess;
+    if (iters <= 0) return hipSuccess;
     const int64_t nvox = (int64_t)G.nx * G.ny * G.nz;
     const int dim = G.dim;
     hipError_t e = launch_fill(p, 0.0f, dim * nvox, st);
     if (e != hipSuccess) return e;
     e = launch_fill(ra, 0.0f, dim * nvox, st);
     if (e != hipSuccess) return e;
-    const float step = (float)(1.0 / (4.0 * dim * (double)w));
     double tk = 1.0;
     float* rin = ra;
     float* rout = rb;
@@ -1672,13 +1684,13 @@ hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float*
         const double tn = (1.0 + sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
         const float coef = (float)((tk - 1.0) / tn);
         if (dim == 3) {
-            hipLaunchKernelGGL(k_fgp_u<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, w);
+            hipLaunchKernelGGL(k_fgp_u<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, wstep);
             hipLaunchKernelGGL(k_fgp_dual<3>, dim3(grid1(nvox)), dim3(WG), 0, st, u, rin, rout, p, G.nx, G.ny, G.nz,
-                               step, coef);
+                               wstep, coef);
         } else {
-            hipLaunchKernelGGL(k_fgp_u<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, w);
+            hipLaunchKernelGGL(k_fgp_u<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, wstep);
             hipLaunchKernelGGL(k_fgp_dual<2>, dim3(grid1(nvox)), dim3(WG), 0, st, u, rin, rout, p, G.nx, G.ny, G.nz,
-                               step, coef);
+                               wstep, coef);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1688,9 +1700,9 @@ hipError_t launch_tv_prox(const DevGeom& G, float* x, float w, int iters, float*
         rout = t;
     }
     if (dim == 3)
-        hipLaunchKernelGGL(k_fgp_final<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, w);
+        hipLaunchKernelGGL(k_fgp_final<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, wstep);
     else
-        hipLaunchKernelGGL(k_fgp_final<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, w);
+        hipLaunchKernelGGL(k_fgp_final<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, wstep);
     return hipGetLastError();
 }
 

@@ -61,3 +61,16 @@ def test_served_results_equal_solo_results():
     assert max(e[1] for e in server.log) > 1  # requests overlapped on the device
     st = latency_stats(served)
     assert st["solves"] == 14 and st["p99_s"] >= st["p50_s"] > 0
+    # each served result against the oracle's run of the same request
+    from oracle.bsgd import Problem, run
+    from oracle.system import matrix
+    problems = {}
+    for req, res in zip(sorted(reqs, key=lambda r: r.rid), served):
+        g = req.geometry
+        if g not in problems:
+            problems[g] = Problem.build(g, matrix(g))
+        p = problems[g]
+        R, B = 1, p.N  # node count 16 = N: one row block and every column block per iteration
+        st = run(p, req.y.double().cpu().numpy(), req.mu, R, B, res.iterations, req.seed)
+        x = res.x.double().cpu().numpy()
+        assert np.linalg.norm(x - st.x) <= 1e-5 * np.linalg.norm(st.x), res.rid

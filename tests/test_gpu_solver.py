@@ -313,6 +313,17 @@ def test_batched_solves_equal_solo_solves():
     for i, r in enumerate(runs):
         assert torch.equal(r[0][0], r[1][0]), i
         assert r[0][1].iterations == r[1][1].iterations
+    # and every batched solve against the oracle's run of the same request (the
+    # importance-sampled one with the library's exported sampling table)
+    for (g, R, B, tv, seed), r in zip(specs, runs):
+        base = g.with_(im_mode="none")
+        A, x_true, y64, y32 = _data(base, seed)
+        geom = geoms[(g.kind, g.im_mode)]
+        q = None
+        if g.im_mode != "none":
+            q = geom.table("im_table").reshape(g.n_views, g.su * g.sv, g.n_blocks)
+        st = run(oracle_problem(base), y64, _mu(A, 0.3), R, B, r[0][1].iterations, seed, q=q, tv_lambda=tv)
+        assert rel_l2(r[0][0].double().cpu().numpy(), st.x) <= TOL, (g.kind, R, B)
 
 
 def test_autotuner_shapes_do_not_change_results():
@@ -393,3 +404,36 @@ def test_normal_residual_matches_oracle(name):
         ref = np.linalg.norm(A.T @ (y64 - A @ x64))
         assert abs(a - ref) <= 1e-4 * ref
         assert abs(r - ref / ref_y) <= 1e-4 * ref / ref_y
+
+
+@pytest.mark.parametrize("scale", [2.0, 0.05])
+def test_auto_step_length_with_tv_on_replayed_graphs(scale):
+    """Algorithm 3 with the TV prox of Algorithm 4 on captured, replayed epochs (T = M,
+    so every epoch ends with a prox and a step-length check): the prox weight mu lambda
+    must follow the step-length changes between replays. Same decisions and iterate as
+    the oracle; lambda is set so the prox weight matters (mu0 lambda = 0.05)."""
+    import torch
+    from oracle.bsgd import AutoMu
+    from paper_1903_11874_amd import Geometry, Solver
+    dev = require_gpu()
+    g = SMALL["fan"]
+    log(f"auto mu + TV on graphs, scale={scale}")
+    p = oracle_problem(g)
+    A, x_true, y64, y32 = _data(g)
+    mu = _mu(A, scale)
+    lam = 0.05 / mu
+    R, B = 1, 9
+    assert tv_period(g.n_row_blocks, g.n_blocks, R, B) == g.n_row_blocks
+    n = 12 * g.n_row_blocks
+    am = AutoMu()
+    st = run(p, y64, mu, R, B, n, 23, auto_mu=am, tv_lambda=lam)
+    geom = Geometry(g)
+    yd = torch.tensor(y32, device=dev)
+    xd = torch.zeros(A.shape[1], device=dev)
+    s = Solver(geom, yd, xd, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=23, auto_mu=True, tv_lambda=lam,
+               tv_inner_iters=20)
+    s.step(n)
+    mu_now, hist = s.step_length()
+    assert np.allclose(hist, am.mu_history, rtol=1e-12)
+    assert len(set(hist)) > 1  # the step length changed between replays
+    assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
