@@ -252,6 +252,22 @@ bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, int32_t n_it
 bsgd_status bsgd_normal_residual(bsgd_solver* const* solvers, int32_t n, int32_t relative, double* out,
                                  void* stream);
 
+/* Allocation-free form of bsgd_normal_residual (relative = 0) for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc. *out = ||A^T (y - A x)|| for the geometry's whole
+ * system, y device [n_views][nv][nu], x device [nz][ny][nx] (caller owned, read only),
+ * out host. The same kernels as bsgd_normal_residual, so the same value bit for bit.
+ * Scratch (the residual, its back projection, reduction partials) lives in one static
+ * device array of bsgd_noalloc_scratch_bytes() bytes (64 MiB) per GPU, held until the
+ * process ends; a geometry needing more (about 4 (n_rays + n_voxels) bytes + 33 KB)
+ * returns BSGD_E_INVALID_ARG before any device work. No hipMalloc, hipFree or other
+ * allocation. Calls on one GPU share that array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ * Synchronises `stream` once. */
+bsgd_status bsgd_normal_residual_noalloc(const bsgd_geometry* geom, const float* y, const float* x, double* out,
+                                         void* stream);
+size_t bsgd_noalloc_scratch_bytes(void);
+
 /* Current step length and its value after each Algorithm 3 check (history[0..cap)). */
 bsgd_status bsgd_solver_step_length(const bsgd_solver* s, double* mu_now, double* history, int32_t cap,
                                     int32_t* n_history);

@@ -77,6 +77,7 @@ EXPORTED = (
     "bsgd_solver_last_schedule", "bsgd_solver_state", "bsgd_solver_set_profiling", "bsgd_solver_kernel_times",
     "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error", "bsgd_step_batch", "bsgd_geometry_set_tuning",
     "bsgd_geometry_get_tuning", "bsgd_solver_step_length", "bsgd_normal_residual",
+    "bsgd_normal_residual_noalloc", "bsgd_noalloc_scratch_bytes",
 )
 
 _lib = None
@@ -115,6 +116,8 @@ def load_library(path: str = LIB_PATH):
         "bsgd_geometry_get_tuning": (i32, [P, ctypes.POINTER(Tuning)]),
         "bsgd_solver_step_length": (i32, [P, ctypes.POINTER(ctypes.c_double), P, i32, ctypes.POINTER(i32)]),
         "bsgd_normal_residual": (i32, [ctypes.POINTER(P), i32, i32, P, P]),
+        "bsgd_normal_residual_noalloc": (i32, [P, P, P, ctypes.POINTER(ctypes.c_double), P]),
+        "bsgd_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -399,6 +402,19 @@ def normal_residual(solvers, relative: bool = True, stream=None):
     _check(load_library().bsgd_normal_residual(arr, len(solvers), int(bool(relative)),
                                                out.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
     return out
+
+
+def normal_residual_noalloc(geom: Geometry, y, x, stream=None) -> float:
+    """||A^T (y - A x)|| through the allocation-free entry point
+    (bsgd_normal_residual_noalloc: static device scratch, no allocation)."""
+    out = ctypes.c_double()
+    _check(load_library().bsgd_normal_residual_noalloc(geom.handle, _dev_ptr(y), _dev_ptr(x), ctypes.byref(out),
+                                                       _stream_ptr(stream)))
+    return out.value
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load_library().bsgd_noalloc_scratch_bytes())
 
 
 def solve(geom: Geometry, y, x, stream=None, **opts):

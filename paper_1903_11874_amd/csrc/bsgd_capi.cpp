@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1592,4 +1593,80 @@ extern "C" bsgd_status bsgd_solve(const bsgd_geometry* g, const float* y, float*
     }
     delete s;
     return stt;
+}
+
+// ------------------------------------------------------------ allocation-free normal residual
+
+// Scratch of bsgd_normal_residual_noalloc: the residual y - A x, the back projection
+// A^T (y - A x), the reduction partials and the final sum, in one file-scope device
+// array that every GPU the library runs on holds until the process ends. Host code
+// never uses the array's name as a device address: the address is looked up once
+// per device with hipGetSymbolAddress and kept in scratch_dev.
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_PARTIALS = 4096;  // launch_sumsq never uses more partials
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+static bsgd_status scratch_address(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(BSGD_E_UNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(BSGD_E_DEVICE, "no device address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return BSGD_OK;
+}
+
+static size_t round_up_256(size_t b) { return (b + 255) & ~size_t(255); }
+
+extern "C" size_t bsgd_noalloc_scratch_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+extern "C" bsgd_status bsgd_normal_residual_noalloc(const bsgd_geometry* g, const float* y, const float* x,
+                                                    double* out, void* stream)
+{
+    if (!g || !y || !x || !out) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    const size_t ty_bytes = round_up_256((size_t)g->n_rays * sizeof(float));
+    const size_t tg_bytes = round_up_256((size_t)g->n_vox * sizeof(float));
+    const size_t part_bytes = round_up_256((size_t)NOALLOC_MAX_PARTIALS * sizeof(double));
+    const size_t need = ty_bytes + tg_bytes + part_bytes + 256;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(BSGD_E_INVALID_ARG, "geometry needs %zu bytes of scratch (rays %lld, voxels %lld); the limit is %zu",
+                    need, (long long)g->n_rays, (long long)g->n_vox, NOALLOC_SCRATCH_BYTES);
+    void* base = nullptr;
+    bsgd_status stt = scratch_address(&base);
+    if (stt != BSGD_OK) return stt;
+    unsigned char* b = static_cast<unsigned char*>(base);
+    float* ty = reinterpret_cast<float*>(b);
+    float* tg = reinterpret_cast<float*>(b + ty_bytes);
+    double* part = reinterpret_cast<double*>(b + ty_bytes + tg_bytes);
+    double* dout = reinterpret_cast<double*>(b + ty_bytes + tg_bytes + part_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    // every scratch word read below is first written on this stream: the forward
+    // projection writes every ray, the back projection of all blocks every voxel,
+    // k_sumsq every partial it reports and k_sum_partials the sum
+    const int32_t* views = g->d_all_views.as<int32_t>();
+    HIP_TRY(launch_fp_full(g->dg, views, g->d.n_views, -1, x, ty, 0, st));
+    HIP_TRY(launch_sub(y, ty, ty, g->n_rays, st));
+    HIP_TRY(launch_bp_full(g->dg, views, g->d.n_views, -1, ty, tg, 1.0f, 0, st));
+    int np = 0;
+    HIP_TRY(launch_sumsq(tg, g->n_vox, part, &np, st));
+    if (np > NOALLOC_MAX_PARTIALS) return fail(BSGD_E_DEVICE, "reduction used %d partials", np);
+    HIP_TRY(launch_sum_partials(part, np, dout, st));
+    double v = 0.0;
+    HIP_TRY(hipMemcpyAsync(&v, dout, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = std::sqrt(v);
+    return BSGD_OK;
 }
