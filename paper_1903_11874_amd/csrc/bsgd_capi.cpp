@@ -561,6 +561,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.kspan = g->kspan.empty() ? nullptr : g->d_kspan.as<float>();
     G.cov_off = nullptr;
     G.cov_idx = nullptr;
+    set_bp3_bounds(G, d.sod, d.sdd, d.du, d.dv);
     return upload_cover_index(g, st);
 }
 

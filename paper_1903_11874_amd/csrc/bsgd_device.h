@@ -90,6 +90,11 @@ struct DevGeom {
     // rebuild then tests the footprint rectangles itself).
     const uint32_t* cov_off;   // [n_views * nu * nv + 1]
     const uint32_t* cov_idx;   // [z_floats]
+    // 3D back projection: largest pixel rectangle (columns, rows) a workgroup tile
+    // projects to in one view, the size of its LDS staging per view; 0 = no staging
+    int32_t bp3_kmax, bp3_lmax;
+    int32_t bp3_steep;  // some ray's chord through a voxel column can meet two z planes
+    int32_t pad_;
 };
 
 // Sub-detector s covers u in [k0, k1), v in [l0, l1).

@@ -139,6 +139,10 @@ hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial
 // the primal point u); ra, rb: device [dim][n_vox] scratch.
 hipError_t launch_tv_prox(const DevGeom& G, float* x, const float* wstep, int iters, float* p, float* ra,
                           float* rb, hipStream_t st);
+// Bounds of the pixel rectangle (columns, rows) one 3D back-projection workgroup tile
+// projects to in any view, from the geometry (DevGeom::bp3_kmax, bp3_lmax); 0 when
+// staging in LDS is off (then every view reads global memory).
+void set_bp3_bounds(DevGeom& G, double sod, double sdd, double du, double dv);
 // Host values of {w, step} for step length mu and TV weight lambda.
 void tv_weight_step(int dim, double mu, double lambda, float* out);
 

@@ -131,95 +131,6 @@ __device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t byte_of
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
-// Back projection of one view into one voxel: sum over candidate rays of a_ij r_i.
-// Candidates are the pixels inside the voxel's shadow (corner projections plus a
-// margin), clipped to [k0, k1) x [l0, l1); ray (k, l) reads rview[l * rstride + k].
-template <int DIM, class Anchor>
-__device__ __forceinline__ float bp_voxel_view(const DevGeom& G, int view, float c, float s, const Anchor& P,
-                                               const int (&li)[3], const float (&h)[3], const float (&vs)[3],
-                                               int k0, int k1, int l0, int l1, const float* __restrict__ rview,
-                                               int rstride)
-{
-    const float hvx = 0.5f * vs[0], hvy = 0.5f * vs[1];
-    const float qx = plane_pos(li[0], vs[0], h[0]) + hvx;
-    const float qy = plane_pos(li[1], vs[1], h[1]) + hvy;
-    const float w0 = fmaf(qy, c, -(qx * s));
-    const float d0 = -fmaf(qx, c, qy * s);
-    const float dwx = -hvx * s, dwy = hvy * c;
-    const float ddx = -hvx * c, ddy = -hvy * s;
-    const float ku = 0.5f * (float)(G.nu - 1);
-    const float inv_du = __builtin_amdgcn_rcpf(G.du);
-    const bool par = (G.kind == KIND_PARALLEL_2D);
-    float kmin = INFINITY, kmax = -INFINITY;
-    float rdep[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float sx = (q & 1) ? 1.0f : -1.0f, sy = (q & 2) ? 1.0f : -1.0f;
-        const float w = fmaf(sy, dwy, fmaf(sx, dwx, w0)) + P.cu;
-        float kk;
-        if (par) {
-            kk = fmaf(w, inv_du, ku);
-            rdep[q] = 0.0f;
-        } else {
-            const float dep = fmaf(sy, ddy, fmaf(sx, ddx, d0)) + P.depth;
-            rdep[q] = G.sdd * __builtin_amdgcn_rcpf(dep);
-            kk = fmaf(w * rdep[q], inv_du, ku);
-        }
-        kmin = fminf(kmin, kk);
-        kmax = fmaxf(kmax, kk);
-    }
-    // clamp in the float domain before converting (the range may be empty)
-    const int klo = max(k0, (int)ceilf(fminf(fmaxf(kmin - SHADOW_EPS, (float)k0), (float)k1)));
-    const int khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kmax + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
-    int llo = l0, lhi = l1 - 1;
-    if (DIM == 3) {
-        const float hvz = 0.5f * vs[2];
-        const float qz = plane_pos(li[2], vs[2], h[2]) + hvz;
-        const float lv = 0.5f * (float)(G.nv - 1);
-        const float inv_dv = __builtin_amdgcn_rcpf(G.dv);
-        float lmin = INFINITY, lmax = -INFINITY;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const float zabs = P.cz + qz + (e ? hvz : -hvz);
-                const float ll = fmaf(zabs * rdep[q], inv_dv, lv);
-                lmin = fminf(lmin, ll);
-                lmax = fmaxf(lmax, ll);
-            }
-        }
-        llo = max(l0, (int)ceilf(fminf(fmaxf(lmin - SHADOW_EPS, (float)l0), (float)l1)));
-        lhi = min(l1 - 1, (int)floorf(fmaxf(fminf(lmax + SHADOW_EPS, (float)l1), (float)l0 - 1.0f)));
-    }
-    // The slab test of voxel_dt factorised: the x and y slabs depend on the pixel
-    // column k only, the z slab on the row l only (min and max are exact, so the
-    // lengths are those of make_ray + voxel_dt bit for bit).
-    const float4* rd = G.raydir + (int64_t)view * G.nu;
-    float acc = 0.0f;
-    for (int k = klo; k <= khi; ++k) {
-        const float lu = fmaf((float)(k - P.kc), P.au, P.bu);
-        const float4 T = ld_off(rd, (uint32_t)k * 16u);
-        float te = -INFINITY, tx = INFINITY;
-        bool hit = true;
-        slab_axis(-lu * s, T.x, li[0], vs[0], h[0], te, tx, hit);
-        slab_axis(lu * c, T.y, li[1], vs[1], h[1], te, tx, hit);
-        if (!hit) continue;
-        for (int l = llo; l <= lhi; ++l) {
-            float te3 = te, tx3 = tx, len = T.z;
-            if (DIM == 3) {
-                const float2 V = G.rayv[l];
-                bool hz = true;
-                slab_axis(fmaf((float)(l - P.lc), P.av, P.bv), V.x, li[2], vs[2], h[2], te3, tx3, hz);
-                if (!hz) continue;
-                len = __builtin_amdgcn_sqrtf(T.z + V.y);
-            }
-            const float dt = fmaxf(tx3 - te3, 0.0f);
-            if (dt > 0.0f) acc = fmaf(dt * len, ld_off(rview, ((uint32_t)l * (uint32_t)rstride + (uint32_t)k) * 4u), acc);
-        }
-    }
-    return acc;
-}
-
 // Candidate pixel range [klo, khi] of a 2D voxel centre (qx, qy), block-local, in one
 // view: the pixels within kc -/+ span of the projection of the centre (kspan / depth for
 // a fan, kspan for parallel rays; kspan bounds the chord's support), clipped to [k0, k1).
@@ -824,36 +735,13 @@ __global__ __launch_bounds__(TPB) void k_resid(DevGeom G, const int32_t* __restr
 
 // ------------------------------------------------------------ solver: back projection + step
 
-// 64 voxels per workgroup, each voxel's views interleaved over bp_split(DIM) threads and
-// summed in a fixed order through LDS.
+// 2D: 64 lanes of two x-adjacent voxels per wave, each voxel's views interleaved over
+// bp_split waves and summed in a fixed order through LDS.
 constexpr int BP_VOX = 64;
-// views of a voxel split over this many waves: four in 2D (where each lane carries two
-// voxels), one in 3D. Measured on the 512^2 fan (2D back projection per iteration): one
-// voxel per lane 36.1 / 30.5 / 30.9 us at 1 / 2 / 4 waves; two voxels per lane 29.4 /
-// 24.0 / 24.6 us at 2 / 4 / 8 waves. On the 256^3 cone (3D): 355 / 372 / 402 us at 1 / 2 / 4.
-__host__ __device__ constexpr int bp_split(int dim) { return dim == 3 ? 1 : 4; }
-__host__ __device__ constexpr int bp_wg(int dim) { return BP_VOX * bp_split(dim); }
-
-template <int DIM>
-struct Tile;
-template <>
-struct Tile<3> {
-    static constexpr int X = 4, Y = 4, Z = 4;
-};
-
-template <int DIM>
-__device__ __forceinline__ bool tile_voxel(const BlockInfo& B, int tile, int vl, int (&li)[3], bool& tile_ok)
-{
-    const int tx_n = (B.nbx + Tile<DIM>::X - 1) / Tile<DIM>::X;
-    const int ty_n = (B.nby + Tile<DIM>::Y - 1) / Tile<DIM>::Y;
-    const int tz_n = (B.nbz + Tile<DIM>::Z - 1) / Tile<DIM>::Z;
-    tile_ok = tile < tx_n * ty_n * tz_n;
-    const int t_x = tile % tx_n, t_y = (tile / tx_n) % ty_n, t_z = tile / (tx_n * ty_n);
-    li[0] = t_x * Tile<DIM>::X + vl % Tile<DIM>::X;
-    li[1] = t_y * Tile<DIM>::Y + (vl / Tile<DIM>::X) % Tile<DIM>::Y;
-    li[2] = t_z * Tile<DIM>::Z + vl / (Tile<DIM>::X * Tile<DIM>::Y);
-    return tile_ok && li[0] < B.nbx && li[1] < B.nby && li[2] < B.nbz;
-}
+// views of a voxel split over this many waves (each lane carries two voxels). Measured on
+// the 512^2 fan (2D back projection per iteration): one voxel per lane 36.1 / 30.5 / 30.9 us
+// at 1 / 2 / 4 waves; two voxels per lane 29.4 / 24.0 / 24.6 us at 2 / 4 / 8 waves.
+constexpr int BP_SPLIT_2D = 4;
 
 // For each selected row block i: g_hat^i_new = 2 (A_{rows(i,j)}^{J_j})^T r;
 // g += sum_i (g_hat^i_new - g_hat^i_old); g_hat^i = g_hat^i_new; then x += mu g.
@@ -886,7 +774,7 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
                                                 const float* __restrict__ src, float* __restrict__ ghat,
                                                 float* __restrict__ gsum, float* __restrict__ x,
                                                 const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
-                                                float (&part)[bp_split(2)][2][BP_VOX])
+                                                float (&part)[BP_SPLIT_2D][2][BP_VOX])
 {
     const int b = by;
     const int j = S_[L.off_blocks() + b];
@@ -908,7 +796,7 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
         const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
         float acc_a = 0.0f, acc_b = 0.0f;
         if (a_ok) {
-            for (int a = a0 + grp; a < a1; a += bp_split(2)) {
+            for (int a = a0 + grp; a < a1; a += BP_SPLIT_2D) {
                 const PairWork W = wb[a];
                 if (W.k1 <= W.k0) continue;
                 if (SUB)
@@ -925,7 +813,7 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
         if (grp == 0 && a_ok) {
             float sa = part[0][0][vl], sb = part[0][1][vl];
 #pragma unroll
-            for (int q = 1; q < bp_split(2); ++q) {
+            for (int q = 1; q < BP_SPLIT_2D; ++q) {
                 sa += part[q][0][vl];
                 sb += part[q][1][vl];
             }
@@ -960,66 +848,456 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
     }
 }
 
-template <int DIM, bool SUB>
-__device__ __forceinline__ void bp_step_body(const DevGeom& G, const int32_t* __restrict__ S_,
-                                             const PairWork* __restrict__ work, SchedLayout L,
-                                             const float* __restrict__ src, float* __restrict__ ghat,
-                                             float* __restrict__ gsum, float* __restrict__ x,
-                                             const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
-                                             float (&part)[bp_split(DIM)][1][BP_VOX])
+// ------------------------------------------------------------ 3D back projection: voxel columns
+
+// Each thread owns one voxel column (x, y) of a workgroup tile of BP3_TX x BP3_TY columns
+// and up to BP3_CZ voxels in z. Per view, the rays that can cross the column are the
+// pixels of the column's shadow: detector columns k from the projections of its four
+// xy corners, and per k the rows l from the z range of the column segment the ray's
+// xy line cuts out (the xy slab interval [te, tx], which is shared by every row of
+// that detector column because all rays of one detector column lie in one vertical
+// plane through the source). Each such row crosses one voxel of the column, or two
+// (rarely more): the pieces of [te, tx] between the z planes, with the plane crossings
+// computed by the forward walk's plane formula. The views' residuals, scaled by the
+// ray lengths |d|, are staged in LDS per round of BP3_VC views over the rectangle the
+// workgroup tile projects to; a thread adds its pieces into its own LDS accumulators
+// (one per voxel of its column), so every voxel's sum is gathered by one thread in a
+// fixed order: views ascending, detector columns ascending, rows ascending.
+constexpr int BP3_TX = 16, BP3_TY = 16, BP3_WG = BP3_TX * BP3_TY;
+constexpr int BP3_CZ = 16;
+constexpr int BP3_VC = 5;
+constexpr float BP3_EPS = 1e-3f;       // candidate margin of a column's shadow (pixels)
+constexpr float BP3_RECT_EPS = 4e-3f;  // margin of the staged rectangle (pixels), wider than BP3_EPS
+
+// plane_pos of a plane index held exactly in a float (the same FMA on the same value).
+__device__ __forceinline__ float plane_pos_f(float i, float v, float h) { return fmaf(i, v, -h); }
+
+// One view of a staging round (LDS, written by the first wave).
+struct Bp3View {
+    int k0, k1, l0, l1;  // pixel rectangle of the workgroup tile in this view, inside the pair's range
+    int staged;          // the rectangle's rays are in LDS (else lanes read global memory)
+    int a;               // view slot
+    int pad0, pad1;
+};
+
+// Dynamic LDS layout: accumulators [BP3_CZ + 2][BP3_WG] (voxel iz of a thread's column in
+// row iz + 1; rows 0 and nzc + 1 absorb the pieces of rays above or below the column, so
+// every add is unconditional), then per view of a round the
+// Bp3View, the detector-column records {1/a, 1/b, p_x, p_y} [kmax], the row records
+// {p_z, 1/v} [lmax] and the tile of r |d| [lmax][kmax].
+__host__ __device__ inline size_t bp3_lds_bytes(const DevGeom& G)
 {
-    static_assert(DIM == 3, "2D uses bp_step_body_2d");
+    const size_t km = (size_t)G.bp3_kmax, lm = (size_t)G.bp3_lmax;
+    return (size_t)(BP3_CZ + 2) * BP3_WG * sizeof(float) +
+           (size_t)BP3_VC * (sizeof(Bp3View) + km * sizeof(float4) + lm * sizeof(float2) + km * lm * sizeof(float));
+}
+
+// Workgroup tiles per block for the largest block.
+__host__ __device__ inline int bp3_tiles(const DevGeom& G)
+{
+    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by, mbz = (G.nz + G.bz - 1) / G.bz;
+    return ((mbx + BP3_TX - 1) / BP3_TX) * ((mby + BP3_TY - 1) / BP3_TY) * ((mbz + BP3_CZ - 1) / BP3_CZ);
+}
+
+// Views of a solver iteration: work records of the selected pairs; the source is the
+// selected rows' residuals (slot a at a * per_view), or with the sub-detector memory
+// the residual changes in each pair's z layout.
+struct Bp3StepViews {
+    const PairWork* wb;
+    const float* src;
+    int per_view, nu;
+    bool sub;
+    __device__ __forceinline__ bool get(int a, PairWork& W, const float*& p, int& stride) const
+    {
+        W = wb[a];
+        if (W.k1 <= W.k0 || W.l1 <= W.l0) return false;
+        if (sub) {
+            p = src + W.zbase;
+            stride = W.zw;
+        } else {
+            p = src + (int64_t)a * per_view;
+            stride = nu;
+        }
+        return true;
+    }
+};
+
+// Views of a standalone back projection: a view list, whole footprints of block j.
+struct Bp3FullViews {
+    const PairInfo* pairs;
+    const float2* cs;
+    const int32_t* views;
+    const float* y;
+    int j, n_blocks, per_view, nu;
+    __device__ __forceinline__ bool get(int a, PairWork& W, const float*& p, int& stride) const
+    {
+        const int v = views[a];
+        const PairInfo P = pairs[(int64_t)v * n_blocks + j];
+        if (P.u1 <= P.u0 || P.v1 <= P.v0) return false;
+        const float2 sc = cs[v];
+        W.k0 = P.u0;
+        W.k1 = P.u1;
+        W.l0 = P.v0;
+        W.l1 = P.v1;
+        W.zbase = 0;
+        W.zw = 0;
+        W.view = v;
+        W.au = P.au;
+        W.bu = P.bu;
+        W.av = P.av;
+        W.bv = P.bv;
+        W.kc = P.kc;
+        W.lc = P.lc;
+        W.cu = P.cu;
+        W.depth = P.depth;
+        W.cz = P.cz;
+        W.c = sc.x;
+        W.s = sc.y;
+        W.pad = 0;
+        p = y + (int64_t)a * per_view;
+        stride = nu;
+        return true;
+    }
+};
+
+// Detector-column record of ray column k: reciprocal direction (x, y) and the ray's
+// block-local xy point (as make_ray).
+__device__ __forceinline__ float4 bp3_kcol(const DevGeom& G, const PairWork& W, int k)
+{
+    const float lu = fmaf((float)(k - W.kc), W.au, W.bu);
+    const float4 T = G.raydir[(int64_t)W.view * G.nu + k];
+    return make_float4(T.x, T.y, -lu * W.s, lu * W.c);
+}
+
+// Row record of ray row l: block-local z of its point and reciprocal z direction (a
+// horizontal row's infinite reciprocal replaced by 1e30, so that a cut never computes
+// 0 * inf; its cuts then clamp to the segment's ends).
+__device__ __forceinline__ float2 bp3_row(const DevGeom& G, const PairWork& W, int l)
+{
+    const float iv = G.rayv[l].x;
+    return make_float2(fmaf((float)(l - W.lc), W.av, W.bv), axis_fixed(iv) ? 1e30f : iv);
+}
+
+// r |d| of ray (k, l).
+__device__ __forceinline__ float bp3_rlen(const DevGeom& G, const PairWork& W, const float* p, int stride, int k, int l)
+{
+    const float T2 = G.raydir[(int64_t)W.view * G.nu + k].z;
+    return p[(int64_t)l * stride + k] * __builtin_amdgcn_sqrtf(T2 + G.rayv[l].y);
+}
+
+// The column's contributions from one view: adds sum a_ij r_i of every ray of the view
+// to the thread's accumulators acc[(iz + 1) * BP3_WG] (iz < nzc). STAGED: the rectangle
+// [R.k0, R.k1) x [R.l0, R.l1) is in LDS (kc, rw, tile); else from global memory.
+template <bool STAGED, bool STEEP>
+__device__ __forceinline__ void bp3_column_view(const DevGeom& G, const PairWork& W, const Bp3View& R,
+                                                const float* p, int stride, const float4* kc, const float2* rw,
+                                                const float* tile, int cx, int cy, int zc0, int nzc,
+                                                const float (&h)[3], float* acc)
+{
+    const float vx = G.vx, vy = G.vy, vz = G.vz;
+    const float X0 = plane_pos(cx, vx, h[0]), X1 = plane_pos(cx + 1, vx, h[0]);
+    const float Y0 = plane_pos(cy, vy, h[1]), Y1 = plane_pos(cy + 1, vy, h[1]);
+    // detector columns of the column's shadow: projections of its four xy corners
+    const float c = W.c, s = W.s;
+    const float ku = 0.5f * (float)(G.nu - 1), lv = 0.5f * (float)(G.nv - 1);
+    const float inv_du = __builtin_amdgcn_rcpf(G.du);
+    float kmin = INFINITY, kmax = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float X = (q & 1) ? X1 : X0, Y = (q & 2) ? Y1 : Y0;
+        const float w = fmaf(Y, c, -(X * s)) + W.cu;
+        const float dep = W.depth - fmaf(X, c, Y * s);
+        const float kk = fmaf(G.sdd * w * __builtin_amdgcn_rcpf(dep), inv_du, ku);
+        kmin = fminf(kmin, kk);
+        kmax = fmaxf(kmax, kk);
+    }
+    const int klo = max(R.k0, (int)ceilf(fminf(fmaxf(kmin - BP3_EPS, (float)R.k0), (float)R.k1)));
+    const int khi = min(R.k1 - 1, (int)floorf(fmaxf(fminf(kmax + BP3_EPS, (float)R.k1), (float)R.k0 - 1.0f)));
+    // z planes of the column: block-local and absolute
+    const float zb = plane_pos(zc0, vz, h[2]);
+    const float zt = plane_pos(zc0 + nzc, vz, h[2]);
+    const float zb_abs = zb + W.cz, zt_abs = zt + W.cz;
+    const float A = W.depth * __builtin_amdgcn_rcpf(G.sdd);  // depth of the ray parameter origin / sdd
+    const float inv_vz = __builtin_amdgcn_rcpf(vz);
+    const float dv = G.dv;
+    const int w_tile = R.k1 - R.k0;
+    const int tid = threadIdx.x;
+    const float nzf = (float)nzc, zcf = (float)zc0;
+    for (int k = klo; k <= khi; ++k) {
+        float4 K;
+        if constexpr (STAGED)
+            K = kc[k - R.k0];
+        else
+            K = bp3_kcol(G, W, k);
+        float te = -INFINITY, tx = INFINITY;
+        bool hit = true;
+        slab_axis(K.z, K.x, cx, vx, h[0], te, tx, hit);
+        slab_axis(K.w, K.y, cy, vy, h[1], te, tx, hit);
+        if (!hit || !(te < tx)) continue;
+        // rows whose ray meets the column between te and tx: row of an absolute height Z
+        // at parameter t is lv + Z / ((A + t) dv)
+        const float rfe = __builtin_amdgcn_rcpf((A + te) * dv), rfx = __builtin_amdgcn_rcpf((A + tx) * dv);
+        const float lmin = fminf(zb_abs * rfe, zb_abs * rfx) + lv;
+        const float lmax = fmaxf(zt_abs * rfe, zt_abs * rfx) + lv;
+        const int llo = max(R.l0, (int)ceilf(fminf(fmaxf(lmin - BP3_EPS, (float)R.l0), (float)R.l1)));
+        const int lhi = min(R.l1 - 1, (int)floorf(fmaxf(fminf(lmax + BP3_EPS, (float)R.l1), (float)R.l0 - 1.0f)));
+        // the height of row l's ray at te and tx, in voxels above the column's bottom
+        // plane, is affine in l (used only to pick the voxels; the cut points below
+        // use the exact plane formula and are clamped to [te, tx])
+        const float se = fmaf(te, dv, W.av) * inv_vz, sx = fmaf(tx, dv, W.av) * inv_vz;
+        const float o0 = fmaf(-(float)W.lc, W.av, W.bv) - zb;
+        float ue = fmaf((float)llo, se, fmaf(-te * lv, dv, o0) * inv_vz);
+        float ux = fmaf((float)llo, sx, fmaf(-tx * lv, dv, o0) * inv_vz);
+        const float2* rwp = nullptr;
+        const float* tp = nullptr;
+        if constexpr (STAGED) {
+            rwp = rw + (llo - R.l0);
+            tp = tile + (llo - R.l0) * w_tile + (k - R.k0);
+        }
+        for (int l = llo; l <= lhi; ++l) {
+            float2 Rw;
+            float rl;
+            if constexpr (STAGED) {
+                Rw = *rwp++;
+                rl = *tp;
+                tp += w_tile;
+            } else {
+                Rw = bp3_row(G, W, l);
+                rl = bp3_rlen(G, W, p, stride, k, l);
+            }
+            // voxels (column-local, -1 and nzc = outside) holding the ray at te and tx
+            const float fe = floorf(__builtin_amdgcn_fmed3f(ue, -1.0f, nzf));
+            const float fx = floorf(__builtin_amdgcn_fmed3f(ux, -1.0f, nzf));
+            ue += se;
+            ux += sx;
+            // one cut, at the plane between the two voxels (the upper one's bottom); on
+            // one voxel the whole chord is its own and the second (zero) piece goes to
+            // the spare row 0. Plain LDS read-add-write (each thread owns its
+            // accumulators; LDS atomics serialise lanes): both reads, then the writes in
+            // program order, the two addresses distinct.
+            const bool one = fe == fx;
+            const float zcut = plane_pos_f(zcf + fmaxf(fe, fx), vz, h[2]);
+            const float ts = one ? tx : __builtin_amdgcn_fmed3f((zcut - Rw.x) * Rw.y, te, tx);
+            float* p0 = acc + (int)fmaf(fe, (float)BP3_WG, (float)(BP3_WG + tid));
+            float* p1 = acc + (one ? tid : (int)fmaf(fx, (float)BP3_WG, (float)(BP3_WG + tid)));
+            const float v0 = *p0, v1 = *p1;
+            *p0 = fmaf(ts - te, rl, v0);
+            float tl = ts;
+            if constexpr (STEEP) {
+                const int ie = (int)fe, ix = (int)fx, d = ix - ie;
+                if (d > 1 || d < -1) {
+                    // more than one plane inside [te, tx]: the voxels between (the cut
+                    // above is then the first one, at the plane next to voxel ie)
+                    const int st = d > 0 ? 1 : -1;
+                    tl = __builtin_amdgcn_fmed3f(plane_t(zc0 + ie + (st > 0 ? 1 : 0), vz, h[2], Rw.x, Rw.y), te, tx);
+                    *p0 = fmaf(tl - te, rl, v0);
+                    for (int i = ie + st; i != ix; i += st) {
+                        const float tn =
+                            __builtin_amdgcn_fmed3f(plane_t(zc0 + i + (st > 0 ? 1 : 0), vz, h[2], Rw.x, Rw.y), tl, tx);
+                        float* pm = acc + (i + 1) * BP3_WG + tid;
+                        *pm = fmaf(tn - tl, rl, *pm);
+                        tl = tn;
+                    }
+                }
+            }
+            *p1 = fmaf(tx - tl, rl, v1);
+        }
+    }
+}
+
+// Back projection of views [a0, a1) of `views` into the columns of one workgroup tile
+// (block-local columns (tx0 + threadIdx.x % BP3_TX, ty0 + threadIdx.x / BP3_TX), z voxels
+// [zc0, zc0 + nzc)): acc[(iz + 1) * BP3_WG + threadIdx.x] += sum over the views' rays of a_ij r_i.
+// Every thread of the workgroup must call it (barriers).
+template <class Views>
+__device__ __forceinline__ void bp3_accumulate(const DevGeom& G, const BlockInfo& B, const Views& views, int a0,
+                                               int a1, int tx0, int ty0, int zc0, int nzc, float* lds)
+{
+    float* acc = lds;
+    Bp3View* rec = reinterpret_cast<Bp3View*>(acc + (BP3_CZ + 2) * BP3_WG);
+    const int km = G.bp3_kmax, lm = G.bp3_lmax;
+    float4* kc_all = reinterpret_cast<float4*>(rec + BP3_VC);
+    float2* rw_all = reinterpret_cast<float2*>(kc_all + BP3_VC * km);
+    float* tile_all = reinterpret_cast<float*>(rw_all + BP3_VC * lm);
+    float h[3];
+    h[0] = B.hx;
+    h[1] = B.hy;
+    h[2] = B.hz;
+    const int cx = tx0 + (int)threadIdx.x % BP3_TX, cy = ty0 + (int)threadIdx.x / BP3_TX;
+    const bool col_ok = cx < B.nbx && cy < B.nby;
+    const int tx1 = min(tx0 + BP3_TX, B.nbx), ty1 = min(ty0 + BP3_TY, B.nby);
+    for (int ab = a0; ab < a1; ab += BP3_VC) {
+        const int nvw = min(BP3_VC, a1 - ab);
+        __syncthreads();  // the previous round's readers are done
+        if (threadIdx.x < 64) {
+            // lanes 8q .. 8q+7: the eight corners of the tile in view slot ab + q
+            const int q = (int)threadIdx.x >> 3, corner = (int)threadIdx.x & 7;
+            PairWork W;
+            const float* p;
+            int stride;
+            const bool ok = q < nvw && views.get(ab + q, W, p, stride);
+            float kk = 0.0f, ll = 0.0f;
+            if (ok) {
+                const float X = plane_pos((corner & 1) ? tx1 : tx0, G.vx, h[0]);
+                const float Y = plane_pos((corner & 2) ? ty1 : ty0, G.vy, h[1]);
+                const float Z = plane_pos((corner & 4) ? zc0 + nzc : zc0, G.vz, h[2]) + W.cz;
+                const float w = fmaf(Y, W.c, -(X * W.s)) + W.cu;
+                const float rdep = __builtin_amdgcn_rcpf(W.depth - fmaf(X, W.c, Y * W.s));
+                kk = fmaf(G.sdd * w * rdep, __builtin_amdgcn_rcpf(G.du), 0.5f * (float)(G.nu - 1));
+                ll = fmaf(G.sdd * Z * rdep, __builtin_amdgcn_rcpf(G.dv), 0.5f * (float)(G.nv - 1));
+            }
+            float kmin = kk, kmax = kk, lmin = ll, lmax = ll;
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                kmin = fminf(kmin, __shfl_xor(kmin, o, 64));
+                kmax = fmaxf(kmax, __shfl_xor(kmax, o, 64));
+                lmin = fminf(lmin, __shfl_xor(lmin, o, 64));
+                lmax = fmaxf(lmax, __shfl_xor(lmax, o, 64));
+            }
+            if (corner == 0 && q < BP3_VC) {
+                Bp3View r;
+                r.a = ab + q;
+                r.pad0 = r.pad1 = 0;
+                if (ok) {
+                    r.k0 = max(W.k0, (int)ceilf(fminf(fmaxf(kmin - BP3_RECT_EPS, (float)W.k0), (float)W.k1)));
+                    r.k1 = min(W.k1, (int)floorf(fmaxf(fminf(kmax + BP3_RECT_EPS, (float)W.k1), (float)W.k0 - 1.0f)) + 1);
+                    r.l0 = max(W.l0, (int)ceilf(fminf(fmaxf(lmin - BP3_RECT_EPS, (float)W.l0), (float)W.l1)));
+                    r.l1 = min(W.l1, (int)floorf(fmaxf(fminf(lmax + BP3_RECT_EPS, (float)W.l1), (float)W.l0 - 1.0f)) + 1);
+                    if (r.k1 <= r.k0 || r.l1 <= r.l0) r.k0 = r.k1 = r.l0 = r.l1 = 0;
+                } else {
+                    r.k0 = r.k1 = r.l0 = r.l1 = 0;
+                }
+                r.staged = (r.k1 - r.k0) <= km && (r.l1 - r.l0) <= lm;
+                rec[q] = r;
+            }
+        }
+        __syncthreads();
+        // stage the rectangles: column records, row records, r |d|
+        for (int q = 0; q < nvw; ++q) {
+            const Bp3View r = rec[q];
+            if (!r.staged || r.k1 <= r.k0) continue;  // uniform
+            PairWork W;
+            const float* p;
+            int stride;
+            views.get(r.a, W, p, stride);
+            const int wt = r.k1 - r.k0, ht = r.l1 - r.l0;
+            float4* kc = kc_all + q * km;
+            float2* rw = rw_all + q * lm;
+            float* tile = tile_all + q * km * lm;
+            for (int e = threadIdx.x; e < wt + ht; e += BP3_WG) {
+                if (e < wt)
+                    kc[e] = bp3_kcol(G, W, r.k0 + e);
+                else
+                    rw[e - wt] = bp3_row(G, W, r.l0 + (e - wt));
+            }
+            for (int e = threadIdx.x; e < wt * ht; e += BP3_WG) {
+                const int l = e / wt, k = e - l * wt;
+                tile[e] = bp3_rlen(G, W, p, stride, r.k0 + k, r.l0 + l);
+            }
+        }
+        __syncthreads();
+        if (!col_ok) continue;
+        for (int q = 0; q < nvw; ++q) {
+            const Bp3View r = rec[q];
+            if (r.k1 <= r.k0) continue;  // uniform
+            PairWork W;
+            const float* p;
+            int stride;
+            views.get(r.a, W, p, stride);
+            if (r.staged) {
+                if (G.bp3_steep)
+                    bp3_column_view<true, true>(G, W, r, p, stride, kc_all + q * km, rw_all + q * lm,
+                                                tile_all + q * km * lm, cx, cy, zc0, nzc, h, acc);
+                else
+                    bp3_column_view<true, false>(G, W, r, p, stride, kc_all + q * km, rw_all + q * lm,
+                                                 tile_all + q * km * lm, cx, cy, zc0, nzc, h, acc);
+            } else {
+                bp3_column_view<false, true>(G, W, r, p, stride, nullptr, nullptr, nullptr, cx, cy, zc0, nzc, h, acc);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Workgroup tile `tile` of block B: first column (tx0, ty0) and z range [zc0, zc0 + nzc);
+// false when the block has fewer tiles (uniform).
+__device__ __forceinline__ bool bp3_tile(const BlockInfo& B, int tile, int& tx0, int& ty0, int& zc0, int& nzc)
+{
+    const int ntx = (B.nbx + BP3_TX - 1) / BP3_TX, nty = (B.nby + BP3_TY - 1) / BP3_TY;
+    const int ntz = (B.nbz + BP3_CZ - 1) / BP3_CZ;
+    if (tile >= ntx * nty * ntz) return false;
+    tx0 = (tile % ntx) * BP3_TX;
+    ty0 = ((tile / ntx) % nty) * BP3_TY;
+    zc0 = (tile / (ntx * nty)) * BP3_CZ;
+    nzc = min(BP3_CZ, B.nbz - zc0);
+    return true;
+}
+
+// Solver step for 3D blocks (bp_step_body's contract): per selected row block the
+// column sums give g_hat^i_new = 2 (A_rows^J)^T r, then g and x as in the 2D form.
+template <bool SUB>
+__device__ __forceinline__ void bp3_step_body(const DevGeom& G, const int32_t* __restrict__ S_,
+                                              const PairWork* __restrict__ work, SchedLayout L,
+                                              const float* __restrict__ src, float* __restrict__ ghat,
+                                              float* __restrict__ gsum, float* __restrict__ x,
+                                              const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
+                                              float* lds)
+{
     const int b = by;
     const int j = S_[L.off_blocks() + b];
     const BlockInfo B = G.blocks[j];
-    int nb[3];
-    float h[3], vs[3];
-    block_dims(G, B, nb, h, vs);
-    const int vl = threadIdx.x % BP_VOX;
-    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
-    int li[3];
-    bool tile_ok;
-    const bool valid = tile_voxel<DIM>(B, bx, vl, li, tile_ok);
-    if (!tile_ok) return;  // uniform over the workgroup
-    const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
-    const int per_view = G.nu * G.nv;
-    const PairWork* wb = work + (int64_t)b * L.maxv;
-    float dg = 0.0f;
+    int tx0, ty0, zc0, nzc;
+    if (!bp3_tile(B, bx, tx0, ty0, zc0, nzc)) return;  // uniform over the workgroup
+    float* acc = lds;
+    const int cx = tx0 + (int)threadIdx.x % BP3_TX, cy = ty0 + (int)threadIdx.x / BP3_TX;
+    const bool col_ok = cx < B.nbx && cy < B.nby;
+#pragma unroll
+    for (int iz = 0; iz < BP3_CZ + 2; ++iz) acc[iz * BP3_WG + threadIdx.x] = 0.0f;
+    const Bp3StepViews views{work + (int64_t)b * L.maxv, src, G.nu * G.nv, G.nu, SUB};
+    const int64_t plane = (int64_t)G.nx * G.ny;
+    const int64_t vox0 = ((int64_t)(B.z0 + zc0) * G.ny + (B.y0 + cy)) * (int64_t)G.nx + (B.x0 + cx);
+    float dg[BP3_CZ];
+#pragma unroll
+    for (int iz = 0; iz < BP3_CZ; ++iz) dg[iz] = 0.0f;
     for (int ri = 0; ri < L.R; ++ri) {
         const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
-        float acc = 0.0f;
-        if (valid) {
-            for (int a = a0 + grp; a < a1; a += bp_split(DIM)) {
-                const PairWork W = wb[a];
-                if (W.k1 <= W.k0) continue;
-                acc += bp_voxel_view<DIM>(G, W.view, W.c, W.s, W, li, h, vs, W.k0, W.k1, W.l0, W.l1,
-                                          SUB ? src + W.zbase : src + (int64_t)a * per_view, SUB ? W.zw : G.nu);
-            }
-        }
-        part[grp][0][vl] = acc;
-        __syncthreads();
-        if (grp == 0 && valid) {
-            float sum = part[0][0][vl];
+        bp3_accumulate(G, B, views, a0, a1, tx0, ty0, zc0, nzc, lds);
+        if (col_ok) {
+            const int i = S_[L.off_rows() + ri];
 #pragma unroll
-            for (int q = 1; q < bp_split(DIM); ++q) sum += part[q][0][vl];
-            if (SUB) {
-                dg += 2.0f * sum;
-            } else {
-                const int i = S_[L.off_rows() + ri];
-                const float gnew = 2.0f * sum;
-                float* gp = ghat + (int64_t)i * n_vox + vox;
-                dg += gnew - *gp;
-                *gp = gnew;
+            for (int iz = 0; iz < BP3_CZ; ++iz) {
+                if (iz < nzc) {
+                    float* ap = acc + (iz + 1) * BP3_WG + threadIdx.x;
+                    const float gnew = 2.0f * *ap;
+                    *ap = 0.0f;
+                    if (SUB) {
+                        dg[iz] += gnew;
+                    } else {
+                        float* gp = ghat + (int64_t)i * n_vox + vox0 + iz * plane;
+                        dg[iz] += gnew - *gp;
+                        *gp = gnew;
+                    }
+                }
             }
         }
-        __syncthreads();
     }
-    if (grp == 0 && valid) {
-        const float gv = gsum[vox] + dg;
-        gsum[vox] = gv;
-        x[vox] = fmaf(*mu_ptr, gv, x[vox]);
+    if (col_ok) {
+        const float mu = *mu_ptr;
+#pragma unroll
+        for (int iz = 0; iz < BP3_CZ; ++iz) {
+            if (iz < nzc) {
+                const int64_t vox = vox0 + iz * plane;
+                const float gv = gsum[vox] + dg[iz];
+                gsum[vox] = gv;
+                x[vox] = fmaf(mu, gv, x[vox]);
+            }
+        }
     }
 }
+
+// Workgroup size of the back projectors: 2D four waves of pair tiles; 3D one thread per
+// voxel column of a 16 x 16 column tile.
+__host__ __device__ constexpr int bp_wg(int dim) { return dim == 3 ? BP3_WG : BP_VOX * BP_SPLIT_2D; }
 
 template <int DIM, bool SUB>
 __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
@@ -1028,13 +1306,15 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t
                                                 float* __restrict__ x, const float* __restrict__ mu,
                                                 long long n_vox)
 {
-    __shared__ float part[bp_split(DIM)][DIM == 2 ? 2 : 1][BP_VOX];
     int bx, by;
     xcd_grid2(bx, by);
-    if constexpr (DIM == 2)
+    if constexpr (DIM == 2) {
+        __shared__ float part[BP_SPLIT_2D][2][BP_VOX];
         bp_step_body_2d<SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
-    else
-        bp_step_body<DIM, SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
+    } else {
+        extern __shared__ float bp3_lds[];
+        bp3_step_body<SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, bp3_lds);
+    }
 }
 
 // Sub-detector gradient memory: one workgroup per (view slot, block slot) pair. Over the
@@ -1120,19 +1400,21 @@ __global__ __launch_bounds__(TPB) void k_resid_batch(const BatchArgs A)
 template <int DIM>
 __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_batch(const BatchArgs A)
 {
-    __shared__ float part[bp_split(DIM)][DIM == 2 ? 2 : 1][BP_VOX];
     const int id = xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 2, id));
     const BatchEntry& B = A.e[e];
     const int local = id - B.base[2];
     const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
     const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
-    if constexpr (DIM == 2)
+    if constexpr (DIM == 2) {
+        __shared__ float part[BP_SPLIT_2D][2][BP_VOX];
         bp_step_body_2d<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
                                local / B.gx[2], part);
-    else
-        bp_step_body<DIM, false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
-                                 local / B.gx[2], part);
+    } else {
+        extern __shared__ float bp3_lds[];
+        bp3_step_body<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
+                             local / B.gx[2], bp3_lds);
+    }
 }
 
 // ------------------------------------------------------------ standalone projectors
@@ -1163,14 +1445,13 @@ __global__ __launch_bounds__(WG) void k_fp_full(DevGeom G, const int32_t* __rest
     *dst = accumulate ? *dst + acc : acc;
 }
 
-// Standalone back projection into block j0 + blockIdx.y: 3D one voxel per lane (tiles
-// of 64), 2D two x-adjacent voxels per lane (pair tiles, as the solver's).
-template <int DIM>
-__global__ __launch_bounds__(bp_wg(DIM)) void k_bp_full(DevGeom G, const int32_t* __restrict__ views, int n_sel, int j0,
-                                                const float* __restrict__ y, float* __restrict__ x, float scale,
-                                                int accumulate)
+// Standalone back projection into block j0 + blockIdx.y, 2D: two x-adjacent voxels per
+// lane (pair tiles, as the solver's).
+__global__ __launch_bounds__(bp_wg(2)) void k_bp_full_2d(DevGeom G, const int32_t* __restrict__ views, int n_sel, int j0,
+                                                 const float* __restrict__ y, float* __restrict__ x, float scale,
+                                                 int accumulate)
 {
-    __shared__ float part[bp_split(DIM)][DIM == 2 ? 2 : 1][BP_VOX];
+    __shared__ float part[BP_SPLIT_2D][2][BP_VOX];
     const int j = j0 + blockIdx.y;
     const BlockInfo B = G.blocks[j];
     int nb[3];
@@ -1180,44 +1461,66 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_full(DevGeom G, const int32_t
     const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / BP_VOX);
     int li[3];
     bool tile_ok, valid, b_ok = false;
-    if constexpr (DIM == 2)
-        pair_tile_voxels(B, blockIdx.x, vl, li, tile_ok, valid, b_ok);
-    else
-        valid = tile_voxel<DIM>(B, blockIdx.x, vl, li, tile_ok);
+    pair_tile_voxels(B, blockIdx.x, vl, li, tile_ok, valid, b_ok);
     if (!tile_ok) return;
     const int per_view = G.nu * G.nv;
     float acc = 0.0f, acc_b = 0.0f;
     if (valid) {
-        for (int a = grp; a < n_sel; a += bp_split(DIM)) {
+        for (int a = grp; a < n_sel; a += BP_SPLIT_2D) {
             const int v = views[a];
             const PairInfo P = G.pairs[(int64_t)v * G.N + j];
             if (P.u1 <= P.u0 || P.v1 <= P.v0) continue;
             const float2 cs = G.cs[v];
-            if (DIM == 2)
-                bp_voxel_pair_view_2d<false>(G, v, cs.x, cs.y, P, li, b_ok, h, vs, P.u0, P.u1,
-                                             y + (int64_t)a * per_view, acc, acc_b);
-            else
-                acc += bp_voxel_view<DIM>(G, v, cs.x, cs.y, P, li, h, vs, P.u0, P.u1, P.v0, P.v1,
-                                          y + (int64_t)a * per_view, G.nu);
+            bp_voxel_pair_view_2d<false>(G, v, cs.x, cs.y, P, li, b_ok, h, vs, P.u0, P.u1, y + (int64_t)a * per_view,
+                                         acc, acc_b);
         }
     }
-    constexpr int IB = DIM == 2 ? 1 : 0;  // slot of the second voxel's partial sums (2D)
     part[grp][0][vl] = acc;
-    part[grp][IB][vl] = DIM == 2 ? acc_b : acc;
+    part[grp][1][vl] = acc_b;
     __syncthreads();
     if (grp == 0 && valid) {
-        float sum = part[0][0][vl], sum_b = part[0][IB][vl];
+        float sum = part[0][0][vl], sum_b = part[0][1][vl];
 #pragma unroll
-        for (int q = 1; q < bp_split(DIM); ++q) {
+        for (int q = 1; q < BP_SPLIT_2D; ++q) {
             sum += part[q][0][vl];
-            sum_b += part[q][IB][vl];
+            sum_b += part[q][1][vl];
         }
-        const int64_t vox = ((int64_t)(B.z0 + li[2]) * G.ny + (B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
+        const int64_t vox = ((int64_t)(B.y0 + li[1])) * (int64_t)G.nx + (B.x0 + li[0]);
         const float val = scale * sum;
         x[vox] = accumulate ? x[vox] + val : val;
-        if (DIM == 2 && b_ok) {
+        if (b_ok) {
             const float vb = scale * sum_b;
             x[vox + 1] = accumulate ? x[vox + 1] + vb : vb;
+        }
+    }
+}
+
+// Standalone back projection into block j0 + blockIdx.y, 3D: voxel-column tiles
+// (bp3_accumulate) over the whole view list.
+__global__ __launch_bounds__(BP3_WG) void k_bp_full_3d(DevGeom G, const int32_t* __restrict__ views, int n_sel, int j0,
+                                                const float* __restrict__ y, float* __restrict__ x, float scale,
+                                                int accumulate)
+{
+    extern __shared__ float bp3_lds[];
+    const int j = j0 + blockIdx.y;
+    const BlockInfo B = G.blocks[j];
+    int tx0, ty0, zc0, nzc;
+    if (!bp3_tile(B, blockIdx.x, tx0, ty0, zc0, nzc)) return;  // uniform
+    float* acc = bp3_lds;
+#pragma unroll
+    for (int iz = 0; iz < BP3_CZ + 2; ++iz) acc[iz * BP3_WG + threadIdx.x] = 0.0f;
+    const Bp3FullViews fv{G.pairs, G.cs, views, y, j, G.N, G.nu * G.nv, G.nu};
+    bp3_accumulate(G, B, fv, 0, n_sel, tx0, ty0, zc0, nzc, bp3_lds);
+    const int cx = tx0 + (int)threadIdx.x % BP3_TX, cy = ty0 + (int)threadIdx.x / BP3_TX;
+    if (cx >= B.nbx || cy >= B.nby) return;
+    const int64_t plane = (int64_t)G.nx * G.ny;
+    const int64_t vox0 = ((int64_t)(B.z0 + zc0) * G.ny + (B.y0 + cy)) * (int64_t)G.nx + (B.x0 + cx);
+#pragma unroll
+    for (int iz = 0; iz < BP3_CZ; ++iz) {
+        if (iz < nzc) {
+            const int64_t vox = vox0 + iz * plane;
+            const float val = scale * acc[(iz + 1) * BP3_WG + threadIdx.x];
+            x[vox] = accumulate ? x[vox] + val : val;
         }
     }
 }
@@ -1459,6 +1762,7 @@ size_t fp_lds_bytes_for(const DevGeom& G)
 size_t resid_lds_bytes_for(const DevGeom& G) { return resid_lds_bytes(G, res_wg(G.dim)); }
 
 static int step_tiles(const DevGeom& G);
+static size_t bp_lds_bytes(const DevGeom& G);
 
 void batch_grids(BatchEntry& e)
 {
@@ -1508,8 +1812,10 @@ hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], co
         hipLaunchKernelGGL(k_resid_batch<res_wg(2)>, dim3(wgs[1]), dim3(res_wg(2)), res_lds, st, A);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    size_t bp_lds = 0;
+    for (int i = 0; i < A.n; ++i) bp_lds = std::max(bp_lds, bp_lds_bytes(A.e[i].G));
     if (dim == 3)
-        hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(bp_wg(3)), 0, st, A);
+        hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(bp_wg(3)), bp_lds, st, A);
     else
         hipLaunchKernelGGL(k_bp_batch<2>, dim3(wgs[2]), dim3(bp_wg(2)), 0, st, A);
     return hipGetLastError();
@@ -1531,15 +1837,16 @@ hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L
 }
 
 
-// Workgroups per block of the back projectors (largest block): 2D pair tiles, 3D tiles.
+// Workgroups per block of the back projectors (largest block): 2D pair tiles, 3D
+// voxel-column tiles.
 static int step_tiles(const DevGeom& G)
 {
-    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by, mbz = (G.nz + G.bz - 1) / G.bz;
-    if (G.dim == 3)
-        return ((mbx + Tile<3>::X - 1) / Tile<3>::X) * ((mby + Tile<3>::Y - 1) / Tile<3>::Y) *
-               ((mbz + Tile<3>::Z - 1) / Tile<3>::Z);
+    if (G.dim == 3) return bp3_tiles(G);
+    const int mbx = (G.nx + G.bx - 1) / G.bx, mby = (G.ny + G.by - 1) / G.by;
     return ((mbx + PAIR_TX - 1) / PAIR_TX) * ((mby + PAIR_TY - 1) / PAIR_TY);
 }
+
+static size_t bp_lds_bytes(const DevGeom& G) { return G.dim == 3 ? bp3_lds_bytes(G) : 0; }
 
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
                           const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, const float* mu,
@@ -1548,15 +1855,16 @@ hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairW
     const int tiles = step_tiles(G);
     const dim3 grid(tiles, L.B), blk(bp_wg(G.dim));
     const long long nv = (long long)n_vox;
+    const size_t lds = bp_lds_bytes(G);
     if (delta) {
         if (G.dim == 3)
-            hipLaunchKernelGGL((k_bp_step<3, true>), grid, blk, 0, st, G, sched_it, work_it, L, delta, ghat, gsum, x,
+            hipLaunchKernelGGL((k_bp_step<3, true>), grid, blk, lds, st, G, sched_it, work_it, L, delta, ghat, gsum, x,
                                mu, nv);
         else
             hipLaunchKernelGGL((k_bp_step<2, true>), grid, blk, 0, st, G, sched_it, work_it, L, delta, ghat, gsum, x,
                                mu, nv);
     } else if (G.dim == 3) {
-        hipLaunchKernelGGL((k_bp_step<3, false>), grid, blk, 0, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
+        hipLaunchKernelGGL((k_bp_step<3, false>), grid, blk, lds, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
                            mu, nv);
     } else {
         hipLaunchKernelGGL((k_bp_step<2, false>), grid, blk, 0, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
@@ -1594,10 +1902,10 @@ hipError_t launch_bp_full(const DevGeom& G, const int32_t* views, int n_sel, int
     const int tiles = step_tiles(G);
     const int j0 = block < 0 ? 0 : block, nj = block < 0 ? G.N : 1;
     if (G.dim == 3)
-        hipLaunchKernelGGL(k_bp_full<3>, dim3(tiles, nj), dim3(bp_wg(3)), 0, st, G, views, n_sel, j0, y, x, scale,
-                           accumulate);
+        hipLaunchKernelGGL(k_bp_full_3d, dim3(tiles, nj), dim3(BP3_WG), bp3_lds_bytes(G), st, G, views, n_sel, j0, y, x,
+                           scale, accumulate);
     else
-        hipLaunchKernelGGL(k_bp_full<2>, dim3(tiles, nj), dim3(bp_wg(2)), 0, st, G, views, n_sel, j0, y, x, scale,
+        hipLaunchKernelGGL(k_bp_full_2d, dim3(tiles, nj), dim3(bp_wg(2)), 0, st, G, views, n_sel, j0, y, x, scale,
                            accumulate);
     return hipGetLastError();
 }
@@ -1657,6 +1965,46 @@ hipError_t launch_fill(float* a, float v, int64_t n, hipStream_t st)
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(WG), 0, st, a, v, (long long)n);
     return hipGetLastError();
+}
+
+void set_bp3_bounds(DevGeom& G, double sod, double sdd, double du, double dv)
+{
+    G.bp3_kmax = G.bp3_lmax = 0;
+    G.bp3_steep = 1;
+    if (G.dim != 3) return;
+    // a ray's height changes by at most |v| / |(a, b)| <= (nv - 1) dv / (2 sdd) per mm of
+    // xy path, and its xy chord through one voxel column is at most the voxel's xy
+    // diagonal: below 0.9 vz no chord reaches across a whole voxel, so it meets at
+    // most one z plane inside a column (with room for the rounding of the voxel pick)
+    {
+        const double slope = 0.5 * (G.nv - 1) * dv / sdd;
+        const double dxy = std::sqrt((double)G.vx * G.vx + (double)G.vy * G.vy);
+        G.bp3_steep = slope * dxy <= 0.9 * (double)G.vz ? 0 : 1;
+    }
+    // A workgroup tile is at most BP3_TX x BP3_TY x BP3_CZ voxels anywhere in the volume.
+    // For two of its points at depths d1, d2 >= dmin and lateral offsets w1, w2,
+    // |w1/d1 - w2/d2| <= |w1 - w2| / dmin + |w2| |d1 - d2| / dmin^2, with |w1 - w2| and
+    // |d1 - d2| at most the tile's xy diagonal and |w2| at most the volume's xy radius;
+    // the same for heights z. The pixel rectangle spans at most that many pixels plus
+    // two (integer ends) plus the margins.
+    const double vx = G.vx, vy = G.vy, vz = G.vz;
+    const double diag = std::sqrt((BP3_TX * vx) * (BP3_TX * vx) + (BP3_TY * vy) * (BP3_TY * vy));
+    const double rxy = 0.5 * std::sqrt((G.nx * vx) * (G.nx * vx) + (G.ny * vy) * (G.ny * vy));
+    const double zmax = 0.5 * G.nz * vz;
+    const double dmin = sod - rxy;
+    if (!(dmin > 0.0)) return;
+    const double wpx = sdd * (diag / dmin + rxy * diag / (dmin * dmin)) / du;
+    const double hpx = sdd * (BP3_CZ * vz / dmin + zmax * diag / (dmin * dmin)) / dv;
+    const int km = (int)std::min((double)G.nu, std::floor(wpx) + 3.0);
+    const int lm = (int)std::min((double)G.nv, std::floor(hpx) + 3.0);
+    DevGeom t = G;
+    t.bp3_kmax = km;
+    t.bp3_lmax = lm;
+    // stay inside the 64 KB a workgroup may address without an opt-in
+    if (km > 0 && lm > 0 && bp3_lds_bytes(t) <= 65536) {
+        G.bp3_kmax = km;
+        G.bp3_lmax = lm;
+    }
 }
 
 void tv_weight_step(int dim, double mu, double lambda, float* out)
