@@ -122,6 +122,9 @@ def im_table(p: Problem, mode: str) -> Optional[np.ndarray]:
         return np.ones((g.n_views, S, p.N), dtype=np.uint32)
     if mode == "colnorm":
         return quantise(im_weights(p))
+    if mode == "area":
+        from .area import area_weights
+        return quantise(area_weights(g))
     raise ValueError(mode)
 
 
