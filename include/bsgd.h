@@ -28,7 +28,8 @@
  *
  * Ownership: the caller owns every pointer it passes (device pointers for x, y, r;
  * host pointers where stated) and the stream; the library owns geometry tables and
- * solver state, allocates them with hipMalloc and frees them in *_destroy.
+ * solver state, allocates them through the geometry's allocator (bsgd_allocator;
+ * hipMalloc when none is given) and frees them in *_destroy.
  * Calls are asynchronous on the given stream (a hipStream_t, NULL = default stream)
  * unless they return host values, which synchronise that stream.
  * Errors: every call returns a status; no exception crosses the ABI. Invalid
@@ -64,8 +65,24 @@ typedef enum { BSGD_PARALLEL_2D = 0, BSGD_FAN_FLAT_2D = 1, BSGD_CONE_FLAT_3D = 2
  * COLNORM : probability of sub-detector s for (view v, block j) proportional to
  *           ||A[rows of s in v, J_j]||_F^2 (the denser sub-matrix is the likelier,
  *           Sec. II-A), quantised to integers q = round(2^20 w / sum w) (>= 1 if w > 0).
+ * AREA    : proportional to the area of block j's projection (the shadow of its
+ *           corners, in detector pixel units, pixel k spanning [k - 1/2, k + 1/2])
+ *           that falls on sub-detector s: the estimate of the sub-matrix density the
+ *           paper gives for Algorithm 2 (Sec. II-A); same quantisation. In 2D the shadow
+ *           is an interval and the area its length.
  * UNIFORM : every sub-detector equally likely (BSGD-RAN, Sec. III-E-3). */
-typedef enum { BSGD_IM_NONE = 0, BSGD_IM_COLNORM = 1, BSGD_IM_UNIFORM = 3 } bsgd_im_mode;
+typedef enum { BSGD_IM_NONE = 0, BSGD_IM_COLNORM = 1, BSGD_IM_AREA = 2, BSGD_IM_UNIFORM = 3 } bsgd_im_mode;
+
+/* Device memory provider for a geometry and every solver created from it (for example
+ * a framework's caching allocator). alloc returns `bytes` of device memory usable on
+ * `stream` (NULL on failure); free releases a pointer alloc returned, on the stream it
+ * was allocated for. ctx and both functions must stay valid until the geometry and its
+ * solvers are destroyed. */
+typedef struct {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*free)(void* ctx, void* ptr, void* stream);
+} bsgd_allocator;
 
 typedef struct {
     int32_t kind;                 /* bsgd_kind */
@@ -82,15 +99,23 @@ typedef struct {
     int32_t su, sv;               /* sub-detectors per view (IM), S = su sv <= 16 */
     int32_t im_mode;              /* bsgd_im_mode */
     const uint32_t* im_table;     /* optional host [n_views][S][N] sampling weights; NULL = computed */
+    const bsgd_allocator* allocator; /* device memory of tables and solver state; NULL = hipMalloc
+                                        (the struct is copied, its ctx and functions are kept) */
 } bsgd_geometry_desc;
 
 typedef struct bsgd_geometry bsgd_geometry;
 typedef struct bsgd_solver bsgd_solver;
 
-/* Validate the descriptor, build the partitions, the per-(view, block) detector
- * footprints and, on the device, the per-(view, sub-detector, block) squared
- * norms and nonzero counts of A (the IM weights; computed for every mode).
- * Synchronises `stream` once. *out is NULL on failure. */
+/* The system matrix A of Sec. I (a_ij = length of ray i inside voxel j, never stored)
+ * and its partition of Sec. II, Eq. (e1): M row blocks of whole views and N column
+ * blocks of the image, with the sampling tables of Algorithm 2. Validates the
+ * descriptor, builds the partitions, the per-(view, block) detector footprints, the
+ * projected areas of the AREA mode and, on the device, the per-(view, sub-detector,
+ * block) squared norms and nonzero counts of A (computed for every mode). Synchronises
+ * `stream`. Invalid descriptors (an unknown kind or sampling mode, sizes out of range,
+ * a volume not strictly between source and detector, an allocator without both
+ * functions) return BSGD_E_INVALID_ARG before any device work; *out is NULL on any
+ * failure. */
 bsgd_status bsgd_geometry_create(const bsgd_geometry_desc* desc, void* stream, bsgd_geometry** out);
 void bsgd_geometry_destroy(bsgd_geometry* geom);
 
@@ -113,14 +138,16 @@ bsgd_status bsgd_geometry_get_info(const bsgd_geometry* geom, bsgd_geometry_info
  * IM_WEIGHTS  double [n_views][S][N]   ||A[rows of sub-detector s of view v, J_j]||_F^2
  * IM_TABLE    uint32 [n_views][S][N]   quantised sampling table in use
  * NNZ         int64 [n_views][S][N]    nonzeros of each such sub-matrix
- * FOOTPRINT   int32 [n_views][N][4]    detector rectangle [u0, u1) x [v0, v1) of block j */
+ * FOOTPRINT   int32 [n_views][N][4]    detector rectangle [u0, u1) x [v0, v1) of block j
+ * IM_AREA     double [n_views][S][N]   area of block j's projection on sub-detector s (pixels^2) */
 typedef enum {
     BSGD_TABLE_VIEW_ORDER = 0,
     BSGD_TABLE_GROUP_START = 1,
     BSGD_TABLE_IM_WEIGHTS = 2,
     BSGD_TABLE_IM_TABLE = 3,
     BSGD_TABLE_NNZ = 4,
-    BSGD_TABLE_FOOTPRINT = 5
+    BSGD_TABLE_FOOTPRINT = 5,
+    BSGD_TABLE_IM_AREA = 6
 } bsgd_table;
 bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* out, size_t bytes);
 
@@ -268,6 +295,14 @@ bsgd_status bsgd_normal_residual_noalloc(const bsgd_geometry* geom, const float*
                                          void* stream);
 size_t bsgd_noalloc_scratch_bytes(void);
 
+/* Asynchronous form of bsgd_normal_residual for serving loops that must not wait on
+ * the device: enqueues, for every solver i, ||A^T (y - A x_i)||^2 into out_sq[2 i] and
+ * ||A^T y||^2 into out_sq[2 i + 1] (computed on the solver's first call and kept on the
+ * device), copied to host memory out_sq (page-locked for the copy to be asynchronous)
+ * in stream order; out_sq is valid once `stream` has passed this call (an event or a
+ * synchronisation). Same kernels and values as bsgd_normal_residual. */
+bsgd_status bsgd_normal_residual_async(bsgd_solver* const* solvers, int32_t n, double* out_sq, void* stream);
+
 /* Current step length and its value after each Algorithm 3 check (history[0..cap)). */
 bsgd_status bsgd_solver_step_length(const bsgd_solver* s, double* mu_now, double* history, int32_t cap,
                                     int32_t* n_history);
@@ -298,7 +333,13 @@ bsgd_status bsgd_solver_kernel_times(bsgd_solver* s, double* ms_out, int64_t* la
 
 void bsgd_solver_destroy(bsgd_solver* s);
 
-/* Create, iterate to the stopping rule, write x, destroy. Synchronises. */
+/* The reconstruction of Sec. I, min 1/2 ||y - A x||^2, by Algorithms 1, 2 and 4 (the
+ * options select the form): create a solver for (y, x), step whole effective epochs
+ * until the stopping rule of bsgd_options (tol, max_effective_epochs), write the image
+ * to x, destroy the solver. x holds the initial image on entry. *iters_out and
+ * *resid_norm_out (either may be NULL) receive the iterations run and ||y - sum_j z^j||.
+ * Synchronises `stream`. Errors as bsgd_solver_create and bsgd_step; x then holds the
+ * last iterate reached. */
 bsgd_status bsgd_solve(const bsgd_geometry* geom, const float* y, float* x, const bsgd_options* opt,
                        void* stream, int32_t* iters_out, double* resid_norm_out);
 

@@ -21,8 +21,9 @@ BSGD_OK = 0
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_UNSUPPORTED", 3: "E_OUT_OF_MEMORY", 4: "E_DEVICE",
                 5: "E_DIVERGED", 6: "E_STATE"}
 KIND = {"parallel2d": 0, "fan2d": 1, "cone3d": 2}
-IM_MODE = {"none": 0, "colnorm": 1, "uniform": 3}
-TABLE = {"view_order": 0, "group_start": 1, "im_weights": 2, "im_table": 3, "nnz": 4, "footprint": 5}
+IM_MODE = {"none": 0, "colnorm": 1, "area": 2, "uniform": 3}
+TABLE = {"view_order": 0, "group_start": 1, "im_weights": 2, "im_table": 3, "nnz": 4, "footprint": 5,
+         "im_area": 6}
 KERNELS = ("forward_project", "residual", "back_project_step", "tv_prox", "draws")
 ACCUMULATE = 1
 
@@ -31,6 +32,14 @@ class BsgdError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"bsgd {STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
 
 
 class GeometryDesc(ctypes.Structure):
@@ -44,6 +53,7 @@ class GeometryDesc(ctypes.Structure):
         ("n_row_blocks", ctypes.c_int32), ("partition_seed", ctypes.c_uint64),
         ("su", ctypes.c_int32), ("sv", ctypes.c_int32), ("im_mode", ctypes.c_int32),
         ("im_table", ctypes.POINTER(ctypes.c_uint32)),
+        ("allocator", ctypes.POINTER(Allocator)),
     ]
 
 
@@ -77,7 +87,7 @@ EXPORTED = (
     "bsgd_solver_last_schedule", "bsgd_solver_state", "bsgd_solver_set_profiling", "bsgd_solver_kernel_times",
     "bsgd_solver_destroy", "bsgd_solve", "bsgd_last_error", "bsgd_step_batch", "bsgd_geometry_set_tuning",
     "bsgd_geometry_get_tuning", "bsgd_solver_step_length", "bsgd_normal_residual",
-    "bsgd_normal_residual_noalloc", "bsgd_noalloc_scratch_bytes",
+    "bsgd_normal_residual_noalloc", "bsgd_noalloc_scratch_bytes", "bsgd_normal_residual_async",
 )
 
 _lib = None
@@ -118,6 +128,7 @@ def load_library(path: str = LIB_PATH):
         "bsgd_normal_residual": (i32, [ctypes.POINTER(P), i32, i32, P, P]),
         "bsgd_normal_residual_noalloc": (i32, [P, P, P, ctypes.POINTER(ctypes.c_double), P]),
         "bsgd_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+        "bsgd_normal_residual_async": (i32, [ctypes.POINTER(P), i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -159,10 +170,34 @@ def _views_arg(views):
     return arr.ctypes.data_as(ctypes.c_void_p), int(arr.size), arr
 
 
-class Geometry:
-    """A scan geometry, its block partition and sampling tables (bsgd_geometry)."""
+def torch_allocator() -> Allocator:
+    """bsgd_allocator over PyTorch's caching allocator (device memory of the current
+    device, stream-ordered on the stream the library names). The returned structure
+    holds the callbacks; keep it alive as long as the geometry and its solvers."""
 
-    def __init__(self, spec, im_table: Optional[np.ndarray] = None, stream=None):
+    def _alloc(ctx, nbytes, stream):
+        try:
+            import torch
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:  # the library reports a failed allocation as out of memory
+            return None
+
+    def _free(ctx, ptr, stream):
+        try:
+            import torch
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    return Allocator(None, ALLOC_FN(_alloc), FREE_FN(_free))
+
+
+class Geometry:
+    """A scan geometry, its block partition and sampling tables (bsgd_geometry).
+    allocator: None (hipMalloc) or "torch" (PyTorch's caching allocator), used for the
+    geometry's tables and the state of every solver created from it."""
+
+    def __init__(self, spec, im_table: Optional[np.ndarray] = None, stream=None, allocator=None):
         self.spec = spec
         lib = load_library()
         angles = np.ascontiguousarray(spec.angles(), dtype=np.float64)
@@ -179,8 +214,14 @@ class Geometry:
         d.n_row_blocks = spec.n_row_blocks
         d.partition_seed = spec.partition_seed
         d.su, d.sv = spec.su, spec.sv
-        d.im_mode = IM_MODE[spec.im_mode] if spec.im_mode in IM_MODE else 2
+        d.im_mode = IM_MODE[spec.im_mode]
         self._im = None
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = torch_allocator()
+            d.allocator = ctypes.pointer(self._alloc)
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
         if im_table is not None:
             self._im = np.ascontiguousarray(im_table, dtype=np.uint32)
             d.im_table = self._im.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
@@ -241,6 +282,7 @@ class Geometry:
         V, S, N, M = g.n_views, g.su * g.sv, g.n_blocks, g.n_row_blocks
         shapes = {"view_order": ((V,), np.int32), "group_start": ((M + 1,), np.int32),
                   "im_weights": ((V, S, N), np.float64), "im_table": ((V, S, N), np.uint32),
+                  "im_area": ((V, S, N), np.float64),
                   "nnz": ((V, S, N), np.int64), "footprint": ((V, N, 4), np.int32)}
         shape, dt = shapes[name]
         out = np.zeros(shape, dtype=dt)
@@ -402,6 +444,19 @@ def normal_residual(solvers, relative: bool = True, stream=None):
     _check(load_library().bsgd_normal_residual(arr, len(solvers), int(bool(relative)),
                                                out.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
     return out
+
+
+def normal_residual_async(solvers, out_sq, stream=None):
+    """Enqueue ||A^T (y - A x)||^2 and ||A^T y||^2 of each solver into out_sq (a page-locked
+    float64 host tensor of 2 n values), without waiting (bsgd_normal_residual_async);
+    read out_sq after the stream has passed this point."""
+    import torch
+    if not (isinstance(out_sq, torch.Tensor) and out_sq.dtype == torch.float64 and not out_sq.is_cuda
+            and out_sq.is_contiguous() and out_sq.numel() >= 2 * len(solvers)):
+        raise ValueError("out_sq must be a contiguous float64 host tensor of at least 2 n values")
+    arr = (ctypes.c_void_p * len(solvers))(*[s._h.value for s in solvers])
+    _check(load_library().bsgd_normal_residual_async(arr, len(solvers), ctypes.c_void_p(out_sq.data_ptr()),
+                                                     _stream_ptr(stream)))
 
 
 def normal_residual_noalloc(geom: Geometry, y, x, stream=None) -> float:

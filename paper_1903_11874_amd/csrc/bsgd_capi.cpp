@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -80,13 +81,28 @@ void choose(uint64_t seed, uint64_t stream, int64_t k, int n, int m, int32_t* ou
     std::copy(scratch.begin(), scratch.begin() + m, out);
 }
 
+// Device buffer from the geometry's allocator (hipMalloc when there is none), released
+// on the stream it was allocated for.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    const bsgd_allocator* A = nullptr;
+    hipStream_t st = nullptr;
     ~DevBuf() { release(); }
+    void use(const bsgd_allocator* a, hipStream_t s)
+    {
+        release();
+        A = a;
+        st = s;
+    }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (A)
+                A->free(A->ctx, p, (void*)st);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
     }
@@ -94,6 +110,12 @@ struct DevBuf {
     {
         release();
         if (b == 0) b = 16;
+        if (A) {
+            p = A->alloc(A->ctx, b, (void*)st);
+            if (!p) return hipErrorOutOfMemory;
+            bytes = b;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(&p, b);
         if (e == hipSuccess) bytes = b;
         return e;
@@ -166,10 +188,21 @@ struct bsgd_geometry {
     std::vector<float4> raydir, raynorm, raytrap;
     std::vector<float2> rayv;
     std::vector<float> kspan;
+    std::vector<double> im_area;  // projected area of block j on sub-detector s of view v
     DevBuf d_cs, d_pairs, d_blocks, d_q, d_all_views, d_views, d_raydir, d_rayv, d_raynorm, d_raytrap, d_kspan;
     DevBuf d_cov_off, d_cov_idx;
     Staging stage;
     DevGeom dg{};
+    bsgd_allocator alloc_copy{};
+    const bsgd_allocator* alloc = nullptr;  // &alloc_copy when the descriptor gave one
+    hipStream_t st = nullptr;               // stream the tables were allocated on
+    void bind(DevBuf& b) const { b.use(alloc, st); }
+    void bind_all()
+    {
+        for (DevBuf* b : {&d_cs, &d_pairs, &d_blocks, &d_q, &d_all_views, &d_views, &d_raydir, &d_rayv, &d_raynorm,
+                          &d_raytrap, &d_kspan, &d_cov_off, &d_cov_idx})
+            bind(*b);
+    }
 };
 
 static bsgd_status validate(const bsgd_geometry_desc* d)
@@ -200,8 +233,11 @@ static bsgd_status validate(const bsgd_geometry_desc* d)
         return fail(BSGD_E_INVALID_ARG, "n_row_blocks must be in [1, n_views]");
     if (d->su < 1 || d->sv < 1 || d->su > d->nu || d->sv > d->nv || d->su * d->sv > 16)
         return fail(BSGD_E_INVALID_ARG, "sub-detectors: 1 <= su <= nu, 1 <= sv <= nv, su sv <= 16");
-    if (d->im_mode != BSGD_IM_NONE && d->im_mode != BSGD_IM_COLNORM && d->im_mode != BSGD_IM_UNIFORM)
-        return fail(d->im_mode == 2 ? BSGD_E_UNSUPPORTED : BSGD_E_INVALID_ARG, "unsupported im_mode %d", d->im_mode);
+    if (d->im_mode != BSGD_IM_NONE && d->im_mode != BSGD_IM_COLNORM && d->im_mode != BSGD_IM_AREA &&
+        d->im_mode != BSGD_IM_UNIFORM)
+        return fail(BSGD_E_INVALID_ARG, "unknown im_mode %d", d->im_mode);
+    if (d->allocator && (!d->allocator->alloc || !d->allocator->free))
+        return fail(BSGD_E_INVALID_ARG, "an allocator needs both alloc and free");
     if (d->kind != BSGD_PARALLEL_2D) {
         if (!(d->sod > 0 && d->sdd > d->sod) || !std::isfinite(d->sdd))
             return fail(BSGD_E_INVALID_ARG, "need 0 < sod < sdd");
@@ -565,10 +601,125 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     return upload_cover_index(g, st);
 }
 
+// ------------------------------------------------------------ projected-area weights
+
+namespace {
+struct P2 {
+    double x, y;
+};
+
+double cross3(const P2& o, const P2& a, const P2& b) { return (a.x - o.x) * (b.y - o.y) - (a.y - o.y) * (b.x - o.x); }
+
+// Convex hull (counter-clockwise, Andrew's monotone chain) of a few points.
+std::vector<P2> hull(std::vector<P2> pts)
+{
+    std::sort(pts.begin(), pts.end(), [](const P2& a, const P2& b) { return a.x < b.x || (a.x == b.x && a.y < b.y); });
+    std::vector<P2> h(2 * pts.size());
+    size_t k = 0;
+    for (size_t i = 0; i < pts.size(); ++i) {
+        while (k >= 2 && cross3(h[k - 2], h[k - 1], pts[i]) <= 0) --k;
+        h[k++] = pts[i];
+    }
+    for (size_t i = pts.size() - 1, t = k + 1; i-- > 0;) {
+        while (k >= t && cross3(h[k - 2], h[k - 1], pts[i]) <= 0) --k;
+        h[k++] = pts[i];
+    }
+    h.resize(k > 1 ? k - 1 : k);
+    return h;
+}
+
+// Polygon clipped to the half-plane sgn * (coordinate axis) <= sgn * c (Sutherland-Hodgman).
+std::vector<P2> clip(const std::vector<P2>& poly, int axis, double c, double sgn)
+{
+    std::vector<P2> out;
+    const size_t n = poly.size();
+    auto val = [&](const P2& p) { return sgn * ((axis == 0 ? p.x : p.y) - c); };
+    for (size_t i = 0; i < n; ++i) {
+        const P2& a = poly[i];
+        const P2& b = poly[(i + 1) % n];
+        const double va = val(a), vb = val(b);
+        if (va <= 0) out.push_back(a);
+        if ((va < 0 && vb > 0) || (va > 0 && vb < 0)) {
+            const double t = va / (va - vb);
+            out.push_back({a.x + t * (b.x - a.x), a.y + t * (b.y - a.y)});
+        }
+    }
+    return out;
+}
+
+double area(const std::vector<P2>& poly)
+{
+    double a = 0.0;
+    for (size_t i = 0; i < poly.size(); ++i) {
+        const P2& p = poly[i];
+        const P2& q = poly[(i + 1) % poly.size()];
+        a += p.x * q.y - q.x * p.y;
+    }
+    return 0.5 * std::fabs(a);
+}
+}  // namespace
+
+// im_area[v][s][j]: area, in detector pixels (pixel k spans [k - 1/2, k + 1/2]), of the
+// part of column block j's projection in view v that falls on sub-detector s. The
+// projection of a box is the convex hull of its corners' projections; in 2D the hull
+// is an interval and the area its length. FP64.
+static void projected_areas(bsgd_geometry* g)
+{
+    const bsgd_geometry_desc& d = g->d;
+    const bool is3d = d.kind == BSGD_CONE_FLAT_3D, par = d.kind == BSGD_PARALLEL_2D;
+    const double ku = 0.5 * (d.nu - 1), lv = 0.5 * (d.nv - 1);
+    const double lox = -0.5 * d.nx * d.vx, loy = -0.5 * d.ny * d.vy, loz = -0.5 * d.nz * d.vz;
+    g->im_area.assign((size_t)d.n_views * g->S * g->N, 0.0);
+    for (int v = 0; v < d.n_views; ++v) {
+        const double c = std::cos(d.angles_rad[v]), s = std::sin(d.angles_rad[v]);
+        for (int j = 0; j < g->N; ++j) {
+            const BlockInfo& B = g->blocks[j];
+            std::vector<P2> pts;
+            for (int q = 0; q < (is3d ? 8 : 4); ++q) {
+                const double X = lox + ((q & 1) ? B.x0 + B.nbx : B.x0) * d.vx;
+                const double Y = loy + ((q & 2) ? B.y0 + B.nby : B.y0) * d.vy;
+                const double Z = loz + ((q & 4) ? B.z0 + B.nbz : B.z0) * d.vz;
+                const double w = -X * s + Y * c;
+                if (par) {
+                    pts.push_back({w / d.du + ku, 0.0});
+                } else {
+                    const double dep = d.sod - (X * c + Y * s);
+                    pts.push_back({d.sdd * w / dep / d.du + ku, is3d ? d.sdd * Z / dep / d.dv + lv : 0.0});
+                }
+            }
+            if (!is3d) {
+                double a = INFINITY, b = -INFINITY;
+                for (const P2& p : pts) {
+                    a = std::min(a, p.x);
+                    b = std::max(b, p.x);
+                }
+                for (int sd = 0; sd < g->S; ++sd) {
+                    const double s0 = (double)((sd * d.nu) / d.su) - 0.5, s1 = (double)(((sd + 1) * d.nu) / d.su) - 0.5;
+                    g->im_area[((size_t)v * g->S + sd) * g->N + j] = std::max(0.0, std::min(b, s1) - std::max(a, s0));
+                }
+                continue;
+            }
+            const std::vector<P2> h = hull(pts);
+            for (int sd = 0; sd < g->S; ++sd) {
+                const int a = sd % d.su, b = sd / d.su;
+                const double k0 = (double)((a * d.nu) / d.su) - 0.5, k1 = (double)(((a + 1) * d.nu) / d.su) - 0.5;
+                const double l0 = (double)((b * d.nv) / d.sv) - 0.5, l1 = (double)(((b + 1) * d.nv) / d.sv) - 0.5;
+                std::vector<P2> poly = clip(h, 0, k0, -1.0);
+                poly = clip(poly, 0, k1, 1.0);
+                poly = clip(poly, 1, l0, -1.0);
+                poly = clip(poly, 1, l1, 1.0);
+                g->im_area[((size_t)v * g->S + sd) * g->N + j] = poly.size() >= 3 ? area(poly) : 0.0;
+            }
+        }
+    }
+}
+
 static bsgd_status compute_im(bsgd_geometry* g, hipStream_t st)
 {
     const size_t n = (size_t)g->d.n_views * g->S * g->N;
     DevBuf dw, dn;
+    g->bind(dw);
+    g->bind(dn);
     HIP_TRY(dw.alloc(n * sizeof(double)));
     HIP_TRY(dn.alloc(n * sizeof(int64_t)));
     HIP_TRY(launch_geom_stats(g->dg, dw.as<double>(), dn.as<int64_t>(), st));
@@ -587,14 +738,16 @@ static bsgd_status compute_im(bsgd_geometry* g, hipStream_t st)
     } else if (d.im_mode == BSGD_IM_UNIFORM) {
         std::fill(g->im_q.begin(), g->im_q.end(), 1u);
     } else {
-        // q = round(2^20 w / sum_s w), at least 1 where w > 0
+        // q = round(2^20 w / sum_s w), at least 1 where w > 0; w = the block column norm
+        // (COLNORM) or the projected area (AREA)
+        const std::vector<double>& W = d.im_mode == BSGD_IM_AREA ? g->im_area : g->im_w;
         for (int v = 0; v < d.n_views; ++v)
             for (int j = 0; j < g->N; ++j) {
                 double tot = 0.0;
-                for (int s = 0; s < g->S; ++s) tot += g->im_w[((size_t)v * g->S + s) * g->N + j];
+                for (int s = 0; s < g->S; ++s) tot += W[((size_t)v * g->S + s) * g->N + j];
                 for (int s = 0; s < g->S; ++s) {
                     const size_t o = ((size_t)v * g->S + s) * g->N + j;
-                    const double w = g->im_w[o];
+                    const double w = W[o];
                     uint32_t q = 0;
                     if (tot > 0.0) q = (uint32_t)std::floor(w / tot * (double)(1u << 20) + 0.5);
                     if (w > 0.0 && q == 0) q = 1;
@@ -621,8 +774,16 @@ extern "C" bsgd_status bsgd_geometry_create(const bsgd_geometry_desc* desc, void
     g->d.angles_rad = g->angles.data();
     g->d.im_table = nullptr;
     hipStream_t st = (hipStream_t)stream;
+    if (desc->allocator) {
+        g->alloc_copy = *desc->allocator;
+        g->alloc = &g->alloc_copy;
+    }
+    g->d.allocator = g->alloc;
+    g->st = st;
+    g->bind_all();
     try {
         build_tables(g);
+        projected_areas(g);
     } catch (...) {
         delete g;
         return fail(BSGD_E_OUT_OF_MEMORY, "host allocation failed while building tables");
@@ -683,6 +844,10 @@ extern "C" bsgd_status bsgd_geometry_table(const bsgd_geometry* g, int32_t which
     case BSGD_TABLE_NNZ:
         src = g->im_nnz.data();
         need = g->im_nnz.size() * sizeof(int64_t);
+        break;
+    case BSGD_TABLE_IM_AREA:
+        src = g->im_area.data();
+        need = g->im_area.size() * sizeof(double);
         break;
     case BSGD_TABLE_FOOTPRINT:
         rects.resize(g->pairs.size() * 4);
@@ -792,6 +957,8 @@ extern "C" bsgd_status bsgd_back_project(const bsgd_geometry* gc, const float* y
 
 enum { KID_FP = 0, KID_RESID = 1, KID_BP = 2, KID_TV = 3, KID_DRAW = 4, KID_COUNT = 5 };
 
+static void drop_batch_graphs(const bsgd_solver* s);
+
 struct bsgd_solver {
     const bsgd_geometry* g = nullptr;
     const float* y = nullptr;
@@ -818,6 +985,8 @@ struct bsgd_solver {
     DevBuf tv_w;             // {w = mu lambda, dual step} of the TV prox, on the device
     float* tv_w_host = nullptr;
     DevBuf nr_ty, nr_tg;   // normal-residual scratch (bsgd_normal_residual)
+    DevBuf nr_out;         // {||A^T (y - A x)||^2, ||A^T y||^2} of the last asynchronous check
+    bool nr_ref_dev = false;  // nr_out[1] holds ||A^T y||^2
     double nr_ref = -1.0;  // ||A^T y||, once computed
     float* mu_host = nullptr;
     double mu_cur = 0.0;
@@ -839,6 +1008,7 @@ struct bsgd_solver {
     ~bsgd_solver()
     {
         if (st) (void)hipStreamSynchronize(st);
+        drop_batch_graphs(this);
         for (auto& p : pending) {
             ev_pool.push_back(p.second.first);
             ev_pool.push_back(p.second.second);
@@ -939,6 +1109,10 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     s->L.stride = SchedLayout::stride_for(R, B, s->maxv);
     s->graphs = (o->flags & BSGD_FLAG_EAGER) == 0;
     s->subdet = (o->flags & BSGD_FLAG_SUBDET_MEMORY) != 0;
+    for (DevBuf* b : {&s->z, &s->ghat, &s->gsum, &s->r_sel, &s->sched, &s->draws, &s->work, &s->partials, &s->norm_out,
+                      &s->tv_p, &s->tv_a, &s->tv_b, &s->rho, &s->delta, &s->g_sched, &s->g_work, &s->g_draws,
+                      &s->mu_dev, &s->eud_cur, &s->eud_prev, &s->tv_w, &s->nr_ty, &s->nr_tg, &s->nr_out})
+        b->use(g->alloc, st);
     const int64_t per_view = (int64_t)g->d.nu * g->d.nv;
     auto cleanup = [&](bsgd_status e) {
         delete s;
@@ -1273,11 +1447,9 @@ extern "C" bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_
     return BSGD_OK;
 }
 
-// Schedule, upload and plan n_iters iterations of one solver on stream st (no kernels
-// of the iteration itself).
-static bsgd_status prepare_iterations(bsgd_solver* s, int n_iters, hipStream_t st)
+// Schedule and upload n_iters iterations of one solver on stream st (no kernels).
+static bsgd_status upload_iterations(bsgd_solver* s, int n_iters, hipStream_t st)
 {
-    const bsgd_geometry* g = s->g;
     bsgd_status stt = ensure_sched(s, n_iters);
     if (stt != BSGD_OK) return stt;
     const size_t sched_bytes = (size_t)n_iters * s->L.stride * sizeof(int32_t);
@@ -1287,55 +1459,38 @@ static bsgd_status prepare_iterations(bsgd_solver* s, int n_iters, hipStream_t s
     s->last_sched.assign(host, host + (size_t)n_iters * s->L.stride);
     s->last_n = n_iters;
     HIP_TRY(s->stage.upload(s->sched.p, sched_bytes, st));
-    HIP_TRY(launch_plan(g->dg, s->sched.as<int32_t>(), s->L, n_iters, s->o.seed,
-                        s->im ? g->d_q.as<uint32_t>() : nullptr, (int64_t)s->o.im_until, s->im ? s->draws.as<int8_t>() : nullptr,
-                        s->work.as<PairWork>(), st));
     return BSGD_OK;
 }
 
-extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, int32_t n_iters, void* stream)
+// The plan (draws and work records) of n_iters uploaded iterations.
+static hipError_t plan_iterations(bsgd_solver* s, int n_iters, hipStream_t st)
 {
-    if (!solvers || n < 1 || n > 65536) return fail(BSGD_E_INVALID_ARG, "need 1 <= n <= 65536 solvers");
-    if (n_iters < 0 || n_iters > (1 << 20)) return fail(BSGD_E_INVALID_ARG, "n_iters must be in [0, 2^20]");
-    hipStream_t st = (hipStream_t)stream;
-    const int dim = solvers[0] ? solvers[0]->g->dim : 0;
-    for (int i = 0; i < n; ++i) {
-        bsgd_solver* s = solvers[i];
-        if (!s) return fail(BSGD_E_INVALID_ARG, "solver %d is NULL", i);
-        if (s->failed) return fail(BSGD_E_STATE, "solver %d is in a failed state", i);
-        if (s->st != st) return fail(BSGD_E_INVALID_ARG, "solver %d was created on another stream", i);
-        if (s->g->dim != dim) return fail(BSGD_E_INVALID_ARG, "a batch mixes 2D and 3D solves");
-        if (s->auto_mu) return fail(BSGD_E_UNSUPPORTED, "solver %d tunes its step length; step it alone", i);
-        if (s->subdet) return fail(BSGD_E_UNSUPPORTED, "solver %d keeps sub-detector memories; step it alone", i);
-        for (int j = 0; j < i; ++j)
-            if (solvers[j] == s) return fail(BSGD_E_INVALID_ARG, "solver %d appears twice", i);
-    }
-    if (n_iters == 0) return BSGD_OK;
-    auto mark_failed = [&](bsgd_status e) {
-        for (int i = 0; i < n; ++i) solvers[i]->failed = true;
-        return e;
-    };
-    for (int i = 0; i < n; ++i) {
-        bsgd_status stt = prepare_iterations(solvers[i], n_iters, st);
-        if (stt != BSGD_OK) return mark_failed(stt);
-    }
-    // launch groups of up to BATCH_GROUP entries (passed as kernel arguments), each
-    // with the LDS-staged forward projections first, sorted by LDS size (the order of
-    // the entries does not affect any solve's arithmetic)
+    const bsgd_geometry* g = s->g;
+    return launch_plan(g->dg, s->sched.as<int32_t>(), s->L, n_iters, s->o.seed,
+                       s->im ? g->d_q.as<uint32_t>() : nullptr, (int64_t)s->o.im_until,
+                       s->im ? s->draws.as<int8_t>() : nullptr, s->work.as<PairWork>(), st);
+}
+
+// Launch groups of a batched call: up to BATCH_GROUP entries each (passed as kernel
+// arguments), the LDS-staged forward projections first, sorted by LDS size (the order
+// of the entries does not affect any solve's arithmetic).
+struct BatchLaunchGroup {
+    BatchArgs A;
+    int wgs[3];
+    std::vector<FpLaunchClass> classes;
+    size_t res_lds;
+};
+
+static std::vector<BatchLaunchGroup> batch_groups(bsgd_solver* const* solvers, int n)
+{
     std::vector<bsgd_solver*> order(solvers, solvers + n);
     std::stable_sort(order.begin(), order.end(), [](const bsgd_solver* a, const bsgd_solver* b) {
         return fp_lds_bytes_for(a->g->dg) > fp_lds_bytes_for(b->g->dg);
     });
-    struct Group {
-        BatchArgs A;
-        int wgs[3];
-        std::vector<FpLaunchClass> classes;
-        size_t res_lds;
-    };
-    std::vector<Group> groups;
+    std::vector<BatchLaunchGroup> groups;
     for (int g0 = 0; g0 < n; g0 += BATCH_GROUP) {
         groups.emplace_back();
-        Group& grp = groups.back();
+        BatchLaunchGroup& grp = groups.back();
         std::memset(&grp.A, 0, sizeof grp.A);
         grp.wgs[0] = grp.wgs[1] = grp.wgs[2] = 0;
         grp.res_lds = 0;
@@ -1369,23 +1524,194 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         }
         grp.A.n = m;
     }
+    return groups;
+}
+
+// The iterations of a batched call (after their plans): per iteration one launch per
+// phase and group, then the TV steps due (k0 = the solvers' common counter before the
+// call when `aligned`, else each solver's own).
+static hipError_t enqueue_batch(std::vector<BatchLaunchGroup>& groups, bsgd_solver* const* solvers, int n,
+                                int n_iters, int dim, hipStream_t st)
+{
     for (int it = 0; it < n_iters; ++it) {
-        for (Group& grp : groups) {
+        for (BatchLaunchGroup& grp : groups) {
             grp.A.it = it;
             hipError_t he = launch_batch_iteration(grp.A, dim, grp.wgs, grp.classes.data(), (int)grp.classes.size(),
                                                    grp.res_lds, st);
-            if (he != hipSuccess)
-                return mark_failed(fail(BSGD_E_DEVICE, "batched launch: %s", hipGetErrorString(he)));
+            if (he != hipSuccess) return he;
         }
         for (int i = 0; i < n; ++i) {
             bsgd_solver* s = solvers[i];
             if (s->o.tv_lambda > 0 && s->mu_cur > 0 && (s->k + it + 1) % s->tv_every == 0) {
                 hipError_t he = launch_tv_prox(s->g->dg, s->x, s->tv_w.as<float>(), s->o.tv_inner_iters,
                                                s->tv_p.as<float>(), s->tv_a.as<float>(), s->tv_b.as<float>(), st);
-                if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "tv: %s", hipGetErrorString(he)));
+                if (he != hipSuccess) return he;
             }
         }
     }
+    return hipSuccess;
+}
+
+// Captured batched epochs: one graph per ordered set of solvers (one effective epoch from
+// an epoch boundary, plans included), replayed while the set recurs. A set is captured
+// the second time in a row it is stepped; a few graphs are kept, and a solver's
+// destruction drops the graphs that hold it.
+namespace {
+struct BatchGraph {
+    std::vector<bsgd_solver*> key;
+    std::vector<const void*> bufs;  // buffers baked into the graph, per solver: sched, work, draws
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchGraph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+constexpr size_t BATCH_GRAPHS_KEPT = 16;
+std::mutex g_bg_mu;
+std::vector<std::unique_ptr<BatchGraph>> g_bg;  // most recently used last
+std::vector<bsgd_solver*> g_bg_last;            // the set of the previous graph-eligible call
+}  // namespace
+
+static std::vector<const void*> batch_bufs(bsgd_solver* const* solvers, int n)
+{
+    std::vector<const void*> b;
+    for (int i = 0; i < n; ++i) {
+        b.push_back(solvers[i]->sched.p);
+        b.push_back(solvers[i]->work.p);
+        b.push_back(solvers[i]->draws.p);
+    }
+    return b;
+}
+
+static void drop_batch_graphs(const bsgd_solver* s)
+{
+    std::lock_guard<std::mutex> lock(g_bg_mu);
+    for (size_t i = 0; i < g_bg.size();) {
+        if (std::find(g_bg[i]->key.begin(), g_bg[i]->key.end(), s) != g_bg[i]->key.end())
+            g_bg.erase(g_bg.begin() + i);
+        else
+            ++i;
+    }
+    if (std::find(g_bg_last.begin(), g_bg_last.end(), s) != g_bg_last.end()) g_bg_last.clear();
+}
+
+static bsgd_status capture_batch_graph(bsgd_solver* const* solvers, int n, int dim, std::unique_ptr<BatchGraph>& out)
+{
+    auto bg = std::make_unique<BatchGraph>();
+    bg->key.assign(solvers, solvers + n);
+    bg->bufs = batch_bufs(solvers, n);
+    const int T = solvers[0]->T;
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    std::vector<BatchLaunchGroup> groups = batch_groups(solvers, n);
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int i = 0; i < n && e == hipSuccess; ++i) e = plan_iterations(solvers[i], T, cap);
+        if (e == hipSuccess) e = enqueue_batch(groups, solvers, n, T, dim, cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e2;
+        bg->graph = graph;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&bg->exec, bg->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(BSGD_E_DEVICE, "batched graph capture: %s", hipGetErrorString(e));
+    out = std::move(bg);
+    return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, int32_t n_iters, void* stream)
+{
+    if (!solvers || n < 1 || n > 65536) return fail(BSGD_E_INVALID_ARG, "need 1 <= n <= 65536 solvers");
+    if (n_iters < 0 || n_iters > (1 << 20)) return fail(BSGD_E_INVALID_ARG, "n_iters must be in [0, 2^20]");
+    hipStream_t st = (hipStream_t)stream;
+    const int dim = solvers[0] ? solvers[0]->g->dim : 0;
+    for (int i = 0; i < n; ++i) {
+        bsgd_solver* s = solvers[i];
+        if (!s) return fail(BSGD_E_INVALID_ARG, "solver %d is NULL", i);
+        if (s->failed) return fail(BSGD_E_STATE, "solver %d is in a failed state", i);
+        if (s->st != st) return fail(BSGD_E_INVALID_ARG, "solver %d was created on another stream", i);
+        if (s->g->dim != dim) return fail(BSGD_E_INVALID_ARG, "a batch mixes 2D and 3D solves");
+        if (s->auto_mu) return fail(BSGD_E_UNSUPPORTED, "solver %d tunes its step length; step it alone", i);
+        if (s->subdet) return fail(BSGD_E_UNSUPPORTED, "solver %d keeps sub-detector memories; step it alone", i);
+        for (int j = 0; j < i; ++j)
+            if (solvers[j] == s) return fail(BSGD_E_INVALID_ARG, "solver %d appears twice", i);
+    }
+    if (n_iters == 0) return BSGD_OK;
+    auto mark_failed = [&](bsgd_status e) {
+        for (int i = 0; i < n; ++i) solvers[i]->failed = true;
+        return e;
+    };
+    // one effective epoch from an epoch boundary of every solver, graphs allowed: replay
+    // (or capture) the set's graph
+    bool graph_ok = true;
+    const int T = solvers[0]->T;
+    for (int i = 0; i < n && graph_ok; ++i) {
+        const bsgd_solver* s = solvers[i];
+        graph_ok = s->graphs && !s->prof && s->T == T && n_iters == T && s->k % T == 0 &&
+                   (!(s->o.tv_lambda > 0) || T % s->tv_every == 0);
+    }
+    if (graph_ok) {
+        // buffers first (a reallocation would invalidate a captured graph)
+        for (int i = 0; i < n; ++i) {
+            bsgd_status stt = ensure_sched(solvers[i], T);
+            if (stt != BSGD_OK) return mark_failed(stt);
+        }
+        const std::vector<bsgd_solver*> key(solvers, solvers + n);
+        BatchGraph* bg = nullptr;
+        bool capture = false;
+        {
+            std::lock_guard<std::mutex> lock(g_bg_mu);
+            for (size_t i = 0; i < g_bg.size(); ++i)
+                if (g_bg[i]->key == key) {
+                    if (g_bg[i]->bufs != batch_bufs(solvers, n)) {
+                        g_bg.erase(g_bg.begin() + i);  // a buffer moved since the capture
+                        break;
+                    }
+                    std::unique_ptr<BatchGraph> hit = std::move(g_bg[i]);
+                    g_bg.erase(g_bg.begin() + i);
+                    g_bg.push_back(std::move(hit));
+                    bg = g_bg.back().get();
+                    break;
+                }
+            if (!bg) {
+                capture = g_bg_last == key;
+                g_bg_last = key;
+            }
+        }
+        if (bg || capture) {
+            for (int i = 0; i < n; ++i) {
+                bsgd_status stt = upload_iterations(solvers[i], T, st);
+                if (stt != BSGD_OK) return mark_failed(stt);
+            }
+            if (!bg) {
+                std::unique_ptr<BatchGraph> fresh;
+                bsgd_status stt = capture_batch_graph(solvers, n, dim, fresh);
+                if (stt != BSGD_OK) return mark_failed(stt);
+                std::lock_guard<std::mutex> lock(g_bg_mu);
+                if (g_bg.size() >= BATCH_GRAPHS_KEPT) g_bg.erase(g_bg.begin());
+                g_bg.push_back(std::move(fresh));
+                bg = g_bg.back().get();
+            }
+            hipError_t he = hipGraphLaunch(bg->exec, st);
+            if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batched graph launch: %s", hipGetErrorString(he)));
+            for (int i = 0; i < n; ++i) solvers[i]->k += n_iters;
+            return BSGD_OK;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        bsgd_status stt = upload_iterations(solvers[i], n_iters, st);
+        if (stt == BSGD_OK) {
+            hipError_t he = plan_iterations(solvers[i], n_iters, st);
+            if (he != hipSuccess) stt = fail(BSGD_E_DEVICE, "plan: %s", hipGetErrorString(he));
+        }
+        if (stt != BSGD_OK) return mark_failed(stt);
+    }
+    std::vector<BatchLaunchGroup> groups = batch_groups(solvers, n);
+    hipError_t he = enqueue_batch(groups, solvers, n, n_iters, dim, st);
+    if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batched launch: %s", hipGetErrorString(he)));
     for (int i = 0; i < n; ++i) solvers[i]->k += n_iters;
     return BSGD_OK;
 }
@@ -1544,6 +1870,46 @@ extern "C" bsgd_status bsgd_normal_residual(bsgd_solver* const* solvers, int32_t
     return BSGD_OK;
 }
 
+extern "C" bsgd_status bsgd_normal_residual_async(bsgd_solver* const* solvers, int32_t n, double* out_sq,
+                                                  void* stream)
+{
+    if (!solvers || !out_sq || n < 1 || n > 65536) return fail(BSGD_E_INVALID_ARG, "need 1 <= n <= 65536 solvers and out_sq");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        if (!solvers[i]) return fail(BSGD_E_INVALID_ARG, "solver %d is NULL", i);
+        if (solvers[i]->st != st) return fail(BSGD_E_INVALID_ARG, "solver %d was created on another stream", i);
+    }
+    for (int i = 0; i < n; ++i) {
+        bsgd_solver* s = solvers[i];
+        const bsgd_geometry* g = s->g;
+        if (!s->nr_ty.p) {
+            HIP_TRY(s->nr_ty.alloc((size_t)g->n_rays * sizeof(float)));
+            HIP_TRY(s->nr_tg.alloc((size_t)g->n_vox * sizeof(float)));
+        }
+        if (!s->nr_out.p) HIP_TRY(s->nr_out.alloc(2 * sizeof(double)));
+        double* dout = s->nr_out.as<double>();
+        double* part = s->partials.as<double>();
+        float* ty = s->nr_ty.as<float>();
+        float* tg = s->nr_tg.as<float>();
+        const int32_t* views = g->d_all_views.as<int32_t>();
+        int np = 0;
+        if (!s->nr_ref_dev) {
+            HIP_TRY(launch_fill(tg, 0.0f, g->n_vox, st));
+            HIP_TRY(launch_bp_full(g->dg, views, g->d.n_views, -1, s->y, tg, 1.0f, 0, st));
+            HIP_TRY(launch_sumsq(tg, g->n_vox, part, &np, st));
+            HIP_TRY(launch_sum_partials(part, np, dout + 1, st));
+            s->nr_ref_dev = true;
+        }
+        HIP_TRY(launch_fp_full(g->dg, views, g->d.n_views, -1, s->x, ty, 0, st));
+        HIP_TRY(launch_sub(s->y, ty, ty, g->n_rays, st));
+        HIP_TRY(launch_bp_full(g->dg, views, g->d.n_views, -1, ty, tg, 1.0f, 0, st));
+        HIP_TRY(launch_sumsq(tg, g->n_vox, part, &np, st));
+        HIP_TRY(launch_sum_partials(part, np, dout, st));
+        HIP_TRY(hipMemcpyAsync(out_sq + 2 * i, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    return BSGD_OK;
+}
+
 extern "C" bsgd_status bsgd_solve(const bsgd_geometry* g, const float* y, float* x, const bsgd_options* o, void* stream,
                                   int32_t* iters_out, double* resid_norm_out)
 {
@@ -1554,6 +1920,8 @@ extern "C" bsgd_status bsgd_solve(const bsgd_geometry* g, const float* y, float*
     const int epochs = o->max_effective_epochs > 0 ? o->max_effective_epochs : 1;
     const int check = o->check_every > 0 ? o->check_every : 1;
     DevBuf ty, tg;
+    g->bind(ty);
+    g->bind(tg);
     double ref = 0.0;
     if (o->tol > 0) {
         if (ty.alloc((size_t)g->n_rays * sizeof(float)) != hipSuccess ||

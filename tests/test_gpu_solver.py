@@ -273,6 +273,52 @@ def test_graph_replay_matches_eager(name, im, tv):
     assert torch.equal(xg, xe)
 
 
+def test_batched_graphs_equal_solo_solves():
+    """Whole-epoch batched calls of a recurring set of solves are captured once and
+    replayed as HIP graphs; every replay equals the solves run alone, bit for bit, with
+    unrelated device work and synchronisations between replays, and a new subset gets
+    its own graph."""
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver, step_batch
+    dev = require_gpu()
+    log("batched graphs vs solo")
+    g = SMALL["fan"]
+    A, x_true, y64, y32 = _data(g, 41)
+    mu = _mu(A, 0.3)
+    p = oracle_problem(g)
+    geoms = {"none": Geometry(g), "colnorm": Geometry(g.with_(im_mode="colnorm"), im_table=im_table(p, "colnorm"))}
+    yd = torch.tensor(y32, device=dev)
+    cfg = [("none", 1, 3, 41), ("none", 3, 1, 42), ("colnorm", 1, 3, 43)]  # every one 15 iterations per epoch
+    bat, solo = [], []
+    for im, R, B, seed in cfg:
+        pair = []
+        for eager in (False, True):
+            x = torch.zeros(A.shape[1], device=dev)
+            pair.append((x, Solver(geoms[im], yd, x, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=seed,
+                                   eager=eager)))
+        bat.append(pair[0])
+        solo.append(pair[1])
+    T = bat[0][1].epoch_iters
+    assert all(b[1].epoch_iters == T for b in bat)
+    sets = [[0, 1, 2]] * 4 + [[0, 2]] * 3 + [[0, 1, 2]]
+    for rep, idx in enumerate(sets):
+        step_batch([bat[i][1] for i in idx], T)
+        for i in idx:
+            solo[i][1].step(T)
+        junk = geoms["none"].forward_project(bat[1][0])  # unrelated work between replays
+        torch.cuda.synchronize()
+        assert float(junk.sum()) == float(junk.sum())
+        for i in range(3):
+            assert torch.equal(bat[i][0], solo[i][0]), (rep, i)
+            assert bat[i][1].iterations == solo[i][1].iterations
+    rb, bb, db = bat[2][1].last_schedule()
+    rs, bs, ds_ = solo[2][1].last_schedule()
+    assert np.array_equal(rb, rs) and np.array_equal(bb, bs) and np.array_equal(db, ds_)
+    # the first solve against the oracle's run of the same iterations
+    st = run(p, y64, mu, 1, 3, bat[0][1].iterations, 41)
+    assert rel_l2(bat[0][0].double().cpu().numpy(), st.x) <= TOL
+
+
 def test_batched_solves_equal_solo_solves():
     """Several solves of different geometries in shared launches give bit-identical
     iterates to the same solves run alone."""

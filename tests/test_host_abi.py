@@ -37,11 +37,12 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header():
     import subprocess
     import tempfile
-    from paper_1903_11874_amd.bsgd import GeometryDesc, Options, GeometryInfo, Tuning
-    src = '#include "%s"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu", ' \
+    from paper_1903_11874_amd.bsgd import Allocator, GeometryDesc, Options, GeometryInfo, Tuning
+    src = '#include "%s"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu", ' \
           'sizeof(bsgd_geometry_desc), sizeof(bsgd_options), sizeof(bsgd_geometry_info), ' \
           'offsetof(bsgd_geometry_desc, im_table), offsetof(bsgd_options, tol), sizeof(bsgd_tuning), ' \
-          'offsetof(bsgd_tuning, fp_ray_split));return 0;}\n' % HEADER
+          'offsetof(bsgd_tuning, fp_ray_split), offsetof(bsgd_geometry_desc, allocator), sizeof(bsgd_allocator));' \
+          'return 0;}\n' % HEADER
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -49,7 +50,8 @@ def test_struct_layouts_match_header():
         out = subprocess.check_output([os.path.join(d, "s")]).decode().split()
     assert [int(v) for v in out] == [ctypes.sizeof(GeometryDesc), ctypes.sizeof(Options),
                                       ctypes.sizeof(GeometryInfo), GeometryDesc.im_table.offset,
-                                      Options.tol.offset, ctypes.sizeof(Tuning), Tuning.fp_ray_split.offset]
+                                      Options.tol.offset, ctypes.sizeof(Tuning), Tuning.fp_ray_split.offset,
+                                      GeometryDesc.allocator.offset, ctypes.sizeof(Allocator)]
 
 
 def _desc(**kw):
@@ -78,10 +80,16 @@ def test_invalid_descriptors_are_rejected(lib, bad):
     assert lib.bsgd_last_error()
 
 
-def test_area_mode_is_reported_unsupported(lib):
-    d, keep = _desc(im_mode=2)
-    out = ctypes.c_void_p()
-    assert lib.bsgd_geometry_create(ctypes.byref(d), None, ctypes.byref(out)) == 2
+def test_allocator_without_free_is_rejected(lib):
+    from paper_1903_11874_amd.bsgd import ALLOC_FN, Allocator
+    d, keep = _desc()
+    a = Allocator()  # free stays NULL
+    fn = ALLOC_FN(lambda ctx, n, s: None)
+    a.alloc = fn
+    d.allocator = ctypes.pointer(a)
+    out = ctypes.c_void_p(123)
+    assert lib.bsgd_geometry_create(ctypes.byref(d), None, ctypes.byref(out)) == 1
+    assert out.value is None
 
 
 def test_null_arguments(lib):
