@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the BSGD hot path on one MI355X.
 
-Workload: 2D fan beam 512x512 (0.5 mm), 720 views over 360 deg, 768 bins (1 mm),
-SOD 500 mm, SDD 1000 mm, 8x8 image blocks, 16 angle subsets, importance sampling
-by block column norms over 4 sub-detectors (BSGD-IM), node count 64 (Eq. 1:
-one row block and all 64 column blocks per iteration). Synthetic seeded data:
-24 random ellipses, Poisson noise at 1e5 incident photons, log transformed.
+Headline workload: 3D cone beam with TV, 256^3 volume (0.5 mm voxels), 360 views over
+360 deg onto a 384x384 detector (1 mm pixels), SOD 600 mm, SDD 1200 mm, 256 column
+blocks (16 axial slabs x 4x4 tiles of 64x64x16), 24 angle subsets, TV weight 1e-3 with
+20 inner iterations, node count 64 (Eq. 1: one row block and 64 column blocks per
+iteration, 96 iterations per effective epoch). Synthetic seeded data: 32 random
+ellipsoids, Gaussian noise at 1% of the maximum.
 
-One step = one effective epoch (16 iterations): forward projection of the sampled
-rays, residual rebuild, matched back projection fused with the block update.
-Throughput = (forward + back projection ray-voxel updates) / s, where an update is
-one nonzero a_ij applied; counts come from the exact per-(view, sub-detector,
-block) nonzero table and the iteration's draws.
+One step = one effective epoch: forward projection of the selected rays, residual
+rebuild, matched back projection fused with the block update, and the TV prox.
+Throughput = (forward + back projection ray-voxel updates) / s, where an update is one
+nonzero a_ij applied; counts come from the exact per-(view, sub-detector, block)
+nonzero table and the iteration's draws.
+
+Also reported: the 2D fan-beam BSGD-IM workload (512^2) as `secondary`; the FP64 oracle
+on the host cores (`cpu_baseline`); the serving mix (512 seeded Poisson requests of 2D
+fan-beam solves, sides 128..1024) at the workload's 20 requests/s and at a saturating
+rate, served with continuous batching against the plain per-solve loop.
 
 Prints one JSON line (rank 0, N = 1).
 """
@@ -31,7 +37,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "c2_fan512_im"
+# VALU issue of the chip: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4
+# cycles (16 lanes per cycle) at 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
 
 
 def log(msg):
@@ -77,10 +87,14 @@ def schedule_counts(geom, spec, rows, blocks, draws, nnz_tab, fp_rect, subdet_w)
     return per_it
 
 
-def profiled_traffic(workload_name, kernel_key):
-    """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy kernel), or None when the kernel
-    or launch sources changed since those counters were taken."""
+KERNEL_NAMES = {"back_project_step": ["k_bp_step"], "forward_project": ["k_fp_pairs_lds", "k_fp_pairs"]}
+
+
+def profiled(workload_name, kernel_key):
+    """The committed rocprofv3 counter runs of a kernel (profiles/traffic.json): HBM bytes
+    per dispatch (FETCH_SIZE and WRITE_SIZE scaled by a plain copy kernel) and wave64
+    VALU instructions per dispatch (SQ_INSTS_VALU); None when the kernel or launch
+    sources changed since those counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -93,8 +107,7 @@ def profiled_traffic(workload_name, kernel_key):
     if hashlib.sha256(src).hexdigest() != t.get("source_sha256"):
         return None
     per = t.get("workloads", {}).get(workload_name, {})
-    names = {"back_project_step": ["k_bp_step"], "forward_project": ["k_fp_pairs_lds", "k_fp_pairs"]}[kernel_key]
-    for n in names:
+    for n in KERNEL_NAMES[kernel_key]:
         if n in per:
             return per[n]
     return None
@@ -154,17 +167,28 @@ def measure(geom, spec, solver, n_vox, warmup, steps, n_prof, workload_name):
     dominant = max(("forward_project", "back_project_step"), key=lambda k: times[k][0])
     alg_bytes = bytes_fp if dominant == "forward_project" else bytes_bp
     achieved = alg_bytes / (avg_ms[dominant] * 1e-3) / 1e9
+    prof = profiled(workload_name, dominant)
+    updates_per_launch = sum(u for u, _, _ in per_it_p) / n_it
+    valu = None
+    if prof and prof.get("valu_insts"):
+        v = prof["valu_insts"]
+        issue_s = v * 4 / SIMDS / CLOCK_HZ
+        valu = {"insts_per_dispatch": v, "lane_slots_per_update": v * 64 / updates_per_launch,
+                "issue_us": issue_s * 1e6, "issue_frac": issue_s / (avg_ms[dominant] * 1e-3),
+                "achieved_lane_ops_per_s": v * 64 / (avg_ms[dominant] * 1e-3), "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK,
+                "source": "rocprofv3 SQ_INSTS_VALU (wave64 instructions per dispatch), profiles/traffic.json"}
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(workload_name, dominant),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("hbm_bytes") if prof else None,
                 "traffic_unit": "bytes per dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms[dominant]}
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms[dominant],
+                "updates_per_launch": updates_per_launch, "valu": valu}
 
-    return {"elapsed": elapsed, "value": value, "updates": updates, "roofline": roofline,
+    return {"elapsed": elapsed, "steps": steps, "value": value, "updates": updates, "roofline": roofline,
             "kernels_avg_ms": avg_ms, "times": times, "r0": r0, "r1": r1, "n_prof": n_prof, "t2": t2, "t3": t3}
 
 
 def cone_bench(steps, warmup, n_prof):
-    """The 3D cone-beam workload with TV (256^3, 360 views of 384^2): same measurement."""
+    """The 3D cone-beam workload with TV (256^3, 360 views of 384^2)."""
     import torch
     from bsgd_inputs.configs import workload
     from bsgd_inputs.phantoms import phantom_for, add_gaussian_noise
@@ -185,69 +209,155 @@ def cone_bench(steps, warmup, n_prof):
     solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed, tv_lambda=wl.solver.tv_lambda,
                     tv_inner_iters=wl.solver.tv_inner_iters)
     m = measure(geom, spec, solver, n_vox, warmup, steps, n_prof, wl.name)
-    T = solver.epoch_iters
-    return {"workload": wl.description, "metric": "FP+BP ray-voxel updates/s", "value": m["value"],
-            "unit": "updates/s", "steps": steps, "ms_per_step": m["elapsed"] / steps * 1e3,
-            "rows_per_iter": solver.rows_per_iter, "blocks_per_iter": solver.blocks_per_iter,
-            "iters_per_step": T, "step": "one effective epoch (TV prox once per epoch)",
-            "roofline": m["roofline"], "kernels_avg_ms": m["kernels_avg_ms"],
-            "kernel_launches": {k: n for k, (ms, n) in m["times"].items()},
-            "residual_norm": {"before": m["r0"], "after": m["r1"]}, "updates_per_step": m["updates"] / steps}
+    m.update(workload=wl.description, spec=spec, rows_per_iter=solver.rows_per_iter,
+             blocks_per_iter=solver.blocks_per_iter, iters_per_step=solver.epoch_iters, nnz=geom.info["nnz"],
+             groups=geom.groups())
+    return m
 
 
-def cpu_baseline(spec, x, budget_s=12.0):
-    """The FP64 oracle's matrix-free FP + BP over every ray, repeated to a bounded time budget."""
+def fan_bench(steps, warmup, n_prof, tune="auto"):
+    """The 2D fan-beam BSGD-IM workload (512^2, 720 views, 768 bins, 4 sub-detectors)."""
+    import torch
+    from bsgd_inputs.configs import workload
+    from bsgd_inputs.phantoms import phantom_for, poisson_log_noise
+    from paper_1903_11874_amd import Geometry, Solver
+    wl = workload("c2_fan512_im")
+    spec = wl.geometry
+    log("fan: geometry")
+    geom = Geometry(spec)
+    n_vox = spec.nx * spec.ny * spec.nz
+    x_true = phantom_for(spec, wl.n_shapes, wl.phantom_seed)
+    xt = torch.tensor(x_true, dtype=torch.float32, device="cuda")
+    y = poisson_log_noise(geom.forward_project(xt).double().cpu().numpy(), wl.noise_level, wl.noise_seed)
+    yd = torch.tensor(y, dtype=torch.float32, device="cuda")
+    L = lipschitz_gpu(geom, n_vox)
+    mu = wl.solver.mu_scale / (2.0 * L)
+    log(f"fan: L = {L:.4e}, mu = {mu:.4e}")
+    if tune == "auto":
+        from paper_1903_11874_amd.tuning import autotune
+        tt = autotune(geom, yd, node_count=64, mu=mu, epochs=2, seed=wl.solver.seed)
+        log("fan: autotune " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in sorted(tt.items(), key=lambda kv: kv[1])[:4]))
+    else:
+        v_, s_ = (int(t) for t in tune.split(","))
+        geom.set_tuning(fp_views_per_group=v_, fp_ray_split=s_)
+    x = torch.zeros(n_vox, dtype=torch.float32, device="cuda")
+    solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed)
+    m = measure(geom, spec, solver, n_vox, warmup, steps, n_prof, wl.name)
+    m.update(workload=wl.description, spec=spec, rows_per_iter=solver.rows_per_iter,
+             blocks_per_iter=solver.blocks_per_iter, iters_per_step=solver.epoch_iters, nnz=geom.info["nnz"],
+             fp_views_per_group=geom.fp_views_per_group, fp_ray_split=geom.fp_ray_split, x_true=x_true,
+             groups=geom.groups())
+    return m
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(spec, rays, threads, budget_s):
+    """FP64 oracle FP + BP over `rays` (all of the volume), repeated to a time budget."""
+    import numpy as np
     from oracle.cfast import Projector
-    threads = max(1, min(16, os.cpu_count() or 1))
-    P = Projector(spec)
+    P = Projector(spec, rays=rays)
+    x = np.random.Generator(np.random.PCG64(7)).uniform(size=spec.nx * spec.ny * spec.nz)
     updates, elapsed, reps = 0, 0.0, 0
-    while elapsed < budget_s and reps < 200:
+    while elapsed < budget_s and reps < 100:
         t0 = time.perf_counter()
-        y = P.fp(x, threads=threads)
-        P.bp(y, threads=threads)
+        yv = P.fp(x, threads=threads)
+        P.bp(yv, threads=threads)
         elapsed += time.perf_counter() - t0
         updates += 2 * P.last_nnz
         reps += 1
-    return {"value": updates / elapsed, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} x (FP + BP over all {spec.n_views} views x {spec.nu} bins, full "
-                      f"{spec.nx}x{spec.ny} image), FP64 matrix-free Siddon, {threads} threads: "
-                      f"{updates:.3e} updates in {elapsed:.2f} s"}
+    return updates / elapsed, updates, elapsed, reps, P.last_nnz
 
 
-def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
-    """Continuous-batching server vs the plain per-solve loop on a seeded Poisson stream
-    of 2D fan-beam solves (sides 128..1024, views = bins = 1.5 side, 1% noise)."""
+def cpu_baseline_cone(spec, groups, nnz_total, budget_s=8.0):
+    """The FP64 oracle's matrix-free FP + BP on the host cores, on a bounded sample of the
+    cone workload: all cores on one row block (its views x every ray x all 256 blocks),
+    one core on one view; extrapolated linearly to an effective epoch (FP + BP of every
+    nonzero of A once)."""
+    import numpy as np
+    per_view = spec.nu * spec.nv
+    views = groups[0]
+    rays = np.concatenate([np.arange(v * per_view, (v + 1) * per_view) for v in views])
+    nproc = os.cpu_count() or 1
+    threads = max(1, min(16, nproc))  # the host share of one GPU
+    rate, upd, el, reps, nnz_rb = _oracle_rate(spec, rays, threads, budget_s)
+    rate1, upd1, el1, reps1, nnz_v = _oracle_rate(spec, rays[:per_view], 1, budget_s)
+    return {"value": rate, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"row block 0 ({len(views)} views x {per_view} rays) through all {spec.n_blocks} blocks of the "
+                      f"{spec.nx}^3 volume, FP + BP, FP64 matrix-free Siddon, {reps} repetitions: {upd:.3e} updates "
+                      f"in {el:.2f} s on {threads} threads",
+            "nproc": nproc, "cpu_model": _cpu_model(),
+            "single_core": {"value": rate1, "unit": "updates/s", "cores": 1,
+                            "sample": f"one view ({per_view} rays), FP + BP, {reps1} repetitions: {upd1:.3e} updates "
+                                      f"in {el1:.2f} s"},
+            "extrapolation": {"nnz_A": nnz_total, "updates_per_effective_epoch": 2 * nnz_total,
+                              "seconds_per_effective_epoch": 2 * nnz_total / rate,
+                              "seconds_per_effective_epoch_single_core": 2 * nnz_total / rate1,
+                              "rule": "linear in the updates: an effective epoch applies every nonzero of A once in "
+                                      "FP and once in BP; the sample's rate is taken for all row blocks"}}
+
+
+def cpu_baseline_fan(spec, budget_s=6.0):
+    """The FP64 oracle's FP + BP over every ray of the fan workload, all host cores."""
+    nproc = os.cpu_count() or 1
+    threads = max(1, min(16, nproc))
+    rate, upd, el, reps, nnz = _oracle_rate(spec, None, threads, budget_s)
+    return {"value": rate, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} x (FP + BP over all {spec.n_views} views x {spec.nu} bins, full {spec.nx}x{spec.ny} "
+                      f"image), FP64 matrix-free Siddon, {threads} threads: {upd:.3e} updates in {el:.2f} s"}
+
+
+def serving_requests(n_requests, seed=4004):
+    """The seeded serving mix: sides from {128..1024}, views = bins = 1.5 side, 10
+    random ellipses per phantom, 1% Gaussian noise; unit-rate Poisson gaps (scaled per
+    run), step length half of 1 / (2 ||A||^2) per geometry."""
     import torch
     from bsgd_inputs.configs import SERVING_SIDES, fan_request_geometry
     from bsgd_inputs.phantoms import phantom_for, add_gaussian_noise
-    from paper_1903_11874_amd.serving import Request, Server, latency_stats
+    from paper_1903_11874_amd.serving import Request
+    from paper_1903_11874_amd import Geometry
     rng = np.random.Generator(np.random.PCG64(seed))
-    server = Server(max_slots=max_slots)
-    mus = {}
-    reqs = []
-    truths = {}
+    geoms, mus, reqs, truths = {}, {}, [], {}
     t = 0.0
     for rid in range(n_requests):
-        t += rng.exponential(1.0 / rate)
+        t += rng.exponential(1.0)
         side = int(rng.choice(SERVING_SIDES))
         spec = fan_request_geometry(side)
-        if spec not in server.geoms:
+        if spec not in geoms:
             log(f"serving: geometry side {side}")
-        geom = server.geometry(spec)
-        if spec not in mus:
-            mus[spec] = 0.5 / (2.0 * lipschitz_gpu(geom, spec.nx * spec.ny, iters=15))
-        x_true = torch.tensor(phantom_for(spec, 10, 5000 + rid), dtype=torch.float32, device="cuda")
-        truths[rid] = x_true
-        y = add_gaussian_noise(geom.forward_project(x_true).double().cpu().numpy(), 0.01, 6000 + rid)
+            geoms[spec] = Geometry(spec)
+            mus[spec] = 0.5 / (2.0 * lipschitz_gpu(geoms[spec], spec.nx * spec.ny, iters=15))
+        x_true = phantom_for(spec, 10, 5000 + rid)
+        truths[rid] = torch.tensor(x_true, dtype=torch.float32, device="cuda")
+        y = add_gaussian_noise(geoms[spec].forward_project(truths[rid]).double().cpu().numpy(), 0.01, 6000 + rid)
         reqs.append(Request(rid=rid, geometry=spec, y=torch.tensor(y, dtype=torch.float32, device="cuda"),
-                            arrival=t, mu=mus[spec], seed=rid, node_count=64, tol=tol, max_epochs=max_epochs,
-                            check_every=5))
+                            arrival=t, mu=mus[spec], seed=rid, node_count=64))
     torch.cuda.synchronize()
-    log(f"serving: {n_requests} requests over {t:.2f} s, sides {sorted(set(r.geometry.nx for r in reqs))}")
-    log("serving: batched run")
-    served = server.run(reqs)
-    log("serving: sequential run")
-    seq = Server(max_slots=1).run_sequential(reqs)
+    return reqs, truths, sorted(geoms, key=lambda g: g.nx), mus
+
+
+def serving_bench(reqs, truths, specs, mus, rate, max_slots, tol, max_epochs):
+    """Continuous-batching server vs the plain per-solve loop on one Poisson stream."""
+    import dataclasses
+    import torch
+    from paper_1903_11874_amd.serving import Server, latency_stats
+    run_reqs = [dataclasses.replace(r, arrival=r.arrival / rate, tol=tol, max_epochs=max_epochs, check_every=5)
+                for r in reqs]
+    server = Server(max_slots=max_slots)
+    server.prepare(specs, node_count=64, mu_of=lambda g: mus[g])
+    log(f"serving at {rate:g}/s: batched run")
+    served = server.run(run_reqs)
+    log(f"serving at {rate:g}/s: sequential run")
+    seq = server.run_sequential(run_reqs)
     same = all(torch.equal(a.x, b.x) for a, b in zip(served, seq))
     st_b, st_s = latency_stats(served), latency_stats(seq)
 
@@ -258,14 +368,24 @@ def serving_bench(n_requests, rate, max_slots, tol, max_epochs, seed=4004):
 
     st_b.update(snr(served))
     st_s.update(snr(seq))
-    return {"requests": n_requests, "rate_per_s": rate, "arrival_span_s": t, "max_slots": max_slots,
+    return {"requests": len(run_reqs), "rate_per_s": rate, "arrival_span_s": max(r.arrival for r in run_reqs),
+            "max_slots": max_slots,
             "stop_rule": f"||A^T(y-Ax)||/||A^T y|| <= {tol} checked every 5 epochs, at most {max_epochs} epochs",
             "batched": st_b, "sequential": st_s,
             "solves_per_s_ratio": st_b["solves_per_s"] / st_s["solves_per_s"],
             "identical_results": bool(same),
-            "max_active": max(e[1] for e in server.log) if server.log else 0,
-            "ticks": len(server.log),
-            "enqueue_s": sum(e[2] for e in server.log), "check_and_wait_s": sum(e[3] for e in server.log)}
+            "max_active": max(e[1] for e in server.log) if server.log else 0, "ticks": len(server.log),
+            "enqueue_s": sum(e[2] for e in server.log), "check_wait_s": sum(e[3] for e in server.log)}
+
+
+def _line_of(m):
+    T = m["iters_per_step"]
+    return {"workload": m["workload"], "metric": "FP+BP ray-voxel updates/s", "value": m["value"],
+            "unit": "updates/s", "steps": m["steps"], "ms_per_step": m["elapsed"] / m["steps"] * 1e3,
+            "rows_per_iter": m["rows_per_iter"], "blocks_per_iter": m["blocks_per_iter"], "iters_per_step": T,
+            "roofline": m["roofline"], "kernels_avg_ms": m["kernels_avg_ms"],
+            "kernel_launches": {k: n for k, (ms, n) in m["times"].items()},
+            "residual_norm": {"before": m["r0"], "after": m["r1"]}, "updates_per_step": m["updates"] / m["steps"]}
 
 
 def main():
@@ -274,16 +394,21 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving", type=int, default=48,
+    ap.add_argument("--serving", type=int, default=512,
                     help="requests of the continuous-batching serving measurement (0 = skip)")
+    ap.add_argument("--serving-rates", default="20,1000",
+                    help="arrival rates (requests/s) of the serving runs: the workload's, then a saturating one")
     ap.add_argument("--serving-tol", type=float, default=1e-3)
-    ap.add_argument("--serving-max-epochs", type=int, default=30)
-    ap.add_argument("--cone-steps", type=int, default=3,
-                    help="epochs of the 3D cone-beam (256^3, TV) measurement reported as 'secondary' (0 = skip)")
+    ap.add_argument("--serving-max-epochs", type=int, default=120)
+    ap.add_argument("--serving-slots", type=int, default=48)
+    ap.add_argument("--fan-steps", type=int, default=20,
+                    help="epochs of the 2D fan-beam measurement reported as 'secondary' (0 = skip)")
     ap.add_argument("--cone-only", action="store_true",
-                    help="profiling aid: run only the cone-beam measurement and print its object")
+                    help="profiling aid: run only the cone-beam measurement and print its line")
+    ap.add_argument("--fan-only", action="store_true",
+                    help="profiling aid: run only the fan-beam measurement and print its line")
     ap.add_argument("--tune", default="auto",
-                    help="forward-projector launch shape: 'auto' (autotuner, before the timed region) "
+                    help="fan-beam forward-projector launch shape: 'auto' (autotuner, before the timed region) "
                          "or 'V,S' (views per workgroup, lanes per ray)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters) and exit")
@@ -305,84 +430,64 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
         return
-    if args.cone_only:
-        print(json.dumps(cone_bench(max(1, args.cone_steps), 1, max(1, args.cone_steps))), flush=True)
+    n_prof = args.profile_steps if args.profile_steps > 0 else args.steps
+    if args.fan_only:
+        f = fan_bench(args.steps, args.warmup, n_prof, args.tune)
+        print(json.dumps(_line_of(f)), flush=True)
         return
-    from bsgd_inputs.configs import workload
-    from bsgd_inputs.phantoms import phantom_for, poisson_log_noise
-    from paper_1903_11874_amd import Geometry, Solver
-
-    wl = workload(WORKLOAD)
-    spec = wl.geometry
-    dev = torch.device("cuda:0")
-    log("geometry")
-    geom = Geometry(spec)
-    n_vox = spec.nx * spec.ny * spec.nz
-    x_true = phantom_for(spec, wl.n_shapes, wl.phantom_seed)
-    xt = torch.tensor(x_true, dtype=torch.float32, device=dev)
-    y_clean = geom.forward_project(xt).double().cpu().numpy()
-    y = poisson_log_noise(y_clean, wl.noise_level, wl.noise_seed)
-    yd = torch.tensor(y, dtype=torch.float32, device=dev)
-    L = lipschitz_gpu(geom, n_vox)
-    mu = wl.solver.mu_scale / (2.0 * L)
-    log(f"L = {L:.4e}, mu = {mu:.4e}")
-
-    if args.tune == "auto":
-        from paper_1903_11874_amd.tuning import autotune
-        tt = autotune(geom, yd, node_count=64, mu=mu, epochs=2, seed=wl.solver.seed)
-        log("autotune: " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in sorted(tt.items(), key=lambda kv: kv[1])[:4]))
-    else:
-        v_, s_ = (int(t) for t in args.tune.split(","))
-        geom.set_tuning(fp_views_per_group=v_, fp_ray_split=s_)
-    log(f"forward projector shape: {geom.fp_views_per_group} views per workgroup, {geom.fp_ray_split} lanes per ray")
-
-    x = torch.zeros(n_vox, dtype=torch.float32, device=dev)
-    solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed)
-    T = solver.epoch_iters
-    log(f"alpha M = {solver.rows_per_iter}, gamma N = {solver.blocks_per_iter}, epoch = {T} iterations")
-
-    m = measure(geom, spec, solver, n_vox, args.warmup, args.steps,
-                args.profile_steps if args.profile_steps > 0 else args.steps, wl.name)
-    elapsed, value, updates, roofline, avg_ms, times = (m["elapsed"], m["value"], m["updates"], m["roofline"],
-                                                        m["kernels_avg_ms"], m["times"])
-    r0, r1, n_prof, t2, t3 = m["r0"], m["r1"], m["n_prof"], m["t2"], m["t3"]
-
+    c = cone_bench(args.steps, args.warmup, n_prof)
+    if args.cone_only:
+        print(json.dumps(_line_of(c)), flush=True)
+        return
+    T = c["iters_per_step"]
     out = {
         "metric": "FP+BP ray-voxel updates/s",
-        "value": value,
+        "value": c["value"],
         "unit": "updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": c["elapsed"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded random-ellipse phantom, Poisson noise)",
-        "config": {"workload": "2D fan-beam BSGD-IM 512x512 @0.5 mm, 720 views/360 deg, 768 bins @1 mm, "
-                               "SOD 500 SDD 1000, 8x8 blocks, 16 angle subsets, 4 sub-detectors, node count 64",
-                   "rows_per_iter": solver.rows_per_iter, "blocks_per_iter": solver.blocks_per_iter,
-                   "iters_per_step": T, "step": "one effective epoch",
-                   "fp_views_per_group": geom.fp_views_per_group, "fp_ray_split": geom.fp_ray_split},
-        "roofline": roofline,
-        "kernels_avg_ms": avg_ms,
-        "kernel_launches": {k: n for k, (ms, n) in times.items()},
-        "kernel_timing": f"HIP events around every kernel in a second timed region of {n_prof} epochs "
-                         f"(eager launches): {(t3 - t2) / n_prof * 1e3:.4f} ms per epoch; the first timed region "
-                         "replays captured HIP graphs without events",
-        "residual_norm": {"before": r0, "after": r1},
-        "updates_per_step": updates / args.steps,
+        "data": "synthetic (seeded random-ellipsoid phantom, 1% Gaussian noise)",
+        "config": {"workload": c["workload"], "rows_per_iter": c["rows_per_iter"],
+                   "blocks_per_iter": c["blocks_per_iter"], "iters_per_step": T,
+                   "step": "one effective epoch (TV prox once per epoch)"},
+        "roofline": c["roofline"],
+        "kernels_avg_ms": c["kernels_avg_ms"],
+        "kernel_launches": {k: n for k, (ms, n) in c["times"].items()},
+        "kernel_timing": f"HIP events around every kernel in a second timed region of {c['n_prof']} epochs "
+                         f"(eager launches): {(c['t3'] - c['t2']) / c['n_prof'] * 1e3:.4f} ms per epoch; the first "
+                         "timed region replays captured HIP graphs without events",
+        "residual_norm": {"before": c["r0"], "after": c["r1"]},
+        "updates_per_step": c["updates"] / args.steps,
     }
-    if args.cone_steps > 0:
-        del solver, x, yd, geom
+    cone_spec, cone_groups, cone_nnz = c["spec"], c["groups"], c["nnz"]
+    del c
+    torch.cuda.empty_cache()
+    if args.fan_steps > 0:
+        f = fan_bench(args.fan_steps, args.warmup, args.fan_steps, args.tune)
+        out["secondary"] = _line_of(f)
+        out["secondary"]["fp_views_per_group"] = f["fp_views_per_group"]
+        out["secondary"]["fp_ray_split"] = f["fp_ray_split"]
+        fan_spec = f["spec"]
+        del f
         torch.cuda.empty_cache()
-        out["secondary"] = cone_bench(args.cone_steps, 1, args.cone_steps)
+        if not args.no_cpu_baseline:
+            log("cpu baseline: fan")
+            out["secondary"]["cpu_baseline"] = cpu_baseline_fan(fan_spec)
     if args.serving > 0:
-        out["serving"] = serving_bench(args.serving, 20.0, 32, args.serving_tol, args.serving_max_epochs)
+        reqs, truths, specs, mus = serving_requests(args.serving)
+        out["serving"] = [serving_bench(reqs, truths, specs, mus, float(r), args.serving_slots, args.serving_tol,
+                                        args.serving_max_epochs) for r in args.serving_rates.split(",")]
+        del reqs, truths
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(spec, x_true)
+        log("cpu baseline: cone")
+        out["cpu_baseline"] = cpu_baseline_cone(cone_spec, cone_groups, cone_nnz)
     print(json.dumps(out), flush=True)
 
 

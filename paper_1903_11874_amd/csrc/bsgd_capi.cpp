@@ -127,6 +127,44 @@ struct DevBuf {
     }
 };
 
+// Page-locked host blocks, recycled through a process-wide pool instead of being freed
+// (freeing page-locked memory waits for the whole device): a block of at least `bytes`
+// (sizes rounded up to powers of two, at least 256 bytes).
+std::mutex g_pin_mu;
+std::vector<std::pair<size_t, void*>> g_pin_free;
+
+size_t pin_class(size_t b)
+{
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+}
+
+hipError_t pinned_get(void** out, size_t b, size_t* got)
+{
+    const size_t c = pin_class(b);
+    {
+        std::lock_guard<std::mutex> lock(g_pin_mu);
+        for (size_t i = 0; i < g_pin_free.size(); ++i)
+            if (g_pin_free[i].first == c) {
+                *out = g_pin_free[i].second;
+                g_pin_free.erase(g_pin_free.begin() + i);
+                if (got) *got = c;
+                return hipSuccess;
+            }
+    }
+    hipError_t e = hipHostMalloc(out, c, hipHostMallocDefault);
+    if (e == hipSuccess && got) *got = c;
+    return e;
+}
+
+void pinned_put(void* p, size_t b)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    g_pin_free.push_back({pin_class(b), p});
+}
+
 // Pinned host staging buffer whose reuse waits for the previous copy out of it.
 struct Staging {
     void* host = nullptr;
@@ -139,7 +177,7 @@ struct Staging {
             if (pending) (void)hipEventSynchronize(done);
             (void)hipEventDestroy(done);
         }
-        if (host) (void)hipHostFree(host);
+        pinned_put(host, bytes);
     }
     hipError_t reserve(size_t b)
     {
@@ -153,11 +191,12 @@ struct Staging {
             pending = false;
         }
         if (b <= bytes) return hipSuccess;
-        if (host) (void)hipHostFree(host);
+        pinned_put(host, bytes);
         host = nullptr;
         bytes = 0;
-        hipError_t e = hipHostMalloc(&host, b, hipHostMallocDefault);
-        if (e == hipSuccess) bytes = b;
+        size_t got = 0;
+        hipError_t e = pinned_get(&host, b, &got);
+        if (e == hipSuccess) bytes = got;
         return e;
     }
     hipError_t upload(void* dst, size_t b, hipStream_t st)
@@ -1000,6 +1039,7 @@ struct bsgd_solver {
     int last_n = 0;
     // profiling
     bool prof = false;
+    hipEvent_t last_use = nullptr;  // recorded after each call's work on the stream
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     double ms[KID_COUNT] = {0, 0, 0, 0, 0};
@@ -1007,16 +1047,22 @@ struct bsgd_solver {
 
     ~bsgd_solver()
     {
-        if (st) (void)hipStreamSynchronize(st);
+        // With an allocator the device buffers return to it in stream order; then only
+        // this solver's own work has to finish (its last-use event), not the stream.
+        if (last_use && g && g->alloc)
+            (void)hipEventSynchronize(last_use);
+        else if (st)
+            (void)hipStreamSynchronize(st);
+        if (last_use) (void)hipEventDestroy(last_use);
         drop_batch_graphs(this);
         for (auto& p : pending) {
             ev_pool.push_back(p.second.first);
             ev_pool.push_back(p.second.second);
         }
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-        if (norm_host) (void)hipHostFree(norm_host);
-        if (mu_host) (void)hipHostFree(mu_host);
-        if (tv_w_host) (void)hipHostFree(tv_w_host);
+        pinned_put(norm_host, 4 * sizeof(double));
+        pinned_put(mu_host, sizeof(float));
+        pinned_put(tv_w_host, 2 * sizeof(float));
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -1052,6 +1098,13 @@ static hipError_t timed(bsgd_solver* s, int kid, F&& fn)
     s->pending.push_back({kid, {a, b}});
     s->launches[kid] += 1;
     return hipSuccess;
+}
+
+// Record that the solver's work so far has been enqueued on st (its destructor waits for
+// this point instead of the whole stream when the memory is stream-ordered).
+static void mark_use(const bsgd_solver* s, hipStream_t st)
+{
+    if (s->last_use) (void)hipEventRecord(s->last_use, st);
 }
 
 static bsgd_status resolve_counts(const bsgd_geometry* g, const bsgd_options* o, int& R, int& B)
@@ -1138,9 +1191,9 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     const int n_part = (int)(((per_view + 255) / 256) * g->d.n_views);
     S_TRY(s->partials.alloc((size_t)std::max(n_part, 4096) * sizeof(double)));
     S_TRY(s->norm_out.alloc(4 * sizeof(double)));
-    S_TRY(hipHostMalloc((void**)&s->norm_host, 4 * sizeof(double), hipHostMallocDefault));
+    S_TRY(pinned_get((void**)&s->norm_host, 4 * sizeof(double), nullptr));
     S_TRY(s->mu_dev.alloc(sizeof(float)));
-    S_TRY(hipHostMalloc((void**)&s->mu_host, sizeof(float), hipHostMallocDefault));
+    S_TRY(pinned_get((void**)&s->mu_host, sizeof(float), nullptr));
     s->mu_cur = o->mu;
     *s->mu_host = (float)o->mu;
     S_TRY(hipMemcpyAsync(s->mu_dev.p, s->mu_host, sizeof(float), hipMemcpyHostToDevice, st));
@@ -1161,7 +1214,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
         S_TRY(s->tv_a.alloc(nb));
         S_TRY(s->tv_b.alloc(nb));
         S_TRY(s->tv_w.alloc(2 * sizeof(float)));
-        S_TRY(hipHostMalloc((void**)&s->tv_w_host, 2 * sizeof(float), hipHostMallocDefault));
+        S_TRY(pinned_get((void**)&s->tv_w_host, 2 * sizeof(float), nullptr));
         tv_weight_step(g->dim, o->mu, o->tv_lambda, s->tv_w_host);
         S_TRY(hipMemcpyAsync(s->tv_w.p, s->tv_w_host, 2 * sizeof(float), hipMemcpyHostToDevice, st));
         S_TRY(hipStreamSynchronize(st));
@@ -1172,6 +1225,8 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     else
         S_TRY(launch_fill(s->ghat.as<float>(), 0.0f, (int64_t)g->M * g->n_vox, st));
     S_TRY(launch_fill(s->gsum.as<float>(), 0.0f, g->n_vox, st));
+    S_TRY(hipEventCreateWithFlags(&s->last_use, hipEventDisableTiming));
+    mark_use(s, st);
 #undef S_TRY
     *out = s;
     return BSGD_OK;
@@ -1436,6 +1491,7 @@ extern "C" bsgd_status bsgd_step(bsgd_solver* s, int32_t n_iters, double* resid_
             return stt;
         }
     }
+    mark_use(s, s->st);
     if (resid_norm_out) {
         bsgd_status stt = resid_norm(s, resid_norm_out);
         if (stt != BSGD_OK) {
@@ -1697,7 +1753,10 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
             }
             hipError_t he = hipGraphLaunch(bg->exec, st);
             if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batched graph launch: %s", hipGetErrorString(he)));
-            for (int i = 0; i < n; ++i) solvers[i]->k += n_iters;
+            for (int i = 0; i < n; ++i) {
+                solvers[i]->k += n_iters;
+                mark_use(solvers[i], st);
+            }
             return BSGD_OK;
         }
     }
@@ -1712,7 +1771,10 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
     std::vector<BatchLaunchGroup> groups = batch_groups(solvers, n);
     hipError_t he = enqueue_batch(groups, solvers, n, n_iters, dim, st);
     if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "batched launch: %s", hipGetErrorString(he)));
-    for (int i = 0; i < n; ++i) solvers[i]->k += n_iters;
+    for (int i = 0; i < n; ++i) {
+        solvers[i]->k += n_iters;
+        mark_use(solvers[i], st);
+    }
     return BSGD_OK;
 }
 
@@ -1779,6 +1841,7 @@ extern "C" bsgd_status bsgd_solver_state(const bsgd_solver* s, int32_t which, fl
     }
     if (bytes < need) return fail(BSGD_E_INVALID_ARG, "state needs %zu bytes", need);
     HIP_TRY(hipMemcpyAsync(out, src->p, need, hipMemcpyDeviceToDevice, s->st));
+    mark_use(s, s->st);
     return BSGD_OK;
 }
 
@@ -1906,6 +1969,7 @@ extern "C" bsgd_status bsgd_normal_residual_async(bsgd_solver* const* solvers, i
         HIP_TRY(launch_sumsq(tg, g->n_vox, part, &np, st));
         HIP_TRY(launch_sum_partials(part, np, dout, st));
         HIP_TRY(hipMemcpyAsync(out_sq + 2 * i, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        mark_use(s, st);
     }
     return BSGD_OK;
 }
