@@ -357,10 +357,12 @@ __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restric
 // ------------------------------------------------------------ solver: forward projection
 
 // G.fp_wpp waves per (view slot, block slot) pair: z^j = A_{rows}^{J_j} x_{J_j} on the
-// pair's range. Wave w of a pair walks pixels q = lane + 64 (w + fp_wpp r) for a
-// wave-uniform number of rounds r; every lane runs every round (lanes past the pair's
-// pixels are dead), so the walk's trip count is wave-uniform. x is gathered from
-// global memory (blocks too large for LDS).
+// pair's range. The range is cut into patches of 8 x 8 pixels (2D: 64 x 1), and wave w of
+// a pair walks patches w, w + fp_wpp, ... one lane per pixel; every lane runs every
+// round (lanes off the range are dead), so the walk's trip count is wave-uniform. A
+// square patch keeps the chord lengths of a wave's rays close (a row of 64 pixels spans
+// the footprint from edge to centre), so fewer steps are wasted on the longest ray. x is
+// gathered from global memory (blocks too large for LDS).
 template <int DIM>
 __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork* __restrict__ work, SchedLayout L,
                                                const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
@@ -373,20 +375,21 @@ __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork*
     const PairWork W = work[pair];
     const int wk = W.k1 - W.k0, wl = W.l1 - W.l0;
     if (wk <= 0 || wl <= 0) return;
-    const int n = wk * wl;
-    if (n <= 64 * w) return;
+    constexpr int PX = DIM == 3 ? 8 : 64, PY = 64 / PX;
+    const int npx = (wk + PX - 1) / PX, n_patch = npx * ((wl + PY - 1) / PY);
+    if (n_patch <= w) return;
     const BlockInfo B = G.blocks[blocks_sel[b]];
     const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
     const int sy = G.nx, sz = G.nx * G.ny;
     int nb[3];
     float h[3], vs[3];
     block_dims(G, B, nb, h, vs);
-    const int rounds = (n - 64 * w + 64 * wpp - 1) / (64 * wpp);
+    const int rounds = (n_patch - w + wpp - 1) / wpp;
     for (int r = 0; r < rounds; ++r) {
-        const int q = lane + 64 * (w + wpp * r);
-        const bool on = q < n;
-        const int qq = on ? q : 0;
-        const int l = W.l0 + qq / wk, k = W.k0 + qq % wk;
+        const int pt = w + wpp * r;
+        const int kk = (pt % npx) * PX + lane % PX, ll = (pt / npx) * PY + lane / PX;
+        const bool on = kk < wk && ll < wl;
+        const int l = W.l0 + (on ? ll : 0), k = W.k0 + (on ? kk : 0);
         Ray R;
         make_ray<DIM>(G, W.view, W.c, W.s, W, k, l, R);
         float tlo = 0.0f, thi = 0.0f, acc;
