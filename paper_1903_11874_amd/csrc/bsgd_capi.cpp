@@ -1210,7 +1210,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     }
     if (o->tv_lambda > 0) {
         const size_t nb = (size_t)g->dim * g->n_vox * sizeof(float);
-        S_TRY(s->tv_p.alloc(nb + (size_t)g->n_vox * sizeof(float)));  // dual p and primal u
+        S_TRY(s->tv_p.alloc(nb));  // three dual iterates in rotation
         S_TRY(s->tv_a.alloc(nb));
         S_TRY(s->tv_b.alloc(nb));
         S_TRY(s->tv_w.alloc(2 * sizeof(float)));

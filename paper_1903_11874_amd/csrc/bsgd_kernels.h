@@ -135,8 +135,8 @@ hipError_t launch_dot(const float* a, const float* b, int64_t n, double* partial
 // TV proximal step of BSGD-TV on x (in place): iters fast-gradient-projection steps.
 // wstep: device {w, step} (prox weight w = mu lambda and the dual step 1/(4 dim w),
 // written by tv_weight_step), read by the kernels at run time so that captured graphs
-// see step-length changes. p: device [dim + 1][n_vox] scratch (the dual iterate, then
-// the primal point u); ra, rb: device [dim][n_vox] scratch.
+// see step-length changes. p, ra, rb: device [dim][n_vox] scratch each, holding the
+// last three dual iterates in rotation.
 hipError_t launch_tv_prox(const DevGeom& G, float* x, const float* wstep, int iters, float* p, float* ra,
                           float* rb, hipStream_t st);
 // Bounds of the pixel rectangle (columns, rows) one 3D back-projection workgroup tile

@@ -1629,54 +1629,113 @@ __device__ __forceinline__ float div_adj(const float* __restrict__ q, int64_t nv
     return r;
 }
 
-// FGP step, first half: the primal point of the current dual iterate,
-// u = b - w D^T r (one thread per voxel).
-// The prox weight w and the dual step are read from the device ({w, step}), so a
-// captured graph follows step-length changes made between its replays.
-template <int DIM>
-__global__ __launch_bounds__(WG) void k_fgp_u(const float* __restrict__ b, const float* __restrict__ rin,
-                                              float* __restrict__ u, int nx, int ny, int nz,
-                                              const float* __restrict__ wstep)
-{
-    const int64_t nvox = (int64_t)nx * ny * nz;
-    const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (o >= nvox) return;
-    const float w = wstep[0];
-    const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
-    u[o] = b[o] - w * div_adj<DIM>(rin, nvox, X, Y, Z, nx, ny, nz);
-}
+// One FGP iteration fused into one pass. The dual iterates p_k (pc) and p_{k-1} (pp)
+// are kept instead of the extrapolated point, which is rebuilt where it is read:
+// r = p_k + coef (p_k - p_{k-1}); then u = b - w D^T r and
+// p_{k+1} = P_ball(r + step D u), with D the backward differences (zero across the low
+// boundary) and P_ball the projection onto the unit ball per voxel. HBM traffic per voxel:
+// p_k and p_{k-1} read, b read, p_{k+1} written (40 B in 3D).
+//
+// A workgroup owns a FGP_TX x FGP_TY column tile and marches up FGP_ZC planes. Per plane
+// it builds r of the next plane in LDS over the tile with a one-voxel halo (three
+// planes rotate, so a plane's r is built once), then u of the plane over the tile and
+// its low halo, then the dual update of its own voxels; u one plane down stays in a
+// register. A chunk starts one plane low (u only) unless it starts at z = 0.
+constexpr int FGP_TX = 64, FGP_TY = 8, FGP_ZC = 32, FGP_WG = FGP_TX * FGP_TY;
+constexpr int FGP_HX = FGP_TX + 2, FGP_HY = FGP_TY + 2;  // r tile with halo, x and y in [-1, T]
+constexpr int FGP_UX = FGP_TX + 1, FGP_UY = FGP_TY + 1;  // u tile with low halo, in [-1, T - 1]
 
-// FGP step, second half: p_new = P_ball(r + step D u); r_out = p_new + coef (p_new - p),
-// with D the backward differences (zero across the low boundary).
 template <int DIM>
-__global__ __launch_bounds__(WG) void k_fgp_dual(const float* __restrict__ u, const float* __restrict__ rin,
-                                                 float* __restrict__ rout, float* __restrict__ p, int nx, int ny,
-                                                 int nz, const float* __restrict__ wstep, float coef)
+__global__ __launch_bounds__(FGP_WG) void k_fgp_step(const float* __restrict__ b, const float* __restrict__ pc,
+                                                     const float* __restrict__ pp, float* __restrict__ pn, int nx,
+                                                     int ny, int nz, const float* __restrict__ wstep, float coef)
 {
+    __shared__ float rL[3][DIM][FGP_HY * FGP_HX];
+    __shared__ float uL[FGP_UY * FGP_UX];
     const int64_t nvox = (int64_t)nx * ny * nz;
-    const int64_t o = (int64_t)blockIdx.x * WG + threadIdx.x;
-    if (o >= nvox) return;
-    const float step = wstep[1];
-    const int X = (int)(o % nx), Y = (int)((o / nx) % ny), Z = (int)(o / ((int64_t)nx * ny));
-    const float uc = u[o];
-    float g[3] = {0.0f, 0.0f, 0.0f};
-    if (X >= 1) g[0] = uc - u[o - 1];
-    if (Y >= 1) g[1] = uc - u[o - nx];
-    if (DIM == 3 && Z >= 1) g[2] = uc - u[o - (int64_t)nx * ny];
-    float q[3];
-    float n2 = 0.0f;
+    const int64_t plane = (int64_t)nx * ny;
+    // tiles x fastest, then y, then z chunks, numbered so that each XCD marches a
+    // contiguous run of them together and the halos its tiles share stay in its L2
+    const int gx = (nx + FGP_TX - 1) / FGP_TX, gy = (ny + FGP_TY - 1) / FGP_TY;
+    const int t = xcd_local((int)blockIdx.x, (int)gridDim.x);
+    const int X0 = (t % gx) * FGP_TX, Y0 = ((t / gx) % gy) * FGP_TY;
+    const int Z0 = DIM == 3 ? (t / (gx * gy)) * FGP_ZC : 0;
+    const int Z1 = DIM == 3 ? min(nz, Z0 + FGP_ZC) : 1;
+    const float w = wstep[0], step = wstep[1];
+    const int tx = threadIdx.x % FGP_TX, ty = threadIdx.x / FGP_TX;
+    const int X = X0 + tx, Y = Y0 + ty;
+    const bool own = X < nx && Y < ny;
+
+    // r of plane z over the tile and its halo into rotation slot z % 3 (zero outside the volume)
+    auto build_r = [&](int z) {
+        float(*dst)[FGP_HY * FGP_HX] = rL[z % 3];
+        for (int e = threadIdx.x; e < FGP_HY * FGP_HX; e += FGP_WG) {
+            const int gx = X0 + e % FGP_HX - 1, gy = Y0 + e / FGP_HX - 1;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const int64_t o = (int64_t)z * plane + (int64_t)gy * nx + gx;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        q[a] = fmaf(step, g[a], rin[a * nvox + o]);
-        n2 = fmaf(q[a], q[a], n2);
-    }
-    const float sc = 1.0f / fmaxf(1.0f, sqrtf(n2));
+                for (int a = 0; a < DIM; ++a) {
+                    const float c = pc[a * nvox + o], q = pp[a * nvox + o];
+                    dst[a][e] = fmaf(coef, c - q, c);
+                }
+            } else {
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const float pn = q[a] * sc;
-        const float po = p[a * nvox + o];
-        rout[a * nvox + o] = fmaf(coef, pn - po, pn);
-        p[a * nvox + o] = pn;
+                for (int a = 0; a < DIM; ++a) dst[a][e] = 0.0f;
+            }
+        }
+    };
+
+    const int zs = Z0 > 0 ? Z0 - 1 : 0;
+    build_r(zs);
+    float u_prev = 0.0f;
+    for (int z = zs; z < Z1; ++z) {
+        if (DIM == 3 && z + 1 < nz) build_r(z + 1);
+        __syncthreads();
+        // u = b - w D^T r over x, y in [-1, T - 1] (the sums in the order of the
+        // separate D^T: +x, -x, +y, -y, +z, -z)
+        const float(*rc)[FGP_HY * FGP_HX] = rL[z % 3];
+        const float(*rn)[FGP_HY * FGP_HX] = rL[(z + 1) % 3];
+        for (int e = threadIdx.x; e < FGP_UY * FGP_UX; e += FGP_WG) {
+            const int lx = e % FGP_UX - 1, ly = e / FGP_UX - 1;
+            const int gx = X0 + lx, gy = Y0 + ly;
+            float uv = 0.0f;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const int h = (ly + 1) * FGP_HX + (lx + 1);
+                float d = 0.0f;
+                if (gx >= 1) d += rc[0][h];
+                if (gx + 1 < nx) d -= rc[0][h + 1];
+                if (gy >= 1) d += rc[1][h];
+                if (gy + 1 < ny) d -= rc[1][h + FGP_HX];
+                if (DIM == 3) {
+                    if (z >= 1) d += rc[DIM - 1][h];
+                    if (z + 1 < nz) d -= rn[DIM - 1][h];
+                }
+                uv = b[(int64_t)z * plane + (int64_t)gy * nx + gx] - w * d;
+            }
+            uL[e] = uv;
+        }
+        __syncthreads();
+        const int hu = (ty + 1) * FGP_UX + (tx + 1);
+        const float uc = uL[hu];
+        if (own && z >= Z0) {
+            float g[3] = {0.0f, 0.0f, 0.0f};
+            if (X >= 1) g[0] = uc - uL[hu - 1];
+            if (Y >= 1) g[1] = uc - uL[hu - FGP_UX];
+            if (DIM == 3 && z >= 1) g[2] = uc - u_prev;
+            const int hr = (ty + 1) * FGP_HX + (tx + 1);
+            float q[3];
+            float n2 = 0.0f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                q[a] = fmaf(step, g[a], rc[a][hr]);
+                n2 = fmaf(q[a], q[a], n2);
+            }
+            const float sc = 1.0f / fmaxf(1.0f, sqrtf(n2));
+            const int64_t o = (int64_t)z * plane + (int64_t)Y * nx + X;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) pn[a * nvox + o] = q[a] * sc;
+        }
+        u_prev = uc;
     }
 }
 
@@ -2023,37 +2082,36 @@ hipError_t launch_tv_prox(const DevGeom& G, float* x, const float* wstep, int it
     if (iters <= 0) return hipSuccess;
     const int64_t nvox = (int64_t)G.nx * G.ny * G.nz;
     const int dim = G.dim;
+    // p_k lives in buf[k % 3]; p_0 = 0 and p_{-1} = p_0
+    float* buf[3] = {p, ra, rb};
     hipError_t e = launch_fill(p, 0.0f, dim * nvox, st);
     if (e != hipSuccess) return e;
-    e = launch_fill(ra, 0.0f, dim * nvox, st);
-    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)(((G.nx + FGP_TX - 1) / FGP_TX) * ((G.ny + FGP_TY - 1) / FGP_TY) *
+                               (dim == 3 ? (G.nz + FGP_ZC - 1) / FGP_ZC : 1)));
     double tk = 1.0;
-    float* rin = ra;
-    float* rout = rb;
-    float* u = p + (int64_t)dim * nvox;  // p holds (dim + 1) nvox floats
+    float coef = 0.0f;  // extrapolation weight of the current iterate ((t_{k-1} - 1) / t_k)
     for (int it = 0; it < iters; ++it) {
-        const double tn = (1.0 + sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
-        const float coef = (float)((tk - 1.0) / tn);
-        if (dim == 3) {
-            hipLaunchKernelGGL(k_fgp_u<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, wstep);
-            hipLaunchKernelGGL(k_fgp_dual<3>, dim3(grid1(nvox)), dim3(WG), 0, st, u, rin, rout, p, G.nx, G.ny, G.nz,
-                               wstep, coef);
-        } else {
-            hipLaunchKernelGGL(k_fgp_u<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, rin, u, G.nx, G.ny, G.nz, wstep);
-            hipLaunchKernelGGL(k_fgp_dual<2>, dim3(grid1(nvox)), dim3(WG), 0, st, u, rin, rout, p, G.nx, G.ny, G.nz,
-                               wstep, coef);
-        }
+        const float* pc = buf[it % 3];
+        const float* pp = buf[(it + 2) % 3];
+        if (it == 0) pp = pc;
+        float* pn = buf[(it + 1) % 3];
+        if (dim == 3)
+            hipLaunchKernelGGL(k_fgp_step<3>, grid, dim3(FGP_WG), 0, st, x, pc, pp, pn, G.nx, G.ny, G.nz, wstep,
+                               coef);
+        else
+            hipLaunchKernelGGL(k_fgp_step<2>, grid, dim3(FGP_WG), 0, st, x, pc, pp, pn, G.nx, G.ny, G.nz, wstep,
+                               coef);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        const double tn = (1.0 + sqrt(1.0 + 4.0 * tk * tk)) / 2.0;
+        coef = (float)((tk - 1.0) / tn);
         tk = tn;
-        float* t = rin;
-        rin = rout;
-        rout = t;
     }
+    const float* pf = buf[iters % 3];
     if (dim == 3)
-        hipLaunchKernelGGL(k_fgp_final<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, wstep);
+        hipLaunchKernelGGL(k_fgp_final<3>, dim3(grid1(nvox)), dim3(WG), 0, st, x, pf, G.nx, G.ny, G.nz, wstep);
     else
-        hipLaunchKernelGGL(k_fgp_final<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, p, G.nx, G.ny, G.nz, wstep);
+        hipLaunchKernelGGL(k_fgp_final<2>, dim3(grid1(nvox)), dim3(WG), 0, st, x, pf, G.nx, G.ny, G.nz, wstep);
     return hipGetLastError();
 }
 
