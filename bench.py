@@ -113,6 +113,96 @@ def profiled(workload_name, kernel_key):
     return None
 
 
+TRAFFIC_WORKLOADS = ("c3_cone256_tv", "c2_fan512_im")
+
+
+def _kernel_base(name):
+    """Kernel name without namespaces, template arguments and parameters."""
+    n = name.replace("(anonymous namespace)::", "").split("(")[0].split("<")[0]
+    return n.split("::")[-1].replace("void ", "").strip()
+
+
+def _counters(db):
+    """{kernel: {counter: mean value per dispatch}} from a rocprofv3 --pmc database."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, counter_name, count(distinct dispatch_id), sum(value) "
+                     "from counters_collection group by kernel_name, counter_name").fetchall()
+    out = {}
+    for name, counter, n, total in rows:
+        k = _kernel_base(name)
+        d = out.setdefault(k, {})
+        # template instances of one kernel are pooled
+        acc = d.setdefault(counter, [0, 0.0])
+        acc[0] += n
+        acc[1] += total
+    return {k: {cn: v[1] / v[0] for cn, v in d.items()} for k, d in out.items()}
+
+
+def _kernel_times(db):
+    """{kernel: (calls, mean us, min us, max us)} from a rocprofv3 --kernel-trace database."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, end - start from kernels").fetchall()
+    out = {}
+    for name, dt in rows:
+        out.setdefault(_kernel_base(name), []).append(dt / 1e3)
+    return {k: (len(v), sum(v) / len(v), min(v), max(v)) for k, v in out.items()}
+
+
+def write_traffic(d):
+    """Write profiles/traffic.json from the rocprofv3 databases under d and print the
+    per-kernel tables: d/copy_fetch, d/copy_write (FETCH_SIZE / WRITE_SIZE of the copy
+    probe), and per workload w: d/w_trace (kernel trace), d/w_fetch, d/w_write, d/w_sq
+    (SQ_INSTS_VALU and other SQ counters). HBM bytes per dispatch are the KiB counters
+    scaled so that the 1 GiB copy reads and writes 1 GiB."""
+    import glob
+    import hashlib
+
+    def db(sub):
+        f = glob.glob(os.path.join(d, sub, "*_results.db"))
+        if len(f) != 1:
+            raise SystemExit(f"expected one rocprofv3 database under {os.path.join(d, sub)}, found {len(f)}")
+        return f[0]
+
+    copy_bytes = float(1 << 30)
+    cf = _counters(db("copy_fetch"))["__amd_rocclr_copyBuffer"]["FETCH_SIZE"]
+    cw = _counters(db("copy_write"))["__amd_rocclr_copyBuffer"]["WRITE_SIZE"]
+    fetch_scale = copy_bytes / (cf * 1024.0)
+    write_scale = copy_bytes / (cw * 1024.0)
+    src = b"".join(open(os.path.join(ROOT, "paper_1903_11874_amd", "csrc", n), "rb").read()
+                   for n in ("bsgd_kernels.hip", "bsgd_device.h", "bsgd_kernels.h", "bsgd_capi.cpp"))
+    out = {"source_sha256": hashlib.sha256(src).hexdigest(), "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "calibration": f"plain 1 GiB device copy (__amd_rocclr_copyBuffer): FETCH_SIZE {cf:.1f} KiB, "
+                          f"WRITE_SIZE {cw:.1f} KiB per dispatch",
+           "workloads": {}}
+    for w in TRAFFIC_WORKLOADS:
+        fe, wr, sq = _counters(db(w + "_fetch")), _counters(db(w + "_write")), _counters(db(w + "_sq"))
+        tt = _kernel_times(db(w + "_trace"))
+        per = {}
+        print(f"\n### {w}\n\n| kernel | calls | avg us | min us | max us |\n|---|---|---|---|---|")
+        for k, (n, avg, mn, mx) in sorted(tt.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+            print(f"| {k} | {n} | {avg:.2f} | {mn:.2f} | {mx:.2f} |")
+        print("\n| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB (scaled) | VALU instr | SALU instr | LDS instr "
+              "| waves | wait-any / wave cycles |\n|---|---|---|---|---|---|---|---|---|")
+        for k in sorted(set(fe) & set(wr)):
+            if not k.startswith("k_"):
+                continue
+            hbm = (fe[k]["FETCH_SIZE"] * fetch_scale + wr[k]["WRITE_SIZE"] * write_scale) * 1024.0
+            q = sq.get(k, {})
+            per[k] = {"hbm_bytes": hbm, "valu_insts": q.get("SQ_INSTS_VALU")}
+            wait = q.get("SQ_WAIT_ANY", 0.0) / q["SQ_WAVE_CYCLES"] if q.get("SQ_WAVE_CYCLES") else float("nan")
+            print(f"| {k} | {fe[k]['FETCH_SIZE']:.4g} | {wr[k]['WRITE_SIZE']:.4g} | {hbm / 1e6:.2f} "
+                  f"| {q.get('SQ_INSTS_VALU', float('nan')):.3g} | {q.get('SQ_INSTS_SALU', float('nan')):.3g} "
+                  f"| {q.get('SQ_INSTS_LDS', float('nan')):.3g} | {q.get('SQ_WAVES', float('nan')):.0f} | {wait:.2f} |")
+        out["workloads"][w] = per
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(f"\nwrote {path}")
+
+
 def measure(geom, spec, solver, n_vox, warmup, steps, n_prof, workload_name):
     """Warm-up epochs, a timed region of `steps` epochs (captured HIP graphs, no
     events), then an event-timed eager region of `n_prof` epochs for per-kernel
@@ -414,7 +504,12 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="epochs of the event-timed second region (0 = same as --steps)")
+    ap.add_argument("--write-traffic", metavar="DIR", default=None,
+                    help="write profiles/traffic.json from the rocprofv3 databases under DIR (no GPU use)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the hot path has no multi-GPU mode)", file=sys.stderr)
@@ -433,7 +528,9 @@ def main():
     n_prof = args.profile_steps if args.profile_steps > 0 else args.steps
     if args.fan_only:
         f = fan_bench(args.steps, args.warmup, n_prof, args.tune)
-        print(json.dumps(_line_of(f)), flush=True)
+        line = _line_of(f)
+        line.update(fp_views_per_group=f["fp_views_per_group"], fp_ray_split=f["fp_ray_split"])
+        print(json.dumps(line), flush=True)
         return
     c = cone_bench(args.steps, args.warmup, n_prof)
     if args.cone_only:
