@@ -637,6 +637,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.cov_off = nullptr;
     G.cov_idx = nullptr;
     set_bp3_bounds(G, d.sod, d.sdd, d.du, d.dv);
+    G.fp_buf = (g->dim == 3 && (int64_t)d.nx * d.ny * ((d.nz + d.bz - 1) / d.bz) < ((int64_t)1 << 29)) ? 1 : 0;
     return upload_cover_index(g, st);
 }
 
@@ -1010,6 +1011,10 @@ struct bsgd_solver {
     SchedLayout L{};
     DevBuf z, ghat, gsum, r_sel, sched, draws, work, partials, norm_out, tv_p, tv_a, tv_b;
     DevBuf rho, delta;  // sub-detector memory: residual snapshots and their changes (z layout)
+    // 3D global-memory forward walk: x stored y fastest ([z][x][y]), refreshed from x at the
+    // start of every step call and after every TV prox, and written with x by the back
+    // projection in between; unallocated otherwise
+    DevBuf xT;
     int sched_cap = 0;
     Staging stage;
     // one captured epoch (T iterations) replayed per epoch
@@ -1164,7 +1169,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
     s->subdet = (o->flags & BSGD_FLAG_SUBDET_MEMORY) != 0;
     for (DevBuf* b : {&s->z, &s->ghat, &s->gsum, &s->r_sel, &s->sched, &s->draws, &s->work, &s->partials, &s->norm_out,
                       &s->tv_p, &s->tv_a, &s->tv_b, &s->rho, &s->delta, &s->g_sched, &s->g_work, &s->g_draws,
-                      &s->mu_dev, &s->eud_cur, &s->eud_prev, &s->tv_w, &s->nr_ty, &s->nr_tg, &s->nr_out})
+                      &s->mu_dev, &s->eud_cur, &s->eud_prev, &s->tv_w, &s->nr_ty, &s->nr_tg, &s->nr_out, &s->xT})
         b->use(g->alloc, st);
     const int64_t per_view = (int64_t)g->d.nu * g->d.nv;
     auto cleanup = [&](bsgd_status e) {
@@ -1186,6 +1191,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
         S_TRY(s->ghat.alloc((size_t)g->M * g->n_vox * sizeof(float)));
     }
     S_TRY(s->gsum.alloc((size_t)g->n_vox * sizeof(float)));
+    if (g->dim == 3 && fp_lds_bytes_for(g->dg) == 0) S_TRY(s->xT.alloc((size_t)g->n_vox * sizeof(float)));
     // 2D: one {w2, slope, lmax, r} record per selected ray; 3D: the residual
     S_TRY(s->r_sel.alloc((size_t)s->maxv * per_view * (g->dim == 2 ? 4 : 1) * sizeof(float)));
     const int n_part = (int)(((per_view + 255) / 256) * g->d.n_views);
@@ -1290,6 +1296,14 @@ static bsgd_status resid_norm(bsgd_solver* s, double* out)
 // Enqueue n_iters iterations reading schedule records `dsched` and writing work
 // records / draws into `dwork` / `ddraws`; k_first is the counter of the first one
 // (used only to place the TV steps).
+// The copy of x stored y fastest, from x (no-op when the solver keeps none).
+static hipError_t refresh_xT(bsgd_solver* s, hipStream_t st)
+{
+    if (!s->xT.p) return hipSuccess;
+    const bsgd_geometry_desc& d = s->g->d;
+    return launch_xy_transpose(s->x, s->xT.as<float>(), d.nx, d.ny, d.nz, st);
+}
+
 static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32_t* dsched, PairWork* dwork,
                                      int8_t* ddraws, int n_iters, int64_t k_first)
 {
@@ -1305,7 +1319,8 @@ static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32
         const int32_t* rec = dsched + (size_t)it * s->L.stride;
         const PairWork* wk = dwork + it * per_it_work;
         e = timed(s, KID_FP, [&] {
-            return launch_fp_pairs(g->dg, wk, s->L, rec + s->L.off_blocks(), s->x, s->z.as<float>(), st);
+            return launch_fp_pairs(g->dg, wk, s->L, rec + s->L.off_blocks(), s->x, s->xT.as<float>(), s->z.as<float>(),
+                                   st);
         });
         if (e != hipSuccess) return e;
         e = timed(s, KID_RESID, [&] {
@@ -1318,7 +1333,8 @@ static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32
         if (e != hipSuccess) return e;
         e = timed(s, KID_BP, [&] {
             return launch_bp_step(g->dg, rec, wk, s->L, s->r_sel.as<float>(), s->subdet ? s->delta.as<float>() : nullptr,
-                                  s->ghat.as<float>(), s->gsum.as<float>(), s->x, s->mu_dev.as<float>(), g->n_vox, st);
+                                  s->ghat.as<float>(), s->gsum.as<float>(), s->x, s->xT.as<float>(), s->mu_dev.as<float>(),
+                                  g->n_vox, st);
         });
         if (e != hipSuccess) return e;
         if (s->auto_mu) {
@@ -1329,8 +1345,9 @@ static hipError_t enqueue_iterations(bsgd_solver* s, hipStream_t st, const int32
         // between replays of a captured epoch); a non-positive weight is the identity
         if (s->o.tv_lambda > 0 && (s->auto_mu || s->mu_cur > 0) && (k_first + it + 1) % s->tv_every == 0) {
             e = timed(s, KID_TV, [&] {
-                return launch_tv_prox(g->dg, s->x, s->tv_w.as<float>(), s->o.tv_inner_iters, s->tv_p.as<float>(),
-                                      s->tv_a.as<float>(), s->tv_b.as<float>(), st);
+                hipError_t e2 = launch_tv_prox(g->dg, s->x, s->tv_w.as<float>(), s->o.tv_inner_iters,
+                                               s->tv_p.as<float>(), s->tv_a.as<float>(), s->tv_b.as<float>(), st);
+                return e2 == hipSuccess ? refresh_xT(s, st) : e2;
             });
             if (e != hipSuccess) return e;
         }
@@ -1369,6 +1386,7 @@ static bsgd_status step_segment(bsgd_solver* s, int n_iters)
         s->graphs && !s->prof && n_iters % T == 0 && s->k % T == 0 && tv_aligned && n_iters > 0;
     bsgd_status stt = ensure_sched(s, n_iters);
     if (stt != BSGD_OK) return stt;
+    HIP_TRY(refresh_xT(s, s->st));  // the caller may have changed x since the last call
     const size_t sched_bytes = (size_t)n_iters * s->L.stride * sizeof(int32_t);
     HIP_TRY(s->stage.reserve(sched_bytes));
     int32_t* host = reinterpret_cast<int32_t*>(s->stage.host);
@@ -1560,6 +1578,7 @@ static std::vector<BatchLaunchGroup> batch_groups(bsgd_solver* const* solvers, i
             e.work = s->work.as<PairWork>();
             e.y = s->y;
             e.x = s->x;
+            e.xT = s->xT.as<float>();
             e.z = s->z.as<float>();
             e.ghat = s->ghat.as<float>();
             e.gsum = s->gsum.as<float>();
@@ -1601,6 +1620,7 @@ static hipError_t enqueue_batch(std::vector<BatchLaunchGroup>& groups, bsgd_solv
             if (s->o.tv_lambda > 0 && s->mu_cur > 0 && (s->k + it + 1) % s->tv_every == 0) {
                 hipError_t he = launch_tv_prox(s->g->dg, s->x, s->tv_w.as<float>(), s->o.tv_inner_iters,
                                                s->tv_p.as<float>(), s->tv_a.as<float>(), s->tv_b.as<float>(), st);
+                if (he == hipSuccess) he = refresh_xT(s, st);
                 if (he != hipSuccess) return he;
             }
         }
@@ -1700,6 +1720,10 @@ extern "C" bsgd_status bsgd_step_batch(bsgd_solver* const* solvers, int32_t n, i
         for (int i = 0; i < n; ++i) solvers[i]->failed = true;
         return e;
     };
+    for (int i = 0; i < n; ++i) {  // the caller may have changed x since the last call
+        const hipError_t he = refresh_xT(solvers[i], st);
+        if (he != hipSuccess) return mark_failed(fail(BSGD_E_DEVICE, "transpose of x: %s", hipGetErrorString(he)));
+    }
     // one effective epoch from an epoch boundary of every solver, graphs allowed: replay
     // (or capture) the set's graph
     bool graph_ok = true;

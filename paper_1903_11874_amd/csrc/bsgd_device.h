@@ -94,7 +94,9 @@ struct DevGeom {
     // projects to in one view, the size of its LDS staging per view; 0 = no staging
     int32_t bp3_kmax, bp3_lmax;
     int32_t bp3_steep;  // some ray's chord through a voxel column can meet two z planes
-    int32_t pad_;
+    // every block spans fewer than 2^29 voxels of x, so the global 3D forward walk's
+    // offsets of nonzero steps fit the byte range (below 2^31) of a buffer load
+    int32_t fp_buf;
 };
 
 // Sub-detector s covers u in [k0, k1), v in [l0, l1).
@@ -443,12 +445,16 @@ __device__ __forceinline__ bool slab_3d(const Ray& R, const int (&nb)[3], const 
 
 // The 3D form of walk_2d_range_wave: Siddon order with ties crossing x, then y, then
 // z (as walk_block); the m-th later crossing of an axis is fmaf(m, v |inv|, t_first);
-// wave-uniform trip count from the crossings each lane's range can hold; offsets
-// off = iz sz + iy sy + ix clamped into the block. All 64 lanes must be active.
+// wave-uniform trip count from the crossings each lane's range can hold. load(off)
+// gets the element offset off = iz sz + iy sy + ix sx from the block's first voxel (sx =
+// 1 for x stored fastest, the y extent of x for the copy stored y fastest); for
+// steps of zero length (past a ray's exit, or a lane without a ray) off may lie outside
+// the block or wrap, and load must then return any finite value (it is multiplied by
+// zero). All 64 lanes must be active.
 template <class Load>
 __device__ __forceinline__ float walk_3d_range_wave(const Ray& R, const int (&nb)[3], const float (&h)[3],
-                                                    const float (&vs)[3], int sy, int sz, float t0, float t1,
-                                                    bool live, Load&& load)
+                                                    const float (&vs)[3], int sx_, int sy, int sz, float t0,
+                                                    float t1, bool live, Load&& load)
 {
     live = live && (t0 < t1);
     int ix = 0, iy = 0, iz = 0, sx = 0, sy_ = 0, sz_ = 0;
@@ -471,23 +477,26 @@ __device__ __forceinline__ float walk_3d_range_wave(const Ray& R, const int (&nb
     const int n = live ? (int)fminf(nxf + nyf + nzf + 5.0f, cap) : 0;
     const int n_wave = wave_max_int(n);
     float mx = 0.0f, my = 0.0f, mz = 0.0f, tx = tx0, ty = ty0, tz = tz0;
-    const int dox = sx, doy = sy_ * sy, doz = sz_ * sz;
-    const unsigned last = (unsigned)((nb[2] - 1) * sz + (nb[1] - 1) * sy + nb[0] - 1);
-    int off = iz * sz + iy * sy + ix;
+    const int dox = sx * sx_, doy = sy_ * sy, doz = sz_ * sz;
+    int off = iz * sz + iy * sy + ix * sx_;
     float t = t0, acc = 0.0f;
     // WALK_UNROLL steps at a time: their voxel offsets and lengths first (the stepping
     // never depends on loaded values), then the gathers back to back, then the FMAs in
-    // step order (the same sum as one step at a time).
+    // step order (the same sum as one step at a time). The crossing axis is the one whose
+    // next crossing equals the minimum (ties: x, then y, then z).
     int it = 0;
     for (; it + WALK_UNROLL <= n_wave; it += WALK_UNROLL) {
         unsigned o[WALK_UNROLL];
         float dt[WALK_UNROLL], v[WALK_UNROLL];
 #pragma unroll
         for (int u = 0; u < WALK_UNROLL; ++u) {
-            const bool cx = (tx <= ty) && (tx <= tz);
-            const bool cy = !cx && (ty <= tz);
-            const float tm = fminf(fminf(fminf(tx, ty), tz), t1);
-            o[u] = min((unsigned)off, last);
+            const float m3 = fminf(fminf(tx, ty), tz);
+            const bool cx = tx == m3;
+            const bool cy = !cx && ty == m3;
+            const float tm = fminf(m3, t1);
+            // a step of zero length (past the ray's exit) reads the block's first voxel,
+            // so finished lanes share one cache line instead of wandering along their rays
+            o[u] = tm > t ? (unsigned)off : 0u;
             dt[u] = tm - t;
             t = tm;
             off += cx ? dox : (cy ? doy : doz);
@@ -504,10 +513,11 @@ __device__ __forceinline__ float walk_3d_range_wave(const Ray& R, const int (&nb
         for (int u = 0; u < WALK_UNROLL; ++u) acc = fmaf(dt[u], v[u], acc);
     }
     for (; it < n_wave; ++it) {
-        const bool cx = (tx <= ty) && (tx <= tz);
-        const bool cy = !cx && (ty <= tz);
-        const float tm = fminf(fminf(fminf(tx, ty), tz), t1);
-        acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
+        const float m3 = fminf(fminf(tx, ty), tz);
+        const bool cx = tx == m3;
+        const bool cy = !cx && ty == m3;
+        const float tm = fminf(m3, t1);
+        acc = fmaf(tm - t, load(tm > t ? (unsigned)off : 0u), acc);
         t = tm;
         off += cx ? dox : (cy ? doy : doz);
         mx += cx ? 1.0f : 0.0f;

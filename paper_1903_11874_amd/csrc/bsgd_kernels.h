@@ -45,6 +45,7 @@ struct BatchEntry {
     const PairWork* work;  // work records of this call
     const float* y;
     float* x;
+    float* xT;             // copy of x stored y fastest (3D global-memory walk), or NULL
     float* z;
     float* ghat;
     float* gsum;
@@ -94,17 +95,21 @@ hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, in
                        const uint32_t* q, int64_t im_until, int8_t* draws, PairWork* work, hipStream_t st);
 
 // blocks_sel: the iteration's selected blocks (device, inside its schedule record).
+// xT: the copy of x stored y fastest ([z][x][y]) for the 3D global-memory walk, or NULL.
 hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,
-                           const float* x, float* z, hipStream_t st);
+                           const float* x, const float* xT, float* z, hipStream_t st);
 
 hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const float* y,
                         const float* z, float* r_sel, hipStream_t st);
 
 // delta == NULL: per-row-block memories ghat (Algorithm 1); else the sub-detector memory
 // form, reading the residual changes `delta` (z layout) and leaving ghat alone.
+// xT (3D, or NULL): the copy of x stored y fastest, kept equal to x for the voxels updated.
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
-                          const float* r_sel, const float* delta, float* ghat, float* gsum, float* x,
+                          const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, float* xT,
                           const float* mu, int64_t n_vox, hipStream_t st);
+// xT[(z nx + x) ny + y] = x[(z ny + y) nx + x]: the copy of x stored y fastest.
+hipError_t launch_xy_transpose(const float* x, float* xT, int nx, int ny, int nz, hipStream_t st);
 
 // delta = r - rho and rho = r over every selected pair's pixel range (z layout).
 hipError_t launch_subdet_delta(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,

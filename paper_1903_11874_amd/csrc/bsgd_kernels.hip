@@ -366,7 +366,8 @@ __global__ __launch_bounds__(WG) void k_plan(DevGeom G, const int32_t* __restric
 template <int DIM>
 __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork* __restrict__ work, SchedLayout L,
                                                const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
-                                               float* __restrict__ z, int wave, int lane)
+                                               const float* __restrict__ xT, float* __restrict__ z, int wave,
+                                               int lane)
 {
     const int wpp = max(1, G.fp_wpp);
     const int pair = wave / wpp, w = wave - pair * wpp;
@@ -375,15 +376,25 @@ __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork*
     const PairWork W = work[pair];
     const int wk = W.k1 - W.k0, wl = W.l1 - W.l0;
     if (wk <= 0 || wl <= 0) return;
-    constexpr int PX = DIM == 3 ? 8 : 64, PY = 64 / PX;
+    constexpr int PX = DIM == 3 ? 16 : 64, PY = 64 / PX;
     const int npx = (wk + PX - 1) / PX, n_patch = npx * ((wl + PY - 1) / PY);
     if (n_patch <= w) return;
     const BlockInfo B = G.blocks[blocks_sel[b]];
-    const float* xb = x + ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
-    const int sy = G.nx, sz = G.nx * G.ny;
+    // rays running closer to x than to y sit side by side in y: they gather from the copy
+    // of x stored y fastest ([z][x][y]), where a patch's neighbouring rays read
+    // neighbouring floats (x stored x fastest would put each on its own cache line)
+    const bool tr = DIM == 3 && xT != nullptr && fabsf(W.c) >= fabsf(W.s);
+    const int64_t xbase = tr ? ((int64_t)B.z0 * G.nx + B.x0) * (int64_t)G.ny + B.y0
+                             : ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
+    const float* xb = (tr ? xT : x) + xbase;
+    const int sx = tr ? G.ny : 1, sy = tr ? 1 : G.nx, sz = G.nx * G.ny;
     int nb[3];
     float h[3], vs[3];
     block_dims(G, B, nb, h, vs);
+    const unsigned last = (unsigned)((nb[2] - 1) * sz + (nb[1] - 1) * sy + (nb[0] - 1) * sx);
+    const int64_t rem = ((int64_t)G.nx * G.ny * G.nz - xbase) * (int64_t)sizeof(float);
+    const __amdgpu_buffer_rsrc_t xr =
+        __builtin_amdgcn_make_buffer_rsrc((void*)xb, (short)0, (int)min(rem, (int64_t)0x7fffffff), 0x00020000);
     const int rounds = (n_patch - w + wpp - 1) / wpp;
     for (int r = 0; r < rounds; ++r) {
         const int pt = w + wpp * r;
@@ -398,7 +409,16 @@ __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork*
             acc = walk_2d_range_wave(R, nb, h, vs, sy, tlo, thi, hit, [&](unsigned off) { return xb[off]; });
         } else {
             const bool hit = on && slab_3d(R, nb, h, vs, tlo, thi);
-            acc = walk_3d_range_wave(R, nb, h, vs, sy, sz, tlo, thi, hit, [&](unsigned off) { return xb[off]; });
+            if (G.fp_buf) {
+                // raw buffer loads: a 32-bit byte offset from the block's first voxel and a
+                // range that ends with x, past which loads return 0
+                acc = walk_3d_range_wave(R, nb, h, vs, sx, sy, sz, tlo, thi, hit, [&](unsigned off) {
+                    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, off << 2, 0, 0));
+                });
+            } else {
+                acc = walk_3d_range_wave(R, nb, h, vs, sx, sy, sz, tlo, thi, hit,
+                                         [&](unsigned off) { return xb[min(off, last)]; });
+            }
         }
         if (on) z[W.zbase + (int64_t)l * W.zw + k] = acc * R.len;
     }
@@ -407,11 +427,27 @@ __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork*
 template <int DIM>
 __global__ __launch_bounds__(WG) void k_fp_pairs(DevGeom G, const PairWork* __restrict__ work, SchedLayout L,
                                                  const int32_t* __restrict__ blocks_sel, const float* __restrict__ x,
-                                                 float* __restrict__ z)
+                                                 const float* __restrict__ xT, float* __restrict__ z)
 {
     const int wg = xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int wave = __builtin_amdgcn_readfirstlane(wg * (WG / 64) + (threadIdx.x >> 6));
-    fp_global_body<DIM>(G, work, L, blocks_sel, x, z, wave, threadIdx.x & 63);
+    fp_global_body<DIM>(G, work, L, blocks_sel, x, xT, z, wave, threadIdx.x & 63);
+}
+
+// The copy of x stored y fastest: xT[(z nx + x) ny + y] = x[(z ny + y) nx + x], through a
+// padded 32 x 32 LDS tile per (x tile, y tile, z).
+__global__ __launch_bounds__(WG) void k_xy_transpose(const float* __restrict__ x, float* __restrict__ xT, int nx,
+                                                     int ny)
+{
+    __shared__ float t[32][33];
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    const int64_t zoff = (int64_t)blockIdx.z * nx * ny;
+    const int c = threadIdx.x % 32, r0 = threadIdx.x / 32;
+    for (int r = r0; r < 32; r += WG / 32)
+        if (x0 + c < nx && y0 + r < ny) t[r][c] = x[zoff + (int64_t)(y0 + r) * nx + x0 + c];
+    __syncthreads();
+    for (int r = r0; r < 32; r += WG / 32)
+        if (y0 + c < ny && x0 + r < nx) xT[zoff + (int64_t)(x0 + r) * ny + y0 + c] = t[c][r];
 }
 
 constexpr int FP_MAX_CHUNK = 16;
@@ -1243,8 +1279,8 @@ __device__ __forceinline__ void bp3_step_body(const DevGeom& G, const int32_t* _
                                               const PairWork* __restrict__ work, SchedLayout L,
                                               const float* __restrict__ src, float* __restrict__ ghat,
                                               float* __restrict__ gsum, float* __restrict__ x,
-                                              const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
-                                              float* lds)
+                                              float* __restrict__ xT, const float* __restrict__ mu_ptr,
+                                              long long n_vox, int bx, int by, float* lds)
 {
     const int b = by;
     const int j = S_[L.off_blocks() + b];
@@ -1292,8 +1328,24 @@ __device__ __forceinline__ void bp3_step_body(const DevGeom& G, const int32_t* _
                 const int64_t vox = vox0 + iz * plane;
                 const float gv = gsum[vox] + dg[iz];
                 gsum[vox] = gv;
-                x[vox] = fmaf(mu, gv, x[vox]);
+                const float xv = fmaf(mu, gv, x[vox]);
+                x[vox] = xv;
+                // staged for the copy of x stored y fastest (each thread's own slots of
+                // the accumulator rows, which it no longer reads)
+                if (xT) acc[iz * BP3_WG + threadIdx.x] = xv;
             }
+        }
+    }
+    if (xT) {  // uniform
+        // the tile's new values into xT, threads over (x, y) with y fastest
+        __syncthreads();
+        const int ty = (int)threadIdx.x % BP3_TY, tx = (int)threadIdx.x / BP3_TY;
+        if (tx0 + tx < B.nbx && ty0 + ty < B.nby) {
+            const int64_t t0 =
+                ((int64_t)(B.z0 + zc0) * G.nx + (B.x0 + tx0 + tx)) * (int64_t)G.ny + (B.y0 + ty0 + ty);
+#pragma unroll
+            for (int iz = 0; iz < BP3_CZ; ++iz)
+                if (iz < nzc) xT[t0 + iz * plane] = acc[iz * BP3_WG + ty * BP3_TX + tx];
         }
     }
 }
@@ -1306,8 +1358,8 @@ template <int DIM, bool SUB>
 __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
                                                 SchedLayout L, const float* __restrict__ src,
                                                 float* __restrict__ ghat, float* __restrict__ gsum,
-                                                float* __restrict__ x, const float* __restrict__ mu,
-                                                long long n_vox)
+                                                float* __restrict__ x, float* __restrict__ xT,
+                                                const float* __restrict__ mu, long long n_vox)
 {
     int bx, by;
     xcd_grid2(bx, by);
@@ -1316,7 +1368,7 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t
         bp_step_body_2d<SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
     } else {
         extern __shared__ float bp3_lds[];
-        bp3_step_body<SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, bp3_lds);
+        bp3_step_body<SUB>(G, S_, work, L, src, ghat, gsum, x, xT, mu, n_vox, bx, by, bp3_lds);
     }
 }
 
@@ -1384,7 +1436,7 @@ __global__ __launch_bounds__(TPB) void k_fp_batch(const BatchArgs A)
                                   local / B.gx[0], xs, sh);
     } else if (!B.fp_lds) {
         const int wave = __builtin_amdgcn_readfirstlane(local * (TPB / 64) + (threadIdx.x >> 6));
-        fp_global_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.z, wave, threadIdx.x & 63);
+        fp_global_body<DIM>(B.G, W, B.L, S_ + B.L.off_blocks(), B.x, B.xT, B.z, wave, threadIdx.x & 63);
     }
 }
 
@@ -1415,7 +1467,7 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_batch(const BatchArgs A)
                                local / B.gx[2], part);
     } else {
         extern __shared__ float bp3_lds[];
-        bp3_step_body<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
+        bp3_step_body<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.xT, B.mu, B.n_vox, local % B.gx[2],
                              local / B.gx[2], bp3_lds);
     }
 }
@@ -1791,7 +1843,7 @@ static int fp_tile_floats(const DevGeom& G)
 }
 
 hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,
-                           const float* x, float* z, hipStream_t st)
+                           const float* x, const float* xT, float* z, hipStream_t st)
 {
     const int tile = fp_tile_floats(G);
     if (tile <= FP_LDS_MAX_FLOATS) {
@@ -1809,9 +1861,17 @@ hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayou
     const int64_t waves = (int64_t)L.maxv * L.B * std::max(1, G.fp_wpp);
     const unsigned blocks = (unsigned)((waves + 3) / 4);
     if (G.dim == 3)
-        hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, z);
+        hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, xT, z);
     else
-        hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, z);
+        hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, nullptr, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_xy_transpose(const float* x, float* xT, int nx, int ny, int nz, hipStream_t st)
+{
+    if ((int64_t)nx * ny * nz == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xy_transpose, dim3((unsigned)((nx + 31) / 32), (unsigned)((ny + 31) / 32), (unsigned)nz),
+                       dim3(WG), 0, st, x, xT, nx, ny);
     return hipGetLastError();
 }
 
@@ -1911,9 +1971,10 @@ static int step_tiles(const DevGeom& G)
 static size_t bp_lds_bytes(const DevGeom& G) { return G.dim == 3 ? bp3_lds_bytes(G) : 0; }
 
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
-                          const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, const float* mu,
-                          int64_t n_vox, hipStream_t st)
+                          const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, float* xT,
+                          const float* mu, int64_t n_vox, hipStream_t st)
 {
+    if (G.dim != 3) xT = nullptr;
     const int tiles = step_tiles(G);
     const dim3 grid(tiles, L.B), blk(bp_wg(G.dim));
     const long long nv = (long long)n_vox;
@@ -1921,16 +1982,16 @@ hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairW
     if (delta) {
         if (G.dim == 3)
             hipLaunchKernelGGL((k_bp_step<3, true>), grid, blk, lds, st, G, sched_it, work_it, L, delta, ghat, gsum, x,
-                               mu, nv);
+                               xT, mu, nv);
         else
             hipLaunchKernelGGL((k_bp_step<2, true>), grid, blk, 0, st, G, sched_it, work_it, L, delta, ghat, gsum, x,
-                               mu, nv);
+                               xT, mu, nv);
     } else if (G.dim == 3) {
         hipLaunchKernelGGL((k_bp_step<3, false>), grid, blk, lds, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
-                           mu, nv);
+                           xT, mu, nv);
     } else {
         hipLaunchKernelGGL((k_bp_step<2, false>), grid, blk, 0, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
-                           mu, nv);
+                           xT, mu, nv);
     }
     return hipGetLastError();
 }

@@ -110,3 +110,68 @@ def test_cone_blocks(tv):
     assert rel_l2(yfp, A @ xt.double().cpu().numpy()) <= TOL
     bp = geom.back_project(torch.tensor(y32, device=dev)).double().cpu().numpy()
     assert rel_l2(bp, A.T @ y64) <= TOL
+
+
+@pytest.mark.parametrize("mode", ["colnorm", "area"])
+def test_cone_blocks_importance_sampled(mode):
+    # the global-memory walk over one drawn sub-detector of each pair (its part of the
+    # pair's ray order), with both weightings; then the unbiased tail (every ray)
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver
+    dev = require_gpu()
+    g = CONE_BLOCKS.with_(im_mode=mode)
+    log(f"bench-shaped cone: 64x64x16 blocks, IM S=4 ({mode})")
+    p = oracle_problem(CONE_BLOCKS)
+    A, y64, y32 = _data(CONE_BLOCKS, 43)
+    mu = float(np.float32(0.5 / (2.0 * lipschitz(A))))
+    q = im_table(p, mode)
+    R, B = 1, 2
+    n = 3 * tv_period(g.n_row_blocks, g.n_blocks, R, B) + 1
+    tail = n - 2
+    trace = []
+    st = run(p, y64, mu, R, B, n, 53, q=q, trace=trace, im_until=tail)
+    geom = Geometry(g, im_table=q)
+    yd = torch.tensor(y32, device=dev)
+    xd = torch.zeros(A.shape[1], dtype=torch.float32, device=dev)
+    s = Solver(geom, yd, xd, node_count=2, mu=mu, seed=53, im_until=tail)
+    rn = s.step(n, residual=True)
+    _check_draws(p, trace, s)
+    assert any(v >= 1 for t in trace for v in t["draws"].values())
+    assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
+    assert abs(rn - np.linalg.norm(st.r)) <= TOL * np.linalg.norm(st.r)
+
+
+def test_cone_blocks_batched_warm_start():
+    # two 64x64x16-block cone solves from a nonzero image (the walk's copy of x stored y
+    # fastest must be built from it), one with TV: batched epochs (eager, captured,
+    # replayed) equal solo solves bit for bit, and both equal the oracle
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver, step_batch
+    dev = require_gpu()
+    g = CONE_BLOCKS
+    log("bench-shaped cone: batched epochs from a nonzero start")
+    p = oracle_problem(g)
+    geom = Geometry(g)
+    R, B = 1, 2
+    T = tv_period(g.n_row_blocks, g.n_blocks, R, B)
+    solves = []
+    for seed, tv in ((61, 0.0), (62, 1.0)):
+        A, y64, y32 = _data(g, seed)
+        mu = float(np.float32(0.5 / (2.0 * lipschitz(A))))
+        lam = tv * 0.01 / mu
+        x0 = (0.5 * phantom_for(g, 6, seed + 7)).astype(np.float32)
+        st = run(p, y64, mu, R, B, 3 * T, seed, x0=x0.astype(np.float64), tv_lambda=lam)
+        yd = torch.tensor(y32, device=dev)
+        pair = []
+        for _ in range(2):
+            x = torch.tensor(x0, device=dev)
+            pair.append((x, Solver(geom, yd, x, node_count=2, mu=mu, seed=seed, tv_lambda=lam, tv_inner_iters=20)))
+        solves.append((pair, st))
+    for _ in range(3):
+        step_batch([pair[0][1] for pair, _ in solves], T)
+    for pair, _ in solves:
+        pair[1][1].step(3 * T)
+    torch.cuda.synchronize()
+    for i, (pair, st) in enumerate(solves):
+        assert torch.equal(pair[0][0], pair[1][0]), i
+        assert rel_l2(pair[0][0].double().cpu().numpy(), st.x) <= TOL, i
