@@ -154,7 +154,8 @@ def write_traffic(d):
     """Write profiles/traffic.json from the rocprofv3 databases under d and print the
     per-kernel tables: d/copy_fetch, d/copy_write (FETCH_SIZE / WRITE_SIZE of the copy
     probe), and per workload w: d/w_trace (kernel trace), d/w_fetch, d/w_write, d/w_sq
-    (SQ_INSTS_VALU and other SQ counters). HBM bytes per dispatch are the KiB counters
+    (SQ_INSTS_VALU and other SQ counters) and, when present, d/w_ta (TA/TD busy cycles
+    summed over CUs, L2 hits and misses). HBM bytes per dispatch are the KiB counters
     scaled so that the 1 GiB copy reads and writes 1 GiB."""
     import glob
     import hashlib
@@ -196,6 +197,18 @@ def write_traffic(d):
                   f"| {q.get('SQ_INSTS_VALU', float('nan')):.3g} | {q.get('SQ_INSTS_SALU', float('nan')):.3g} "
                   f"| {q.get('SQ_INSTS_LDS', float('nan')):.3g} | {q.get('SQ_WAVES', float('nan')):.0f} | {wait:.2f} |")
         out["workloads"][w] = per
+        ta_dir = glob.glob(os.path.join(d, w + "_ta", "*_results.db"))
+        if ta_dir:
+            ta = _counters(ta_dir[0])
+            print("\n| kernel | TA busy per CU (us) | TD busy per CU (us) | L2 hit rate |\n|---|---|---|---|")
+            for k in sorted(ta):
+                if not k.startswith("k_"):
+                    continue
+                q = ta[k]
+                hits, miss = q.get("TCC_HIT_sum", 0.0), q.get("TCC_MISS_sum", 0.0)
+                rate = hits / (hits + miss) if hits + miss > 0 else float("nan")
+                print(f"| {k} | {q.get('TA_TA_BUSY_sum', float('nan')) / SIMDS * 4 / CLOCK_HZ * 1e6:.1f} "
+                      f"| {q.get('TD_TD_BUSY_sum', float('nan')) / SIMDS * 4 / CLOCK_HZ * 1e6:.1f} | {100 * rate:.1f}% |")
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

@@ -322,7 +322,8 @@ __device__ __forceinline__ float walk_2d_range(const Ray& R, const int (&nb)[3],
         for (int u = 0; u < WALK2_UNROLL; ++u) {
             const bool cx = tx <= ty;
             const float tm = fminf(fminf(tx, ty), t1);
-            o[u] = min((unsigned)off, last);
+            // zero-length steps (past the exit) read the block's first pixel
+            o[u] = tm > t ? min((unsigned)off, last) : 0u;
             dt[u] = tm - t;
             t = tm;
             off += cx ? dox : doy;
@@ -409,7 +410,7 @@ __device__ __forceinline__ float walk_2d_range_wave(const Ray& R, const int (&nb
     for (; it < n_wave; ++it) {
         const bool cx = tx <= ty;
         const float tm = fminf(fminf(tx, ty), t1);
-        acc = fmaf(tm - t, load(min((unsigned)off, last)), acc);
+        acc = fmaf(tm - t, load(tm > t ? min((unsigned)off, last) : 0u), acc);
         t = tm;
         off += cx ? dox : doy;
         mx += cx ? 1.0f : 0.0f;
