@@ -157,12 +157,21 @@ bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* 
  * projection through a block, 1, 2 or 4 (default 1): the chord is cut into that many
  * equal parameter segments, walked in parallel and summed in a fixed order, so
  * results depend on it only through FP32 rounding and are reproducible for a given
- * value (3D rays are never split). Solvers read both at each launch; a solver that
- * already captured its epoch graph keeps the shape it captured. reserved must be 0. */
+ * value (3D rays are never split). fp_waves_per_pair: waves of the global-memory
+ * forward walk (blocks too large for the LDS stage) per (view, block) pair, in [1, 64]
+ * (default from the mean footprint); it does not change any result; 0 in
+ * bsgd_geometry_set_tuning keeps the current value. fp_staged (filled by
+ * bsgd_geometry_get_tuning, ignored by set): 1 when the forward projector stages
+ * blocks in LDS (fp_views_per_group and fp_ray_split apply), 0 when it walks global
+ * memory (fp_waves_per_pair applies). Solvers read the shape at each launch; a solver
+ * that already captured its epoch graph keeps the shape it captured. reserved must
+ * be 0. */
 typedef struct {
     int32_t fp_views_per_group;
     int32_t fp_ray_split;
-    int32_t reserved[6];
+    int32_t fp_waves_per_pair;
+    int32_t fp_staged;
+    int32_t reserved[4];
 } bsgd_tuning;
 bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* geom, const bsgd_tuning* tuning);
 bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* geom, bsgd_tuning* tuning);

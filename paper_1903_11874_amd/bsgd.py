@@ -78,7 +78,8 @@ class Options(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fp_views_per_group", ctypes.c_int32), ("fp_ray_split", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("fp_waves_per_pair", ctypes.c_int32), ("fp_staged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 EXPORTED = (
@@ -252,14 +253,26 @@ class Geometry:
         _check(load_library().bsgd_geometry_get_tuning(self._h, ctypes.byref(t)))
         return t
 
-    def set_tuning(self, fp_views_per_group: Optional[int] = None, fp_ray_split: Optional[int] = None):
+    def set_tuning(self, fp_views_per_group: Optional[int] = None, fp_ray_split: Optional[int] = None,
+                   fp_waves_per_pair: Optional[int] = None):
         """Launch shape of the forward projector (bsgd_geometry_set_tuning)."""
         t = self._get_tuning()
         if fp_views_per_group is not None:
             t.fp_views_per_group = int(fp_views_per_group)
         if fp_ray_split is not None:
             t.fp_ray_split = int(fp_ray_split)
+        if fp_waves_per_pair is not None:
+            t.fp_waves_per_pair = int(fp_waves_per_pair)
         _check(load_library().bsgd_geometry_set_tuning(self._h, ctypes.byref(t)))
+
+    @property
+    def fp_waves_per_pair(self) -> int:
+        return self._get_tuning().fp_waves_per_pair
+
+    @property
+    def fp_staged(self) -> bool:
+        """True when the forward projector stages blocks in LDS."""
+        return bool(self._get_tuning().fp_staged)
 
     @property
     def fp_views_per_group(self) -> int:

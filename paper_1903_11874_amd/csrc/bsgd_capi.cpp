@@ -915,10 +915,13 @@ extern "C" bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* g, const bsgd_tun
         return fail(BSGD_E_INVALID_ARG, "fp_views_per_group must be in [1, %d]", FP_CHUNK_MAX);
     if (t->fp_ray_split != 1 && t->fp_ray_split != 2 && t->fp_ray_split != 4)
         return fail(BSGD_E_INVALID_ARG, "fp_ray_split must be 1, 2 or 4");
-    for (int i = 0; i < 6; ++i)
+    if (t->fp_waves_per_pair < 0 || t->fp_waves_per_pair > 64)
+        return fail(BSGD_E_INVALID_ARG, "fp_waves_per_pair must be in [1, 64] (0 keeps the current value)");
+    for (int i = 0; i < 4; ++i)
         if (t->reserved[i] != 0) return fail(BSGD_E_INVALID_ARG, "reserved tuning fields must be 0");
     g->dg.fp_chunk = t->fp_views_per_group;
     g->dg.fp_split = t->fp_ray_split;
+    if (t->fp_waves_per_pair > 0) g->dg.fp_wpp = t->fp_waves_per_pair;
     return BSGD_OK;
 }
 
@@ -928,6 +931,8 @@ extern "C" bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* g, bsgd_tun
     std::memset(t, 0, sizeof *t);
     t->fp_views_per_group = g->dg.fp_chunk;
     t->fp_ray_split = g->dg.fp_split;
+    t->fp_waves_per_pair = g->dg.fp_wpp;
+    t->fp_staged = fp_lds_bytes_for(g->dg) > 0 ? 1 : 0;
     return BSGD_OK;
 }
 

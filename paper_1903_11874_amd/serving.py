@@ -145,7 +145,7 @@ class Server:
             if tune:
                 y0 = torch.zeros(geom.info["n_rays"], dtype=torch.float32, device="cuda")
                 timings = autotune(geom, y0, node_count=node_count, mu=mu_of(spec), epochs=1, stream=self.stream)
-                shapes[spec] = (geom.fp_views_per_group, geom.fp_ray_split, min(timings.values()))
+                shapes[spec] = (min(timings, key=timings.get), min(timings.values()))
         return shapes
 
     def _fits(self, geom: Geometry, node_count: int) -> bool:

@@ -399,6 +399,36 @@ def test_autotuner_shapes_do_not_change_results():
         assert rel_l2(outs[(1, sp)].double().cpu().numpy(), outs[(1, 1)].double().cpu().numpy()) < 1e-5
 
 
+@pytest.mark.parametrize("name", ["fan_wide", "cone_wide"])
+def test_autotuner_waves_per_pair_of_the_global_walk(name):
+    # blocks too large for the LDS stage: the tuner searches waves per (view, block)
+    # pair, which only regroups the rays among waves, so every shape gives the same bits
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver
+    from paper_1903_11874_amd.tuning import autotune
+    dev = require_gpu()
+    log(f"autotuner, global walk {name}")
+    g = SMALL[name]
+    A, x_true, y64, y32 = _data(g)
+    mu = _mu(A, 0.3)
+    geom = Geometry(g)
+    assert not geom.fp_staged
+    yd = torch.tensor(y32, device=dev)
+    timings = autotune(geom, yd, node_count=4, mu=mu, waves=(1, 3, 16), epochs=1)
+    assert set(timings) == {(1,), (3,), (16,)}
+    assert (geom.fp_waves_per_pair,) in timings
+    outs = []
+    for w in (1, 2, 5, 64):
+        geom.set_tuning(fp_waves_per_pair=w)
+        assert geom.fp_waves_per_pair == w
+        x = torch.zeros(A.shape[1], device=dev)
+        Solver(geom, yd, x, node_count=4, mu=mu, seed=5, eager=True).step(12)
+        outs.append(x)
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
+    with pytest.raises(Exception):
+        geom.set_tuning(fp_waves_per_pair=65)
+
+
 @pytest.mark.parametrize("scale,eager", [(2.0, True), (0.05, False)])
 def test_auto_step_length_matches_oracle(scale, eager):
     """Algorithm 3: the same step-length decisions as the oracle, and the iterate."""
