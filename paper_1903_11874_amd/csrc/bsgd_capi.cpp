@@ -1016,7 +1016,7 @@ struct bsgd_solver {
     SchedLayout L{};
     DevBuf z, ghat, gsum, r_sel, sched, draws, work, partials, norm_out, tv_p, tv_a, tv_b;
     DevBuf rho, delta;  // sub-detector memory: residual snapshots and their changes (z layout)
-    // 3D global-memory forward walk: x stored y fastest ([z][x][y]), refreshed from x at the
+    // global-memory forward walk: x stored y fastest ([z][x][y]), refreshed from x at the
     // start of every step call and after every TV prox, and written with x by the back
     // projection in between; unallocated otherwise
     DevBuf xT;
@@ -1196,7 +1196,7 @@ static bsgd_status solver_create(const bsgd_geometry* g, const float* y, float* 
         S_TRY(s->ghat.alloc((size_t)g->M * g->n_vox * sizeof(float)));
     }
     S_TRY(s->gsum.alloc((size_t)g->n_vox * sizeof(float)));
-    if (g->dim == 3 && fp_lds_bytes_for(g->dg) == 0) S_TRY(s->xT.alloc((size_t)g->n_vox * sizeof(float)));
+    if (fp_lds_bytes_for(g->dg) == 0) S_TRY(s->xT.alloc((size_t)g->n_vox * sizeof(float)));
     // 2D: one {w2, slope, lmax, r} record per selected ray; 3D: the residual
     S_TRY(s->r_sel.alloc((size_t)s->maxv * per_view * (g->dim == 2 ? 4 : 1) * sizeof(float)));
     const int n_part = (int)(((per_view + 255) / 256) * g->d.n_views);

@@ -353,11 +353,12 @@ __device__ __forceinline__ int wave_max_int(int v)
 // active: each lane bounds its pixel count by the plane crossings its parameter range
 // can hold, the wave loops to the largest bound on a scalar counter, and a lane past
 // its end adds zero-length steps (tm = t = t1). No per-lane exit, so no exec-mask
-// bookkeeping per step. live = false gives 0.
+// bookkeeping per step. live = false gives 0. Offsets are iy sy + ix sx_ from the
+// block's first pixel (sx_ = 1 for x stored fastest, the y extent for x stored y fastest).
 template <class Load>
 __device__ __forceinline__ float walk_2d_range_wave(const Ray& R, const int (&nb)[3], const float (&h)[3],
-                                                    const float (&vs)[3], int sy, float t0, float t1, bool live,
-                                                    Load&& load)
+                                                    const float (&vs)[3], int sx_, int sy, float t0, float t1,
+                                                    bool live, Load&& load)
 {
     live = live && (t0 < t1);
     int ix = 0, iy = 0, sx = 0, sy_ = 0;
@@ -379,9 +380,9 @@ __device__ __forceinline__ float walk_2d_range_wave(const Ray& R, const int (&nb
     const int n = live ? (int)fminf(nxf + nyf + 4.0f, cap) : 0;
     const int n_wave = wave_max_int(n);
     float mx = 0.0f, my = 0.0f, tx = tx0, ty = ty0;
-    const int dox = sx, doy = sy_ * sy;
-    const unsigned last = (unsigned)((nb[1] - 1) * sy + nb[0] - 1);
-    int off = iy * sy + ix;
+    const int dox = sx * sx_, doy = sy_ * sy;
+    const unsigned last = (unsigned)((nb[1] - 1) * sy + (nb[0] - 1) * sx_);
+    int off = iy * sy + ix * sx_;
     float t = t0, acc = 0.0f;
     // WALK2_UNROLL steps at a time, as in walk_3d_range_wave: offsets and lengths, then
     // the loads, then the FMAs in step order

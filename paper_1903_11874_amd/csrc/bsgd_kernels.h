@@ -45,7 +45,7 @@ struct BatchEntry {
     const PairWork* work;  // work records of this call
     const float* y;
     float* x;
-    float* xT;             // copy of x stored y fastest (3D global-memory walk), or NULL
+    float* xT;             // copy of x stored y fastest (global-memory walk), or NULL
     float* z;
     float* ghat;
     float* gsum;
@@ -95,7 +95,7 @@ hipError_t launch_plan(const DevGeom& G, const int32_t* sched, SchedLayout L, in
                        const uint32_t* q, int64_t im_until, int8_t* draws, PairWork* work, hipStream_t st);
 
 // blocks_sel: the iteration's selected blocks (device, inside its schedule record).
-// xT: the copy of x stored y fastest ([z][x][y]) for the 3D global-memory walk, or NULL.
+// xT: the copy of x stored y fastest ([z][x][y]) for the global-memory walk, or NULL.
 hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayout L, const int32_t* blocks_sel,
                            const float* x, const float* xT, float* z, hipStream_t st);
 
@@ -104,7 +104,7 @@ hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L
 
 // delta == NULL: per-row-block memories ghat (Algorithm 1); else the sub-detector memory
 // form, reading the residual changes `delta` (z layout) and leaving ghat alone.
-// xT (3D, or NULL): the copy of x stored y fastest, kept equal to x for the voxels updated.
+// xT (or NULL): the copy of x stored y fastest, kept equal to x for the voxels updated.
 hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairWork* work_it, SchedLayout L,
                           const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, float* xT,
                           const float* mu, int64_t n_vox, hipStream_t st);

@@ -383,7 +383,7 @@ __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork*
     // rays running closer to x than to y sit side by side in y: they gather from the copy
     // of x stored y fastest ([z][x][y]), where a patch's neighbouring rays read
     // neighbouring floats (x stored x fastest would put each on its own cache line)
-    const bool tr = DIM == 3 && xT != nullptr && fabsf(W.c) >= fabsf(W.s);
+    const bool tr = xT != nullptr && fabsf(W.c) >= fabsf(W.s);
     const int64_t xbase = tr ? ((int64_t)B.z0 * G.nx + B.x0) * (int64_t)G.ny + B.y0
                              : ((int64_t)B.z0 * G.ny + B.y0) * (int64_t)G.nx + B.x0;
     const float* xb = (tr ? xT : x) + xbase;
@@ -406,7 +406,7 @@ __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork*
         float tlo = 0.0f, thi = 0.0f, acc;
         if (DIM == 2) {
             const bool hit = on && slab_2d(R, nb, h, vs, tlo, thi);
-            acc = walk_2d_range_wave(R, nb, h, vs, sy, tlo, thi, hit, [&](unsigned off) { return xb[off]; });
+            acc = walk_2d_range_wave(R, nb, h, vs, sx, sy, tlo, thi, hit, [&](unsigned off) { return xb[off]; });
         } else {
             const bool hit = on && slab_3d(R, nb, h, vs, tlo, thi);
             if (G.fp_buf) {
@@ -557,7 +557,7 @@ __device__ __forceinline__ void fp_lds_body(const DevGeom& G, const PairWork* __
             const float span = thi - tlo;
             const float t0 = seg == 0 ? tlo : fmaf((float)seg * invS, span, tlo);
             const float t1 = seg == S - 1 ? thi : fmaf((float)(seg + 1) * invS, span, tlo);
-            float acc = walk_2d_range_wave(R, nb, h, vs, rs, t0, t1, hit, [&](unsigned off) { return xs[off]; });
+            float acc = walk_2d_range_wave(R, nb, h, vs, 1, rs, t0, t1, hit, [&](unsigned off) { return xs[off]; });
             if (S >= 2) acc += __shfl_xor(acc, 1, 64);
             if (S >= 4) acc += __shfl_xor(acc, 2, 64);
             if (on && seg == 0) z[W.zbase + (int64_t)W.l0 * W.zw + k] = acc * R.len;
@@ -812,7 +812,8 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
                                                 const PairWork* __restrict__ work, SchedLayout L,
                                                 const float* __restrict__ src, float* __restrict__ ghat,
                                                 float* __restrict__ gsum, float* __restrict__ x,
-                                                const float* __restrict__ mu_ptr, long long n_vox, int bx, int by,
+                                                float* __restrict__ xT, const float* __restrict__ mu_ptr,
+                                                long long n_vox, int bx, int by,
                                                 float (&part)[BP_SPLIT_2D][2][BP_VOX])
 {
     const int b = by;
@@ -878,11 +879,17 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
         const float mu = *mu_ptr;
         const float gva = gsum[vox] + dga;
         gsum[vox] = gva;
-        x[vox] = fmaf(mu, gva, x[vox]);
+        const float xa = fmaf(mu, gva, x[vox]);
+        x[vox] = xa;
+        // the copy of x stored y fastest (a wave's lanes cover 8 rows of y per x)
+        const int64_t tvox = (int64_t)(B.x0 + li[0]) * G.ny + (B.y0 + li[1]);
+        if (xT) xT[tvox] = xa;
         if (b_ok) {
             const float gvb = gsum[vox + 1] + dgb;
             gsum[vox + 1] = gvb;
-            x[vox + 1] = fmaf(mu, gvb, x[vox + 1]);
+            const float xb = fmaf(mu, gvb, x[vox + 1]);
+            x[vox + 1] = xb;
+            if (xT) xT[tvox + G.ny] = xb;
         }
     }
 }
@@ -1365,7 +1372,7 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t
     xcd_grid2(bx, by);
     if constexpr (DIM == 2) {
         __shared__ float part[BP_SPLIT_2D][2][BP_VOX];
-        bp_step_body_2d<SUB>(G, S_, work, L, src, ghat, gsum, x, mu, n_vox, bx, by, part);
+        bp_step_body_2d<SUB>(G, S_, work, L, src, ghat, gsum, x, xT, mu, n_vox, bx, by, part);
     } else {
         extern __shared__ float bp3_lds[];
         bp3_step_body<SUB>(G, S_, work, L, src, ghat, gsum, x, xT, mu, n_vox, bx, by, bp3_lds);
@@ -1463,7 +1470,7 @@ __global__ __launch_bounds__(bp_wg(DIM)) void k_bp_batch(const BatchArgs A)
     const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
     if constexpr (DIM == 2) {
         __shared__ float part[BP_SPLIT_2D][2][BP_VOX];
-        bp_step_body_2d<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.mu, B.n_vox, local % B.gx[2],
+        bp_step_body_2d<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.xT, B.mu, B.n_vox, local % B.gx[2],
                                local / B.gx[2], part);
     } else {
         extern __shared__ float bp3_lds[];
@@ -1863,7 +1870,7 @@ hipError_t launch_fp_pairs(const DevGeom& G, const PairWork* work_it, SchedLayou
     if (G.dim == 3)
         hipLaunchKernelGGL(k_fp_pairs<3>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, xT, z);
     else
-        hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, nullptr, z);
+        hipLaunchKernelGGL(k_fp_pairs<2>, dim3(blocks), dim3(WG), 0, st, G, work_it, L, blocks_sel, x, xT, z);
     return hipGetLastError();
 }
 
@@ -1974,7 +1981,6 @@ hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairW
                           const float* r_sel, const float* delta, float* ghat, float* gsum, float* x, float* xT,
                           const float* mu, int64_t n_vox, hipStream_t st)
 {
-    if (G.dim != 3) xT = nullptr;
     const int tiles = step_tiles(G);
     const dim3 grid(tiles, L.B), blk(bp_wg(G.dim));
     const long long nv = (long long)n_vox;

@@ -16,7 +16,7 @@ from bsgd_inputs.configs import GeometrySpec
 from bsgd_inputs.phantoms import phantom_for, add_gaussian_noise
 from oracle.bsgd import run, lipschitz, im_table, tv_period
 
-from helpers import log, oracle_matrix, oracle_problem, rel_l2, require_gpu
+from helpers import SMALL, log, oracle_matrix, oracle_problem, rel_l2, require_gpu
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -141,17 +141,20 @@ def test_cone_blocks_importance_sampled(mode):
     assert abs(rn - np.linalg.norm(st.r)) <= TOL * np.linalg.norm(st.r)
 
 
-def test_cone_blocks_batched_warm_start():
-    # two 64x64x16-block cone solves from a nonzero image (the walk's copy of x stored y
-    # fastest must be built from it), one with TV: batched epochs (eager, captured,
-    # replayed) equal solo solves bit for bit, and both equal the oracle
+@pytest.mark.parametrize("name", ["cone_blocks", "fan_wide"])
+def test_global_walk_batched_warm_start(name):
+    # two solves whose blocks exceed the LDS stage (64x64x16 cone blocks; 131x130-pixel
+    # fan blocks) from a nonzero image (the walk's copy of x stored y fastest must be
+    # built from it), one with TV: batched epochs (eager, captured, replayed) equal solo
+    # solves bit for bit, and both equal the oracle
     import torch
     from paper_1903_11874_amd import Geometry, Solver, step_batch
     dev = require_gpu()
-    g = CONE_BLOCKS
-    log("bench-shaped cone: batched epochs from a nonzero start")
+    g = CONE_BLOCKS if name == "cone_blocks" else SMALL["fan_wide"]
+    log(f"global walk {name}: batched epochs from a nonzero start")
     p = oracle_problem(g)
     geom = Geometry(g)
+    assert not geom.fp_staged
     R, B = 1, 2
     T = tv_period(g.n_row_blocks, g.n_blocks, R, B)
     solves = []
