@@ -1024,6 +1024,18 @@ __device__ __forceinline__ float2 bp3_row(const DevGeom& G, const PairWork& W, i
     return make_float2(fmaf((float)(l - W.lc), W.av, W.bv), axis_fixed(iv) ? 1e30f : iv);
 }
 
+// Row record of the one-cut form (geometries where no chord through a voxel column
+// meets two z planes): {plane_pos(zc0 + up - 1) - z_l, 1/v_l}, up = 1 when the ray
+// rises with t. The plane between a ray's entry voxel e (column-local) and its exit
+// voxel is then at block-local height plane_pos(zc0 + e + up), and
+// (e + 1) v_z + x is that height minus z_l; e + 1 is the entry voxel's accumulator row.
+__device__ __forceinline__ float2 bp3_row_cut(const DevGeom& G, const PairWork& W, int l, int zc0, float hz)
+{
+    const float2 R = bp3_row(G, W, l);
+    const int up = R.y > 0.0f ? 1 : 0;
+    return make_float2(plane_pos(zc0 + up - 1, G.vz, hz) - R.x, R.y);
+}
+
 // r |d| of ray (k, l).
 __device__ __forceinline__ float bp3_rlen(const DevGeom& G, const PairWork& W, const float* p, int stride, int k, int l)
 {
@@ -1099,6 +1111,37 @@ __device__ __forceinline__ void bp3_column_view(const DevGeom& G, const PairWork
         if constexpr (STAGED) {
             rwp = rw + (llo - R.l0);
             tp = tile + (llo - R.l0) * w_tile + (k - R.k0);
+        }
+        if constexpr (STAGED && !STEEP) {
+            // One cut per row, at the plane beyond the entry voxel in the ray's z
+            // direction (rows staged by bp3_row_cut). Heights are kept one voxel up, so
+            // the clamped truncation is the accumulator row (voxel + 1; rows 0 and
+            // nzc + 1 are the spares). When entry and exit rows coincide the cut clamps
+            // to te or tx and the two pieces add to the whole chord: the exit piece is
+            // added first and the entry write, made last, carries both.
+            ue += 1.0f;
+            ux += 1.0f;
+            const float top = nzf + 1.0f;
+            float* const accp = acc + tid;
+            for (int l = llo; l <= lhi; ++l) {
+                const float2 Rw = *rwp++;
+                const float rl = *tp;
+                tp += w_tile;
+                const float fe = truncf(__builtin_amdgcn_fmed3f(ue, 0.0f, top));
+                const int re = (int)fe;
+                const int rx = (int)__builtin_amdgcn_fmed3f(ux, 0.0f, top);
+                ue += se;
+                ux += sx;
+                const float ts = __builtin_amdgcn_fmed3f(fmaf(fe, vz, Rw.x) * Rw.y, te, tx);
+                float* p0 = accp + re * BP3_WG;
+                float* p1 = accp + rx * BP3_WG;
+                const float v0 = *p0, v1 = *p1;
+                const float n1 = fmaf(tx - ts, rl, v1);
+                const float n0 = fmaf(ts - te, rl, re == rx ? n1 : v0);
+                *p1 = n1;
+                *p0 = n0;
+            }
+            continue;
         }
         for (int l = llo; l <= lhi; ++l) {
             float2 Rw;
@@ -1234,7 +1277,8 @@ __device__ __forceinline__ void bp3_accumulate(const DevGeom& G, const BlockInfo
                 if (e < wt)
                     kc[e] = bp3_kcol(G, W, r.k0 + e);
                 else
-                    rw[e - wt] = bp3_row(G, W, r.l0 + (e - wt));
+                    rw[e - wt] = G.bp3_steep ? bp3_row(G, W, r.l0 + (e - wt))
+                                             : bp3_row_cut(G, W, r.l0 + (e - wt), zc0, h[2]);
             }
             for (int e = threadIdx.x; e < wt * ht; e += BP3_WG) {
                 const int l = e / wt, k = e - l * wt;
