@@ -481,6 +481,25 @@ def serving_bench(reqs, truths, specs, mus, rate, max_slots, tol, max_epochs):
             "enqueue_s": sum(e[2] for e in server.log), "check_wait_s": sum(e[3] for e in server.log)}
 
 
+def serving_mode(reqs, specs, mus, rate, max_slots, tol, max_epochs, mode):
+    """One mode of the serving mix alone (for kernel traces of each mode): the server's
+    continuous batching or the plain per-solve loop, with serving_bench's settings."""
+    import dataclasses
+    import torch
+    from paper_1903_11874_amd.serving import Server, latency_stats
+    run_reqs = [dataclasses.replace(r, arrival=r.arrival / rate, tol=tol, max_epochs=max_epochs, check_every=5)
+                for r in reqs]
+    server = Server(max_slots=max_slots)
+    server.prepare(specs, node_count=64, mu_of=lambda g: mus[g])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = server.run(run_reqs) if mode == "batched" else server.run_sequential(run_reqs)
+    torch.cuda.synchronize()
+    st = latency_stats(res)
+    st["wall_s"] = time.perf_counter() - t0
+    return st
+
+
 def _line_of(m):
     T = m["iters_per_step"]
     return {"workload": m["workload"], "metric": "FP+BP ray-voxel updates/s", "value": m["value"],
@@ -513,6 +532,9 @@ def main():
     ap.add_argument("--tune", default="auto",
                     help="fan-beam forward-projector launch shape: 'auto' (autotuner, before the timed region) "
                          "or 'V,S' (views per workgroup, lanes per ray)")
+    ap.add_argument("--serving-only", choices=("batched", "sequential"), default=None,
+                    help="profiling aid: run only one mode of the serving mix at the last of --serving-rates "
+                         "and print its statistics")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -539,6 +561,14 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
         return
     n_prof = args.profile_steps if args.profile_steps > 0 else args.steps
+    if args.serving_only:
+        reqs, truths, specs, mus = serving_requests(args.serving)
+        rate = float(args.serving_rates.split(",")[-1])
+        st = serving_mode(reqs, specs, mus, rate, args.serving_slots, args.serving_tol, args.serving_max_epochs,
+                          args.serving_only)
+        print(json.dumps({"serving_mode": args.serving_only, "requests": len(reqs), "rate_per_s": rate, **st}),
+              flush=True)
+        return
     if args.fan_only:
         f = fan_bench(args.steps, args.warmup, n_prof, args.tune)
         line = _line_of(f)

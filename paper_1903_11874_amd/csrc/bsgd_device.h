@@ -448,8 +448,9 @@ __device__ __forceinline__ bool slab_3d(const Ray& R, const int (&nb)[3], const 
 // The 3D form of walk_2d_range_wave: Siddon order with ties crossing x, then y, then
 // z (as walk_block); the m-th later crossing of an axis is fmaf(m, v |inv|, t_first);
 // wave-uniform trip count from the crossings each lane's range can hold. load(off)
-// gets the element offset off = iz sz + iy sy + ix sx from the block's first voxel (sx =
-// 1 for x stored fastest, the y extent of x for the copy stored y fastest); for
+// gets the offset off = iz sz + iy sy + ix sx from the block's first voxel, in the units
+// of the strides passed (elements or bytes; sx is one element for x stored fastest, the
+// y extent of x for the copy stored y fastest); for
 // steps of zero length (past a ray's exit, or a lane without a ray) off may lie outside
 // the block or wrap, and load must then return any finite value (it is multiplied by
 // zero). All 64 lanes must be active.

@@ -410,10 +410,10 @@ __device__ __forceinline__ void fp_global_body(const DevGeom& G, const PairWork*
         } else {
             const bool hit = on && slab_3d(R, nb, h, vs, tlo, thi);
             if (G.fp_buf) {
-                // raw buffer loads: a 32-bit byte offset from the block's first voxel and a
-                // range that ends with x, past which loads return 0
-                acc = walk_3d_range_wave(R, nb, h, vs, sx, sy, sz, tlo, thi, hit, [&](unsigned off) {
-                    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, off << 2, 0, 0));
+                // raw buffer loads: the walk steps byte offsets from the block's first voxel
+                // (strides in bytes) and the range ends with x, past which loads return 0
+                acc = walk_3d_range_wave(R, nb, h, vs, 4 * sx, 4 * sy, 4 * sz, tlo, thi, hit, [&](unsigned off) {
+                    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xr, off, 0, 0));
                 });
             } else {
                 acc = walk_3d_range_wave(R, nb, h, vs, sx, sy, sz, tlo, thi, hit,
