@@ -497,6 +497,13 @@ def serving_mode(reqs, specs, mus, rate, max_slots, tol, max_epochs, mode):
     torch.cuda.synchronize()
     st = latency_stats(res)
     st["wall_s"] = time.perf_counter() - t0
+    if mode == "sequential":
+        # the loop serves one request at a time, so admission to completion is its service time
+        side = {r.rid: r.geometry.nx for r in run_reqs}
+        by = {}
+        for r in res:
+            by[side[r.rid]] = by.get(side[r.rid], 0.0) + (r.finished - r.admitted)
+        st["service_s_by_side"] = {str(k): v for k, v in sorted(by.items())}
     return st
 
 
