@@ -341,14 +341,16 @@ def fan_bench(steps, warmup, n_prof, tune="auto"):
         tt = autotune(geom, yd, node_count=64, mu=mu, epochs=2, seed=wl.solver.seed)
         log("fan: autotune " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in sorted(tt.items(), key=lambda kv: kv[1])[:4]))
     else:
-        v_, s_ = (int(t) for t in tune.split(","))
-        geom.set_tuning(fp_views_per_group=v_, fp_ray_split=s_)
+        parts = [int(t) for t in tune.split(",")]
+        geom.set_tuning(fp_views_per_group=parts[0], fp_ray_split=parts[1],
+                        bp_waves=parts[2] if len(parts) > 2 else None)
     x = torch.zeros(n_vox, dtype=torch.float32, device="cuda")
     solver = Solver(geom, yd, x, node_count=64, mu=mu, seed=wl.solver.seed)
     m = measure(geom, spec, solver, n_vox, warmup, steps, n_prof, wl.name)
     m.update(workload=wl.description, spec=spec, rows_per_iter=solver.rows_per_iter,
              blocks_per_iter=solver.blocks_per_iter, iters_per_step=solver.epoch_iters, nnz=geom.info["nnz"],
-             fp_views_per_group=geom.fp_views_per_group, fp_ray_split=geom.fp_ray_split, x_true=x_true,
+             fp_views_per_group=geom.fp_views_per_group, fp_ray_split=geom.fp_ray_split, bp_waves=geom.bp_waves,
+             x_true=x_true,
              groups=geom.groups())
     return m
 
@@ -537,8 +539,8 @@ def main():
     ap.add_argument("--fan-only", action="store_true",
                     help="profiling aid: run only the fan-beam measurement and print its line")
     ap.add_argument("--tune", default="auto",
-                    help="fan-beam forward-projector launch shape: 'auto' (autotuner, before the timed region) "
-                         "or 'V,S' (views per workgroup, lanes per ray)")
+                    help="fan-beam launch shapes: 'auto' (autotuner, before the timed region) or 'V,S[,W]' "
+                         "(views per forward-projection workgroup, lanes per ray, back-projection waves)")
     ap.add_argument("--serving-only", choices=("batched", "sequential"), default=None,
                     help="profiling aid: run only one mode of the serving mix at the last of --serving-rates "
                          "and print its statistics")
@@ -579,7 +581,7 @@ def main():
     if args.fan_only:
         f = fan_bench(args.steps, args.warmup, n_prof, args.tune)
         line = _line_of(f)
-        line.update(fp_views_per_group=f["fp_views_per_group"], fp_ray_split=f["fp_ray_split"])
+        line.update(fp_views_per_group=f["fp_views_per_group"], fp_ray_split=f["fp_ray_split"], bp_waves=f["bp_waves"])
         print(json.dumps(line), flush=True)
         return
     c = cone_bench(args.steps, args.warmup, n_prof)
@@ -620,6 +622,7 @@ def main():
         out["secondary"] = _line_of(f)
         out["secondary"]["fp_views_per_group"] = f["fp_views_per_group"]
         out["secondary"]["fp_ray_split"] = f["fp_ray_split"]
+        out["secondary"]["bp_waves"] = f["bp_waves"]
         fan_spec = f["spec"]
         del f
         torch.cuda.empty_cache()

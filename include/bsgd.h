@@ -163,15 +163,20 @@ bsgd_status bsgd_geometry_table(const bsgd_geometry* geom, int32_t which, void* 
  * bsgd_geometry_set_tuning keeps the current value. fp_staged (filled by
  * bsgd_geometry_get_tuning, ignored by set): 1 when the forward projector stages
  * blocks in LDS (fp_views_per_group and fp_ray_split apply), 0 when it walks global
- * memory (fp_waves_per_pair applies). Solvers read the shape at each launch; a solver
- * that already captured its epoch graph keeps the shape it captured. reserved must
- * be 0. */
+ * memory (fp_waves_per_pair applies). bp_waves: waves of a 2D back-projection
+ * workgroup, 2, 4 or 8 (default 4): each wave gathers a share of the views into the
+ * tile's voxels and the shares are added in a fixed order, so results depend on it only
+ * through FP32 rounding and are reproducible for a given value; 0 in
+ * bsgd_geometry_set_tuning keeps the current value; 3D geometries ignore it. Solvers
+ * read the shape at each launch; a solver that already captured its epoch graph keeps
+ * the shape it captured. reserved must be 0. */
 typedef struct {
     int32_t fp_views_per_group;
     int32_t fp_ray_split;
     int32_t fp_waves_per_pair;
     int32_t fp_staged;
-    int32_t reserved[4];
+    int32_t bp_waves;
+    int32_t reserved[3];
 } bsgd_tuning;
 bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* geom, const bsgd_tuning* tuning);
 bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* geom, bsgd_tuning* tuning);

@@ -79,7 +79,7 @@ class Options(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("fp_views_per_group", ctypes.c_int32), ("fp_ray_split", ctypes.c_int32),
                 ("fp_waves_per_pair", ctypes.c_int32), ("fp_staged", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("bp_waves", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 EXPORTED = (
@@ -254,8 +254,8 @@ class Geometry:
         return t
 
     def set_tuning(self, fp_views_per_group: Optional[int] = None, fp_ray_split: Optional[int] = None,
-                   fp_waves_per_pair: Optional[int] = None):
-        """Launch shape of the forward projector (bsgd_geometry_set_tuning)."""
+                   fp_waves_per_pair: Optional[int] = None, bp_waves: Optional[int] = None):
+        """Launch shapes of the projectors (bsgd_geometry_set_tuning)."""
         t = self._get_tuning()
         if fp_views_per_group is not None:
             t.fp_views_per_group = int(fp_views_per_group)
@@ -263,7 +263,14 @@ class Geometry:
             t.fp_ray_split = int(fp_ray_split)
         if fp_waves_per_pair is not None:
             t.fp_waves_per_pair = int(fp_waves_per_pair)
+        if bp_waves is not None:
+            t.bp_waves = int(bp_waves)
         _check(load_library().bsgd_geometry_set_tuning(self._h, ctypes.byref(t)))
+
+    @property
+    def bp_waves(self) -> int:
+        """Waves of a 2D back-projection workgroup (views split over them)."""
+        return self._get_tuning().bp_waves
 
     @property
     def fp_waves_per_pair(self) -> int:

@@ -617,6 +617,7 @@ static bsgd_status upload_tables(bsgd_geometry* g, hipStream_t st)
     G.rayv = g->d_rayv.as<float2>();
     G.fp_chunk = 12;
     G.fp_split = 1;
+    G.bp_split = 4;  // 2D back projection: views of a voxel over four waves (the measured best on the 512^2 fan)
     // waves per pair of the global-memory forward projector: one per 48 pixels of the
     // mean footprint (about one 64-pixel round per wave; more, shorter waves hide the
     // gather latency of the walk better), at most 64
@@ -917,11 +918,14 @@ extern "C" bsgd_status bsgd_geometry_set_tuning(bsgd_geometry* g, const bsgd_tun
         return fail(BSGD_E_INVALID_ARG, "fp_ray_split must be 1, 2 or 4");
     if (t->fp_waves_per_pair < 0 || t->fp_waves_per_pair > 64)
         return fail(BSGD_E_INVALID_ARG, "fp_waves_per_pair must be in [1, 64] (0 keeps the current value)");
-    for (int i = 0; i < 4; ++i)
+    if (t->bp_waves != 0 && t->bp_waves != 2 && t->bp_waves != 4 && t->bp_waves != 8)
+        return fail(BSGD_E_INVALID_ARG, "bp_waves must be 2, 4 or 8 (0 keeps the current value)");
+    for (int i = 0; i < 3; ++i)
         if (t->reserved[i] != 0) return fail(BSGD_E_INVALID_ARG, "reserved tuning fields must be 0");
     g->dg.fp_chunk = t->fp_views_per_group;
     g->dg.fp_split = t->fp_ray_split;
     if (t->fp_waves_per_pair > 0) g->dg.fp_wpp = t->fp_waves_per_pair;
+    if (t->bp_waves > 0) g->dg.bp_split = t->bp_waves;
     return BSGD_OK;
 }
 
@@ -933,6 +937,7 @@ extern "C" bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* g, bsgd_tun
     t->fp_ray_split = g->dg.fp_split;
     t->fp_waves_per_pair = g->dg.fp_wpp;
     t->fp_staged = fp_lds_bytes_for(g->dg) > 0 ? 1 : 0;
+    t->bp_waves = g->dg.bp_split;
     return BSGD_OK;
 }
 
@@ -1557,14 +1562,19 @@ struct BatchLaunchGroup {
     BatchArgs A;
     int wgs[3];
     std::vector<FpLaunchClass> classes;
+    std::vector<BpLaunchClass> bp_classes;
     size_t res_lds;
 };
 
 static std::vector<BatchLaunchGroup> batch_groups(bsgd_solver* const* solvers, int n)
 {
     std::vector<bsgd_solver*> order(solvers, solvers + n);
+    // forward-projection LDS size descending, then the 2D back projection's wave split, so
+    // each launch class is one contiguous run of workgroups
     std::stable_sort(order.begin(), order.end(), [](const bsgd_solver* a, const bsgd_solver* b) {
-        return fp_lds_bytes_for(a->g->dg) > fp_lds_bytes_for(b->g->dg);
+        const size_t la = fp_lds_bytes_for(a->g->dg), lb = fp_lds_bytes_for(b->g->dg);
+        if (la != lb) return la > lb;
+        return a->g->dg.bp_split < b->g->dg.bp_split;
     });
     std::vector<BatchLaunchGroup> groups;
     for (int g0 = 0; g0 < n; g0 += BATCH_GROUP) {
@@ -1600,6 +1610,9 @@ static std::vector<BatchLaunchGroup> batch_groups(bsgd_solver* const* solvers, i
             if (grp.classes.empty() || grp.classes.back().lds_bytes != lb)
                 grp.classes.push_back({(int)e.base[0], 0, lb});
             grp.classes.back().wgs += per[0];
+            if (grp.bp_classes.empty() || grp.bp_classes.back().split != e.G.bp_split)
+                grp.bp_classes.push_back({(int)e.base[2], 0, (int)e.G.bp_split});
+            grp.bp_classes.back().wgs += per[2];
             grp.res_lds = std::max(grp.res_lds, resid_lds_bytes_for(e.G));
         }
         grp.A.n = m;
@@ -1617,7 +1630,7 @@ static hipError_t enqueue_batch(std::vector<BatchLaunchGroup>& groups, bsgd_solv
         for (BatchLaunchGroup& grp : groups) {
             grp.A.it = it;
             hipError_t he = launch_batch_iteration(grp.A, dim, grp.wgs, grp.classes.data(), (int)grp.classes.size(),
-                                                   grp.res_lds, st);
+                                                   grp.bp_classes.data(), (int)grp.bp_classes.size(), grp.res_lds, st);
             if (he != hipSuccess) return he;
         }
         for (int i = 0; i < n; ++i) {

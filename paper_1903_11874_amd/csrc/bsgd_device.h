@@ -75,6 +75,7 @@ struct DevGeom {
     int32_t fp_chunk;          // views per workgroup of the LDS forward projector (tuning)
     int32_t fp_split;          // lanes per 2D ray in the LDS forward projector: 1, 2 or 4 (tuning)
     int32_t fp_wpp;            // waves per (view, block) pair of the global-memory forward projector
+    int32_t bp_split;          // waves of a 2D back-projection tile, each a share of the views: 2, 4 or 8 (tuning)
     // 2D chord tables: per (view, pixel) the unit normal (nx, ny) of the ray, xi with
     // n . p = lambda xi for the ray's anchor point p, and the trapezoid of the chord
     // length through one voxel as a function of the signed distance of the voxel

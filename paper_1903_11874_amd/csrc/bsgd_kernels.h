@@ -70,7 +70,7 @@ struct BatchArgs {
     BatchEntry e[BATCH_GROUP];
     int n;    // entries in use
     int it;   // iteration index into every entry's records
-    int id0;  // workgroup id of this launch's first workgroup (phase 0 classes)
+    int id0;  // workgroup id of this launch's first workgroup (forward and 2D back projection classes)
 };
 static_assert(sizeof(BatchArgs) <= 4096, "batched kernel arguments must fit the 4 KB argument segment");
 
@@ -79,10 +79,15 @@ struct FpLaunchClass {
     int wg0, wgs;
     size_t lds_bytes;
 };
+// A contiguous range of back-projection workgroups whose solves share the 2D wave split.
+struct BpLaunchClass {
+    int wg0, wgs, split;
+};
 // Launch one iteration (A.it) of all entries of A; the entries share the dimension;
 // wgs[p] = total workgroups of phase p over the group.
 hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], const FpLaunchClass* fp_classes,
-                                  int n_fp_classes, size_t res_lds_bytes, hipStream_t st);
+                                  int n_fp_classes, const BpLaunchClass* bp_classes, int n_bp_classes,
+                                  size_t res_lds_bytes, hipStream_t st);
 size_t fp_lds_bytes_for(const DevGeom& G);
 size_t resid_lds_bytes_for(const DevGeom& G);
 

@@ -775,9 +775,10 @@ __global__ __launch_bounds__(TPB) void k_resid(DevGeom G, const int32_t* __restr
 // ------------------------------------------------------------ solver: back projection + step
 
 // 2D: 64 lanes of two x-adjacent voxels per wave, each voxel's views interleaved over
-// bp_split waves and summed in a fixed order through LDS.
+// SPLIT waves (DevGeom::bp_split: 2, 4 or 8, a tuned launch shape) and the waves' partial
+// sums added in a fixed order through LDS.
 constexpr int BP_VOX = 64;
-// views of a voxel split over this many waves (each lane carries two voxels). Measured on
+// waves of the standalone 2D back projection, and the default of the solver's. Measured on
 // the 512^2 fan (2D back projection per iteration): one voxel per lane 36.1 / 30.5 / 30.9 us
 // at 1 / 2 / 4 waves; two voxels per lane 29.4 / 24.0 / 24.6 us at 2 / 4 / 8 waves.
 constexpr int BP_SPLIT_2D = 4;
@@ -807,14 +808,13 @@ __device__ __forceinline__ void pair_tile_voxels(const BlockInfo& B, int tile, i
 
 // bp_step_body for 2D: each lane two x-adjacent voxels (bp_voxel_pair_view_2d), the
 // same per-voxel update for both.
-template <bool SUB>
+template <bool SUB, int SPLIT>
 __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t* __restrict__ S_,
                                                 const PairWork* __restrict__ work, SchedLayout L,
                                                 const float* __restrict__ src, float* __restrict__ ghat,
                                                 float* __restrict__ gsum, float* __restrict__ x,
                                                 float* __restrict__ xT, const float* __restrict__ mu_ptr,
-                                                long long n_vox, int bx, int by,
-                                                float (&part)[BP_SPLIT_2D][2][BP_VOX])
+                                                long long n_vox, int bx, int by, float (&part)[SPLIT][2][BP_VOX])
 {
     const int b = by;
     const int j = S_[L.off_blocks() + b];
@@ -836,7 +836,7 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
         const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
         float acc_a = 0.0f, acc_b = 0.0f;
         if (a_ok) {
-            for (int a = a0 + grp; a < a1; a += BP_SPLIT_2D) {
+            for (int a = a0 + grp; a < a1; a += SPLIT) {
                 const PairWork W = wb[a];
                 if (W.k1 <= W.k0) continue;
                 if (SUB)
@@ -853,7 +853,7 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
         if (grp == 0 && a_ok) {
             float sa = part[0][0][vl], sb = part[0][1][vl];
 #pragma unroll
-            for (int q = 1; q < BP_SPLIT_2D; ++q) {
+            for (int q = 1; q < SPLIT; ++q) {
                 sa += part[q][0][vl];
                 sb += part[q][1][vl];
             }
@@ -1401,22 +1401,26 @@ __device__ __forceinline__ void bp3_step_body(const DevGeom& G, const int32_t* _
     }
 }
 
-// Workgroup size of the back projectors: 2D four waves of pair tiles; 3D one thread per
-// voxel column of a 16 x 16 column tile.
-__host__ __device__ constexpr int bp_wg(int dim) { return dim == 3 ? BP3_WG : BP_VOX * BP_SPLIT_2D; }
+// Workgroup size of the back projectors: 2D `split` waves of pair tiles; 3D one thread
+// per voxel column of a 16 x 16 column tile.
+__host__ __device__ constexpr int bp_wg(int dim, int split = BP_SPLIT_2D)
+{
+    return dim == 3 ? BP3_WG : BP_VOX * split;
+}
 
-template <int DIM, bool SUB>
-__global__ __launch_bounds__(bp_wg(DIM)) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_, const PairWork* __restrict__ work,
-                                                SchedLayout L, const float* __restrict__ src,
-                                                float* __restrict__ ghat, float* __restrict__ gsum,
-                                                float* __restrict__ x, float* __restrict__ xT,
-                                                const float* __restrict__ mu, long long n_vox)
+template <int DIM, bool SUB, int SPLIT = BP_SPLIT_2D>
+__global__ __launch_bounds__(bp_wg(DIM, SPLIT)) void k_bp_step(DevGeom G, const int32_t* __restrict__ S_,
+                                                              const PairWork* __restrict__ work, SchedLayout L,
+                                                              const float* __restrict__ src,
+                                                              float* __restrict__ ghat, float* __restrict__ gsum,
+                                                              float* __restrict__ x, float* __restrict__ xT,
+                                                              const float* __restrict__ mu, long long n_vox)
 {
     int bx, by;
     xcd_grid2(bx, by);
     if constexpr (DIM == 2) {
-        __shared__ float part[BP_SPLIT_2D][2][BP_VOX];
-        bp_step_body_2d<SUB>(G, S_, work, L, src, ghat, gsum, x, xT, mu, n_vox, bx, by, part);
+        __shared__ float part[SPLIT][2][BP_VOX];
+        bp_step_body_2d<SUB, SPLIT>(G, S_, work, L, src, ghat, gsum, x, xT, mu, n_vox, bx, by, part);
     } else {
         extern __shared__ float bp3_lds[];
         bp3_step_body<SUB>(G, S_, work, L, src, ghat, gsum, x, xT, mu, n_vox, bx, by, bp3_lds);
@@ -1503,19 +1507,19 @@ __global__ __launch_bounds__(TPB) void k_resid_batch(const BatchArgs A)
     resid_body<TPB>(B.G, S_, B.L, B.y, B.z, B.r_sel, local % B.gx[1], local / B.gx[1], rc);
 }
 
-template <int DIM>
-__global__ __launch_bounds__(bp_wg(DIM)) void k_bp_batch(const BatchArgs A)
+template <int DIM, int SPLIT = BP_SPLIT_2D>
+__global__ __launch_bounds__(bp_wg(DIM, SPLIT)) void k_bp_batch(const BatchArgs A)
 {
-    const int id = xcd_local((int)blockIdx.x, (int)gridDim.x);
+    const int id = A.id0 + xcd_local((int)blockIdx.x, (int)gridDim.x);
     const int e = __builtin_amdgcn_readfirstlane(find_entry(A.e, A.n, 2, id));
     const BatchEntry& B = A.e[e];
     const int local = id - B.base[2];
     const int32_t* S_ = B.sched + (int64_t)A.it * B.L.stride;
     const PairWork* W = B.work + (int64_t)A.it * B.L.maxv * B.L.B;
     if constexpr (DIM == 2) {
-        __shared__ float part[BP_SPLIT_2D][2][BP_VOX];
-        bp_step_body_2d<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.xT, B.mu, B.n_vox, local % B.gx[2],
-                               local / B.gx[2], part);
+        __shared__ float part[SPLIT][2][BP_VOX];
+        bp_step_body_2d<false, SPLIT>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.xT, B.mu, B.n_vox,
+                                      local % B.gx[2], local / B.gx[2], part);
     } else {
         extern __shared__ float bp3_lds[];
         bp3_step_body<false>(B.G, S_, W, B.L, B.r_sel, B.ghat, B.gsum, B.x, B.xT, B.mu, B.n_vox, local % B.gx[2],
@@ -1955,7 +1959,8 @@ void batch_grids(BatchEntry& e)
 }
 
 hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], const FpLaunchClass* fp_classes,
-                                  int n_fp_classes, size_t res_lds, hipStream_t st)
+                                  int n_fp_classes, const BpLaunchClass* bp_classes, int n_bp_classes,
+                                  size_t res_lds, hipStream_t st)
 {
     if (A.n == 0) return hipSuccess;
     // forward projection: one launch per LDS size class (contiguous workgroup ranges),
@@ -1985,13 +1990,29 @@ hipError_t launch_batch_iteration(BatchArgs& A, int dim, const int (&wgs)[3], co
         hipLaunchKernelGGL(k_resid_batch<res_wg(2)>, dim3(wgs[1]), dim3(res_wg(2)), res_lds, st, A);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t bp_lds = 0;
-    for (int i = 0; i < A.n; ++i) bp_lds = std::max(bp_lds, bp_lds_bytes(A.e[i].G));
-    if (dim == 3)
+    if (dim == 3) {
+        size_t bp_lds = 0;
+        for (int i = 0; i < A.n; ++i) bp_lds = std::max(bp_lds, bp_lds_bytes(A.e[i].G));
         hipLaunchKernelGGL(k_bp_batch<3>, dim3(wgs[2]), dim3(bp_wg(3)), bp_lds, st, A);
-    else
-        hipLaunchKernelGGL(k_bp_batch<2>, dim3(wgs[2]), dim3(bp_wg(2)), 0, st, A);
-    return hipGetLastError();
+        return hipGetLastError();
+    }
+    // 2D back projection: one launch per wave split (contiguous workgroup ranges), each
+    // solve with its own tuned workgroup shape
+    for (int c = 0; c < n_bp_classes; ++c) {
+        const BpLaunchClass& k = bp_classes[c];
+        if (k.wgs <= 0) continue;
+        A.id0 = k.wg0;
+        if (k.split == 2)
+            hipLaunchKernelGGL((k_bp_batch<2, 2>), dim3(k.wgs), dim3(bp_wg(2, 2)), 0, st, A);
+        else if (k.split == 8)
+            hipLaunchKernelGGL((k_bp_batch<2, 8>), dim3(k.wgs), dim3(bp_wg(2, 8)), 0, st, A);
+        else
+            hipLaunchKernelGGL((k_bp_batch<2>), dim3(k.wgs), dim3(bp_wg(2)), 0, st, A);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    A.id0 = 0;
+    return hipSuccess;
 }
 
 hipError_t launch_resid(const DevGeom& G, const int32_t* sched_it, SchedLayout L, const float* y, const float* z,
@@ -2039,6 +2060,12 @@ hipError_t launch_bp_step(const DevGeom& G, const int32_t* sched_it, const PairW
     } else if (G.dim == 3) {
         hipLaunchKernelGGL((k_bp_step<3, false>), grid, blk, lds, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
                            xT, mu, nv);
+    } else if (G.bp_split == 2) {
+        hipLaunchKernelGGL((k_bp_step<2, false, 2>), grid, dim3(bp_wg(2, 2)), 0, st, G, sched_it, work_it, L, r_sel,
+                           ghat, gsum, x, xT, mu, nv);
+    } else if (G.bp_split == 8) {
+        hipLaunchKernelGGL((k_bp_step<2, false, 8>), grid, dim3(bp_wg(2, 8)), 0, st, G, sched_it, work_it, L, r_sel,
+                           ghat, gsum, x, xT, mu, nv);
     } else {
         hipLaunchKernelGGL((k_bp_step<2, false>), grid, blk, 0, st, G, sched_it, work_it, L, r_sel, ghat, gsum, x,
                            xT, mu, nv);

@@ -53,13 +53,13 @@ def _check_draws(p, trace, solver):
                 assert int(draws[it, a, b]) == want, (it, v, j)
 
 
-@pytest.mark.parametrize("split", [1, 4])
-def test_fan_tiles_importance_sampled(split):
+@pytest.mark.parametrize("split,bp_waves", [(1, 4), (4, 4), (1, 2), (1, 8)])
+def test_fan_tiles_importance_sampled(split, bp_waves):
     import torch
     from paper_1903_11874_amd import Geometry, Solver
     dev = require_gpu()
     g = FAN_TILES.with_(im_mode="colnorm")
-    log(f"bench-shaped fan: 64x64 LDS tiles, 12-view chunks, IM S=4, ray split {split}")
+    log(f"bench-shaped fan: 64x64 LDS tiles, 12-view chunks, IM S=4, ray split {split}, BP waves {bp_waves}")
     p = oracle_problem(FAN_TILES)
     A, y64, y32 = _data(FAN_TILES, 41)
     mu = float(np.float32(0.5 / (2.0 * lipschitz(A))))
@@ -69,7 +69,7 @@ def test_fan_tiles_importance_sampled(split):
     trace = []
     st = run(p, y64, mu, R, B, n, 51, q=q, trace=trace)
     geom = Geometry(g, im_table=q)
-    geom.set_tuning(fp_views_per_group=12, fp_ray_split=split)
+    geom.set_tuning(fp_views_per_group=12, fp_ray_split=split, bp_waves=bp_waves)
     yd = torch.tensor(y32, device=dev)
     xd = torch.zeros(A.shape[1], dtype=torch.float32, device=dev)
     s = Solver(geom, yd, xd, node_count=4, mu=mu, seed=51)

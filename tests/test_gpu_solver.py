@@ -29,7 +29,7 @@ def _mu(A, scale):
 
 
 def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed=3, im_until=0, subdet=False,
-          eager=False):
+          eager=False, bp_waves=None):
     import torch
     from paper_1903_11874_amd import Geometry, Solver
     dev = require_gpu()
@@ -41,6 +41,9 @@ def _pair(g, n_iter, R, B, seed, im=None, tv_lambda=0.0, mu_scale=0.3, data_seed
     st = run(p, y64, mu, R, B, n_iter, seed, q=q, tv_lambda=tv_lambda, trace=trace, im_until=im_until or None,
              subdet_memory=subdet)
     geom = Geometry(g.with_(im_mode=im or "none"), im_table=q)
+    if bp_waves is not None:
+        geom.set_tuning(bp_waves=bp_waves)
+        assert geom.bp_waves == bp_waves
     yd = torch.tensor(y32, device=dev)
     xd = torch.zeros(A.shape[1], dtype=torch.float32, device=dev)
     solver = Solver(geom, yd, xd, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=seed, tv_lambda=tv_lambda,
@@ -70,6 +73,19 @@ def _check_schedule(p, trace, solver, tail_from=None):
 def test_trajectory_plain(name, R, B):
     log(f"trajectory plain {name} R={R} B={B}")
     p, st, trace, solver, xd, rn = _pair(SMALL[name], 60, R, B, seed=7)
+    _check_schedule(p, trace, solver)
+    assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
+    assert abs(rn - np.linalg.norm(st.r)) <= TOL * np.linalg.norm(st.r)
+
+
+@pytest.mark.parametrize("name,waves,im", [("fan", 2, "colnorm"), ("fan", 8, "colnorm"), ("parallel", 8, None),
+                                           ("fan_wide", 2, None)])
+def test_trajectory_back_projection_waves(name, waves, im):
+    """Every wave split of the 2D back projector (a tuned launch shape: the views of a
+    voxel gathered by that many waves, their sums added in a fixed order) follows the
+    oracle, on the LDS-staged and the global-memory forward paths."""
+    log(f"trajectory 2D back projection over {waves} waves {name}")
+    p, st, trace, solver, xd, rn = _pair(SMALL[name], 40, 2, 3, seed=17, im=im, bp_waves=waves)
     _check_schedule(p, trace, solver)
     assert rel_l2(xd.double().cpu().numpy(), st.x) <= TOL
     assert abs(rn - np.linalg.norm(st.r)) <= TOL * np.linalg.norm(st.r)
@@ -343,6 +359,10 @@ def test_batched_solves_equal_solo_solves():
             pair.append((x, Solver(geoms[key], yd, x, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=seed,
                                    tv_lambda=tv, eager=True)))
         runs.append(pair)
+    # the geometries' 2D back projections use different wave splits, so each batched
+    # iteration launches one back projection per split
+    for geom, w in zip(geoms.values(), (2, 8, 4)):
+        geom.set_tuning(bp_waves=w)
     for rep, n in enumerate((7, 1, 12)):
         step_batch([r[0][1] for r in runs], n)
         for r in runs:
@@ -384,8 +404,13 @@ def test_autotuner_shapes_do_not_change_results():
     geom = Geometry(g)
     yd = torch.tensor(y32, device=dev)
     timings = autotune(geom, yd, node_count=9, mu=mu, views=(1, 2, 5, 16), splits=(1, 4), epochs=1)
-    assert set(timings) == {(c, s) for c in (1, 2, 5, 16) for s in (1, 4)}
+    assert set(timings) == ({(c, s) for c in (1, 2, 5, 16) for s in (1, 4)} |
+                            {("bp_waves", w) for w in (2, 4, 8)})
     assert (geom.fp_views_per_group, geom.fp_ray_split) in timings
+    assert ("bp_waves", geom.bp_waves) in timings
+    with pytest.raises(Exception):
+        geom.set_tuning(bp_waves=3)
+    geom.set_tuning(bp_waves=4)
     outs = {}
     for sp in (1, 2, 4):
         for c in (1, 4, 16):
@@ -414,7 +439,7 @@ def test_autotuner_waves_per_pair_of_the_global_walk(name):
     geom = Geometry(g)
     assert not geom.fp_staged
     yd = torch.tensor(y32, device=dev)
-    timings = autotune(geom, yd, node_count=4, mu=mu, waves=(1, 3, 16), epochs=1)
+    timings = autotune(geom, yd, node_count=4, mu=mu, waves=(1, 3, 16), bp_waves=(), epochs=1)
     assert set(timings) == {(1,), (3,), (16,)}
     assert (geom.fp_waves_per_pair,) in timings
     outs = []

@@ -38,11 +38,11 @@ def test_struct_layouts_match_header():
     import subprocess
     import tempfile
     from paper_1903_11874_amd.bsgd import Allocator, GeometryDesc, Options, GeometryInfo, Tuning
-    src = '#include "%s"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu", ' \
+    src = '#include "%s"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu", ' \
           'sizeof(bsgd_geometry_desc), sizeof(bsgd_options), sizeof(bsgd_geometry_info), ' \
           'offsetof(bsgd_geometry_desc, im_table), offsetof(bsgd_options, tol), sizeof(bsgd_tuning), ' \
           'offsetof(bsgd_tuning, fp_ray_split), offsetof(bsgd_geometry_desc, allocator), sizeof(bsgd_allocator), ' \
-          'offsetof(bsgd_tuning, fp_waves_per_pair), offsetof(bsgd_tuning, fp_staged));' \
+          'offsetof(bsgd_tuning, fp_waves_per_pair), offsetof(bsgd_tuning, fp_staged), offsetof(bsgd_tuning, bp_waves));' \
           'return 0;}\n' % HEADER
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
@@ -53,7 +53,7 @@ def test_struct_layouts_match_header():
                                       ctypes.sizeof(GeometryInfo), GeometryDesc.im_table.offset,
                                       Options.tol.offset, ctypes.sizeof(Tuning), Tuning.fp_ray_split.offset,
                                       GeometryDesc.allocator.offset, ctypes.sizeof(Allocator),
-                                      Tuning.fp_waves_per_pair.offset, Tuning.fp_staged.offset]
+                                      Tuning.fp_waves_per_pair.offset, Tuning.fp_staged.offset, Tuning.bp_waves.offset]
 
 
 def _desc(**kw):
