@@ -188,7 +188,8 @@ bsgd_status bsgd_geometry_get_tuning(const bsgd_geometry* geom, bsgd_tuning* tun
  * x: device [nz][ny][nx]; y: device [n_sel][nv][nu] with n_sel = n_views_sel, or
  * all views in index order when views == NULL. views: host int32 list (copied).
  * block = -1 projects the whole volume, otherwise only column block `block`.
- * flags: BSGD_ACCUMULATE adds into y instead of overwriting. */
+ * flags: BSGD_ACCUMULATE adds into y instead of overwriting. A non-NULL views list with
+ * n_views_sel = 0 selects no view: nothing is written and y may be NULL. */
 bsgd_status bsgd_forward_project(const bsgd_geometry* geom, const float* x, float* y,
                                  const int32_t* views, int32_t n_views_sel, int32_t block,
                                  uint32_t flags, void* stream);
@@ -196,7 +197,9 @@ bsgd_status bsgd_forward_project(const bsgd_geometry* geom, const float* x, floa
 /* Matched back projection (Sec. I: BP = A^T r), same lengths as the forward projection:
  *   x[J] (= or +=) scale * (A_{views}^{J})^T y
  * for every voxel of `block` (all voxels when block = -1); voxels outside J are untouched.
- * y: device [n_sel][nv][nu] as for bsgd_forward_project. */
+ * y: device [n_sel][nv][nu] as for bsgd_forward_project. With an empty views list
+ * (n_views_sel = 0, y may be NULL) the sum is empty: x[J] is set to 0, or left as it is
+ * with BSGD_ACCUMULATE. */
 bsgd_status bsgd_back_project(const bsgd_geometry* geom, const float* y, float* x,
                               const int32_t* views, int32_t n_views_sel, int32_t block,
                               float scale, uint32_t flags, void* stream);

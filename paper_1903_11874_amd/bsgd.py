@@ -167,8 +167,10 @@ def _dev_ptr(t, dtype_name="float32"):
 def _views_arg(views):
     if views is None:
         return None, 0, None
-    arr = np.ascontiguousarray(np.asarray(views, dtype=np.int32))
-    return arr.ctypes.data_as(ctypes.c_void_p), int(arr.size), arr
+    arr = np.ascontiguousarray(np.asarray(views, dtype=np.int32).reshape(-1))
+    # an empty list must stay a (non-NULL) list: NULL would select every view
+    keep = arr if arr.size else np.zeros(1, dtype=np.int32)
+    return keep.ctypes.data_as(ctypes.c_void_p), int(arr.size), keep
 
 
 def torch_allocator() -> Allocator:

@@ -962,10 +962,11 @@ static bsgd_status view_list(bsgd_geometry* g, const int32_t* views, int32_t n, 
     return BSGD_OK;
 }
 
+// a: the image argument, b: the projections (NULL allowed when an empty view list selects none)
 static bsgd_status check_proj_args(const bsgd_geometry* g, const void* a, const void* b, const int32_t* views,
                                    int32_t n_sel, int32_t block, uint32_t flags)
 {
-    if (!g || !a || !b) return fail(BSGD_E_INVALID_ARG, "NULL argument");
+    if (!g || !a || (!b && !(views && n_sel == 0))) return fail(BSGD_E_INVALID_ARG, "NULL argument");
     if (views && (n_sel < 0 || n_sel > 65535)) return fail(BSGD_E_INVALID_ARG, "n_views_sel must be in [0, 65535]");
     if (block < -1 || block >= g->N) return fail(BSGD_E_INVALID_ARG, "block %d out of range", block);
     if (flags & ~BSGD_ACCUMULATE) return fail(BSGD_E_INVALID_ARG, "unknown flags 0x%x", flags);
@@ -990,7 +991,7 @@ extern "C" bsgd_status bsgd_forward_project(const bsgd_geometry* gc, const float
 extern "C" bsgd_status bsgd_back_project(const bsgd_geometry* gc, const float* y, float* x, const int32_t* views,
                                          int32_t n_sel, int32_t block, float scale, uint32_t flags, void* stream)
 {
-    bsgd_status stt = check_proj_args(gc, y, x, views, n_sel, block, flags);
+    bsgd_status stt = check_proj_args(gc, x, y, views, n_sel, block, flags);
     if (stt != BSGD_OK) return stt;
     if (!std::isfinite(scale)) return fail(BSGD_E_INVALID_ARG, "scale must be finite");
     bsgd_geometry* g = const_cast<bsgd_geometry*>(gc);
