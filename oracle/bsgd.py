@@ -192,7 +192,21 @@ def iterate(p: Problem, st: State, y: np.ndarray, mu: float, rows_per_iter: int,
             blocks_per_iter: int, seed: int, q=None, tv_lambda: float = 0.0,
             tv_iters: int = 20, trace: Optional[list] = None, im_until: Optional[int] = None,
             subdet_memory: bool = False):
-    """One BSGD iteration (Algorithm 1 / 2 / 4) in place on ``st``. With ``im_until``,
+    """One BSGD iteration in place on ``st``, as the state updates of Sec. IV define it.
+    The stacked memories are z-bar (one r-vector z^j per column block) and g-bar (one
+    c-vector g_hat^i per row block); random 0/1 diagonal selections R1, R2, R3 pick the
+    slots of the chosen (row block, column block) pairs and the chosen blocks' voxels:
+
+      Eq. (Updaz)  z-bar += R1 (A-bar x - z-bar): z^j on the chosen rows becomes A^{J_j} x_{J_j}
+                   (x as it stood when the iteration began);
+      Eq. (Updag)  g-bar += R2 (2 A^T-bar (y - I z-bar) - g-bar): g_hat^i on the chosen
+                   blocks becomes the gradient of those rows at the refreshed residual
+                   (the factor 2 of Eq. (SGDITE) kept literally);
+      Eq. (Updax)  x += mu R3 I g-bar: the chosen blocks move along g = sum_i g_hat^i;
+
+    then the TV prox every round(1/(alpha gamma)) iterations (Algorithm 4). Which pairs
+    are chosen is Algorithm 1's selection; with importance sampling (Algorithm 2) a pair
+    uses only its view's drawn sub-detector rows. With ``im_until``,
     iterations k >= im_until run without importance sampling (all rays of the selected
     row blocks): the unbiased tail that Sec. II-A recommends for the last iterations.
 
@@ -213,8 +227,10 @@ def iterate(p: Problem, st: State, y: np.ndarray, mu: float, rows_per_iter: int,
               np.concatenate([r for _, r in parts]) if parts else np.zeros(0, dtype=np.int64))
              for i, j, parts in pairs]
     x_frozen = st.x.copy()
+    # Eq. (Updaz): refresh the chosen z slots
     for i, j, _, rows in pairs:
         st.z[j][rows] = p.A_cols[j][rows] @ x_frozen[p.blocks[j]]
+    # the residual y - I z-bar that Eq. (Updag) reads
     st.r = y - st.z.sum(axis=0)
     if subdet_memory:
         if st.mem is None:
@@ -224,9 +240,11 @@ def iterate(p: Problem, st: State, y: np.ndarray, mu: float, rows_per_iter: int,
                 st.mem[v, s, p.blocks[j]] = 2.0 * (p.A_cols[j][rows].T @ st.r[rows])
         st.gsum = st.mem.sum(axis=(0, 1))
     else:
+        # Eq. (Updag): refresh the chosen g_hat slots; g = I g-bar
         for i, j, _, rows in pairs:
             st.ghat[i][p.blocks[j]] = 2.0 * (p.A_cols[j][rows].T @ st.r[rows])
         st.gsum = st.ghat.sum(axis=0)
+    # Eq. (Updax): the chosen blocks' voxels move
     for j in C:
         st.x[p.blocks[j]] += mu * st.gsum[p.blocks[j]]
     st.k += 1
