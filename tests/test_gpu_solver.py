@@ -392,6 +392,43 @@ def test_batched_solves_equal_solo_solves():
         assert rel_l2(r[0][0].double().cpu().numpy(), st.x) <= TOL, (g.kind, R, B)
 
 
+def test_batched_cone_solves_equal_solo_solves_and_the_oracle():
+    """Cone-beam solves in shared launches: one whose blocks are staged in LDS by the
+    forward projector and one whose blocks are walked in global memory (two forward
+    launch classes in one batch), one of them with TV. Each equals its solo twin bit for
+    bit and follows the oracle."""
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver, step_batch
+    dev = require_gpu()
+    log("batched cone solves vs solo and oracle")
+    specs = [(SMALL["cone"], 1, 4, 0.0, 61), (SMALL["cone_wide"], 2, 2, 0.5, 62), (SMALL["cone"], 2, 3, 0.3, 63)]
+    geoms, runs = {}, []
+    for g, R, B, tv, seed in specs:
+        A, x_true, y64, y32 = _data(g, seed)
+        if g.nx not in geoms:
+            geoms[g.nx] = Geometry(g)
+        yd = torch.tensor(y32, device=dev)
+        mu = _mu(A, 0.3)
+        pair = []
+        for _ in range(2):
+            x = torch.zeros(A.shape[1], device=dev)
+            pair.append((x, Solver(geoms[g.nx], yd, x, rows_per_iter=R, blocks_per_iter=B, mu=mu, seed=seed,
+                                   tv_lambda=tv, eager=True)))
+        runs.append(pair)
+    assert geoms[SMALL["cone"].nx].fp_staged and not geoms[SMALL["cone_wide"].nx].fp_staged
+    for rep, n in enumerate((9, 1, 14)):
+        step_batch([r[0][1] for r in runs], n)
+        for r in runs:
+            r[1][1].step(n)
+        torch.cuda.synchronize()
+        for i, r in enumerate(runs):
+            assert torch.equal(r[0][0], r[1][0]), (rep, i)
+    for (g, R, B, tv, seed), r in zip(specs, runs):
+        A, x_true, y64, y32 = _data(g, seed)
+        st = run(oracle_problem(g), y64, _mu(A, 0.3), R, B, r[0][1].iterations, seed, tv_lambda=tv)
+        assert rel_l2(r[0][0].double().cpu().numpy(), st.x) <= TOL, (g.nx, R, B, tv)
+
+
 def test_autotuner_shapes_do_not_change_results():
     import torch
     from paper_1903_11874_amd import Geometry, Solver
