@@ -137,3 +137,28 @@ def test_invalid_inputs_are_refused():
         Solver(geom, y, x, rows_per_iter=1, blocks_per_iter=g.n_blocks + 1, mu=1e-3)
     with pytest.raises(BsgdError):
         geom.set_tuning(fp_views_per_group=0)
+
+
+@pytest.mark.parametrize("name", ["fan", "cone"])
+def test_divergence_is_reported(name):
+    """A step length far beyond 1 / (2 ||A||^2) makes the iterates overflow: the residual
+    norm is not finite and bsgd_step reports BSGD_E_DIVERGED (status 5); the solver stays
+    usable, so a further step with a residual still reports it."""
+    import torch
+    from paper_1903_11874_amd import Geometry, Solver
+    from paper_1903_11874_amd.bsgd import BsgdError
+    dev = require_gpu()
+    log(f"divergence {name}")
+    g = SMALL[name]
+    A, y64, y32 = _data(g)
+    mu = float(1e10 / (2.0 * lipschitz(A)))  # a growth of about 1e10 per effective epoch
+    x = torch.zeros(A.shape[1], device=dev)
+    s = Solver(Geometry(g), torch.tensor(y32, device=dev), x, rows_per_iter=1, blocks_per_iter=2, mu=mu, seed=2,
+               eager=True)
+    with pytest.raises(BsgdError) as e:
+        s.step(300, residual=True)
+    assert e.value.status == 5
+    assert not bool(torch.isfinite(x).all())
+    with pytest.raises(BsgdError) as e:
+        s.step(1, residual=True)
+    assert e.value.status == 5
