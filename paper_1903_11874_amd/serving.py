@@ -5,9 +5,11 @@ over time. A request is admitted when a slot is free and the device has room for
 state (measured free HBM minus a reserve); waiting requests are admitted in arrival
 order. The admitted solves share the GPU in ticks:
 
-* each solve gets a quota of effective epochs per tick, inversely proportional to its
-  cost per epoch (the largest gets one), so a small reconstruction is not paced by the
-  largest one in the mix; a quota never passes the solve's next stopping check;
+* each solve gets a quota of effective epochs per tick, (largest cost / its cost) **
+  quota_power (at least one, at most max_quota), so with the default power 1 a small
+  reconstruction is not paced by the largest one in the mix; a quota never passes the
+  solve's next stopping check. A smaller power shares the GPU more evenly: it trades a
+  longer median latency for a shorter tail;
 * the epochs of a tick are issued round by round, each round one batched call
   (``bsgd_step_batch``: one launch per phase for all solves of the round, replayed as a
   captured HIP graph while the set recurs), the solves in admission order;
@@ -118,13 +120,15 @@ class _Active:
 
 class Server:
     def __init__(self, max_slots: int = 32, hbm_reserve: float = 0.1, stream=None,
-                 clock: Callable[[], float] = time.perf_counter, max_quota: int = 16, allocator="torch"):
+                 clock: Callable[[], float] = time.perf_counter, max_quota: int = 16, allocator="torch",
+                 quota_power: float = 1.0):
         import torch
         self.max_slots = max_slots
         self.hbm_reserve = hbm_reserve
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.clock = clock
         self.max_quota = max_quota
+        self.quota_power = quota_power
         self.allocator = allocator
         self.geoms: Dict[object, Geometry] = {}
         self.log: List[tuple] = []
@@ -177,7 +181,8 @@ class Server:
             stepping = [a for a in active if not (a.checked is not None and a.epochs >= a.req.max_epochs)]
             if stepping:
                 cmax = max(a.cost for a in stepping)
-                quota = {id(a): min(self.max_quota, max(1, int(cmax / a.cost)), a.to_next_check())
+                quota = {id(a): min(self.max_quota, max(1, int((cmax / a.cost) ** self.quota_power)),
+                                    a.to_next_check())
                          for a in stepping}
                 for e in range(max(quota.values())):
                     groups: Dict[tuple, List[_Active]] = {}
