@@ -509,6 +509,27 @@ def serving_mode(reqs, specs, mus, rate, max_slots, tol, max_epochs, mode):
     return st
 
 
+def hbm_copy_rate(reps: int = 10):
+    """Achievable HBM bandwidth: bytes read plus written per second of a plain 1 GiB device
+    copy (torch's copy kernel), timed with HIP events after three untimed copies."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbps = 2.0 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def _line_of(m):
     T = m["iters_per_step"]
     return {"workload": m["workload"], "metric": "FP+BP ray-voxel updates/s", "value": m["value"],
@@ -617,6 +638,11 @@ def main():
     cone_spec, cone_groups, cone_nnz = c["spec"], c["groups"], c["nnz"]
     del c
     torch.cuda.empty_cache()
+    # context for the HBM fractions: what a plain device copy reaches on this GPU
+    copy_gbps = hbm_copy_rate()
+    out["roofline"]["copy_GBps"] = copy_gbps
+    out["roofline"]["copy_note"] = ("achievable HBM bandwidth: a plain 1 GiB device copy, bytes read plus written "
+                                    "per second (context; peak stays the published 8 TB/s)")
     if args.fan_steps > 0:
         f = fan_bench(args.fan_steps, args.warmup, args.fan_steps, args.tune)
         out["secondary"] = _line_of(f)
