@@ -832,9 +832,29 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
     const int per_view = G.nu;
     const PairWork* wb = work + (int64_t)b * L.maxv;
     float dga = 0.0f, dgb = 0.0f;
+    // the lanes that update the voxels load g and x before the views, so the loads are
+    // in flight while the sums are gathered
+    const bool upd = grp == 0 && a_ok;
+    float gsa = 0.0f, gsb = 0.0f, xva = 0.0f, xvb = 0.0f;
+    if (upd) {
+        gsa = gsum[vox];
+        xva = x[vox];
+        if (b_ok) {
+            gsb = gsum[vox + 1];
+            xvb = x[vox + 1];
+        }
+    }
     for (int ri = 0; ri < L.R; ++ri) {
         const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
         float acc_a = 0.0f, acc_b = 0.0f;
+        // this row block's old memories, loaded the same way
+        float goa = 0.0f, gob = 0.0f;
+        float* gp = nullptr;
+        if (!SUB && upd) {
+            gp = ghat + (int64_t)S_[L.off_rows() + ri] * n_vox + vox;
+            goa = gp[0];
+            if (b_ok) gob = gp[1];
+        }
         if (a_ok) {
             for (int a = a0 + grp; a < a1; a += SPLIT) {
                 const PairWork W = wb[a];
@@ -861,33 +881,31 @@ __device__ __forceinline__ void bp_step_body_2d(const DevGeom& G, const int32_t*
                 dga += 2.0f * sa;
                 dgb += 2.0f * sb;
             } else {
-                const int i = S_[L.off_rows() + ri];
-                float* gp = ghat + (int64_t)i * n_vox + vox;
                 const float ga = 2.0f * sa;
-                dga += ga - gp[0];
+                dga += ga - goa;
                 gp[0] = ga;
                 if (b_ok) {
                     const float gb = 2.0f * sb;
-                    dgb += gb - gp[1];
+                    dgb += gb - gob;
                     gp[1] = gb;
                 }
             }
         }
         __syncthreads();
     }
-    if (grp == 0 && a_ok) {
+    if (upd) {
         const float mu = *mu_ptr;
-        const float gva = gsum[vox] + dga;
+        const float gva = gsa + dga;
         gsum[vox] = gva;
-        const float xa = fmaf(mu, gva, x[vox]);
+        const float xa = fmaf(mu, gva, xva);
         x[vox] = xa;
         // the copy of x stored y fastest (a wave's lanes cover 8 rows of y per x)
         const int64_t tvox = (int64_t)(B.x0 + li[0]) * G.ny + (B.y0 + li[1]);
         if (xT) xT[tvox] = xa;
         if (b_ok) {
-            const float gvb = gsum[vox + 1] + dgb;
+            const float gvb = gsb + dgb;
             gsum[vox + 1] = gvb;
-            const float xb = fmaf(mu, gvb, x[vox + 1]);
+            const float xb = fmaf(mu, gvb, xvb);
             x[vox + 1] = xb;
             if (xT) xT[tvox + G.ny] = xb;
         }
@@ -1349,23 +1367,48 @@ __device__ __forceinline__ void bp3_step_body(const DevGeom& G, const int32_t* _
     float dg[BP3_CZ];
 #pragma unroll
     for (int iz = 0; iz < BP3_CZ; ++iz) dg[iz] = 0.0f;
-    for (int ri = 0; ri < L.R; ++ri) {
-        const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
-        bp3_accumulate(G, B, views, a0, a1, tx0, ty0, zc0, nzc, lds);
+    if (!SUB && L.R == 1) {
+        // one row block: its old memories are loaded into dg before the accumulation, so
+        // they arrive with the first staging loads instead of after the last view; then
+        // dg = g_hat_new - g_hat_old, the same value as below
+        const int i = S_[L.off_rows()];
         if (col_ok) {
-            const int i = S_[L.off_rows() + ri];
+#pragma unroll
+            for (int iz = 0; iz < BP3_CZ; ++iz)
+                if (iz < nzc) dg[iz] = ghat[(int64_t)i * n_vox + vox0 + iz * plane];
+        }
+        bp3_accumulate(G, B, views, S_[L.off_gstart()], S_[L.off_gstart() + 1], tx0, ty0, zc0, nzc, lds);
+        if (col_ok) {
 #pragma unroll
             for (int iz = 0; iz < BP3_CZ; ++iz) {
                 if (iz < nzc) {
                     float* ap = acc + (iz + 1) * BP3_WG + threadIdx.x;
                     const float gnew = 2.0f * *ap;
                     *ap = 0.0f;
-                    if (SUB) {
-                        dg[iz] += gnew;
-                    } else {
-                        float* gp = ghat + (int64_t)i * n_vox + vox0 + iz * plane;
-                        dg[iz] += gnew - *gp;
-                        *gp = gnew;
+                    dg[iz] = gnew - dg[iz];
+                    ghat[(int64_t)i * n_vox + vox0 + iz * plane] = gnew;
+                }
+            }
+        }
+    } else {
+        for (int ri = 0; ri < L.R; ++ri) {
+            const int a0 = S_[L.off_gstart() + ri], a1 = S_[L.off_gstart() + ri + 1];
+            bp3_accumulate(G, B, views, a0, a1, tx0, ty0, zc0, nzc, lds);
+            if (col_ok) {
+                const int i = S_[L.off_rows() + ri];
+#pragma unroll
+                for (int iz = 0; iz < BP3_CZ; ++iz) {
+                    if (iz < nzc) {
+                        float* ap = acc + (iz + 1) * BP3_WG + threadIdx.x;
+                        const float gnew = 2.0f * *ap;
+                        *ap = 0.0f;
+                        if (SUB) {
+                            dg[iz] += gnew;
+                        } else {
+                            float* gp = ghat + (int64_t)i * n_vox + vox0 + iz * plane;
+                            dg[iz] += gnew - *gp;
+                            *gp = gnew;
+                        }
                     }
                 }
             }
