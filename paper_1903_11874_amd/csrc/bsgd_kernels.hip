@@ -1233,8 +1233,10 @@ __device__ __forceinline__ void bp3_accumulate(const DevGeom& G, const BlockInfo
     const int cx = tx0 + (int)threadIdx.x % BP3_TX, cy = ty0 + (int)threadIdx.x / BP3_TX;
     const bool col_ok = cx < B.nbx && cy < B.nby;
     const int tx1 = min(tx0 + BP3_TX, B.nbx), ty1 = min(ty0 + BP3_TY, B.nby);
-    for (int ab = a0; ab < a1; ab += BP3_VC) {
-        const int nvw = min(BP3_VC, a1 - ab);
+    // workgroups start with rounds of 5, 4, 3 or 2 views by their id, so that workgroups
+    // sharing a CU stage at different times (the views and their order are the same)
+    const int phase = (int)((blockIdx.y * gridDim.x + blockIdx.x) & 3);
+    for (int ab = a0, nvw = min(BP3_VC - phase, a1 - a0); ab < a1; ab += nvw, nvw = min(BP3_VC, a1 - ab)) {
         __syncthreads();  // the previous round's readers are done
         if (threadIdx.x < 64) {
             // lanes 8q .. 8q+7: the eight corners of the tile in view slot ab + q
