@@ -467,10 +467,10 @@ static void build_tables(bsgd_geometry* g)
         const double hx = 0.5 * d.vx, hy = 0.5 * d.vy;
         g->raynorm.resize((size_t)d.n_views * d.nu);
         g->raytrap.resize((size_t)d.n_views * d.nu);
-        g->kspan.resize(d.n_views);
+        g->kspan.resize(2 * (size_t)d.n_views);
         for (int v = 0; v < d.n_views; ++v) {
             const double c = std::cos(d.angles_rad[v]), s = std::sin(d.angles_rad[v]);
-            double span = 0.0;
+            double span = 0.0, span2 = 0.0;
             for (int k = 0; k < d.nu; ++k) {
                 double nx, ny, xi, len;
                 if (par) {
@@ -496,8 +496,11 @@ static void build_tables(bsgd_geometry* g)
                 g->raynorm[(size_t)v * d.nu + k] = make_float4((float)nx, (float)ny, (float)xi, 0.0f);
                 g->raytrap[(size_t)v * d.nu + k] = make_float4((float)w1, (float)w2, (float)lmax, (float)slope);
                 span = std::max(span, w2 * len / d.du);
+                // two x-adjacent voxels as one 2 x 1 rectangle: support half-width 2 hx |nx| + hy |ny|
+                span2 = std::max(span2, (w2 + hx * ax) * len / d.du);
             }
             g->kspan[v] = (float)(span * (1.0 + 1e-5));
+            g->kspan[(size_t)d.n_views + v] = (float)(span2 * (1.0 + 1e-5));
         }
     }
 }

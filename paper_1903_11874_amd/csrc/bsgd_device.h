@@ -81,10 +81,11 @@ struct DevGeom {
     // length through one voxel as a function of the signed distance of the voxel
     // centre from the ray: plateau half-width w1, support half-width w2, plateau
     // length lmax and flank slope lmax / (w2 - w1). Per view: kspan, the candidate
-    // half-range in pixels times the voxel depth (fan) or in pixels (parallel).
+    // half-range in pixels times the depth of the centre (fan) or in pixels (parallel),
+    // first of one voxel, then of two x-adjacent voxels as one 2 x 1 rectangle.
     const float4* raynorm;     // [n_views][nu]: nx, ny, xi, unused
     const float4* raytrap;     // [n_views][nu]: w1, w2, lmax, slope
-    const float* kspan;        // [n_views]
+    const float* kspan;        // [2][n_views]: one voxel, two voxels
     // Pixel-major index of z: ray p = view * nu * nv + l * nu + k has the z slots
     // cov_idx[cov_off[p] .. cov_off[p + 1]), one per column block whose footprint holds
     // the pixel, blocks ascending. NULL when z has 2^32 or more slots (the residual

@@ -134,9 +134,13 @@ __device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t byte_of
 // Candidate pixel range [klo, khi] of a 2D voxel centre (qx, qy), block-local, in one
 // view: the pixels within kc -/+ span of the projection of the centre (kspan / depth for
 // a fan, kspan for parallel rays; kspan bounds the chord's support), clipped to [k0, k1).
+// which = 1 takes the span of two x-adjacent voxels and (qx, qy) the centre of their
+// shared edge. For a fan the bound is exact for any convex body: a ray at distance d
+// from the centre meets the detector d |ray| / depth away from the centre's projection,
+// and it can cross the body only while d is within the body's support half-width.
 template <class Anchor>
 __device__ __forceinline__ void bp2d_range(const DevGeom& G, int view, float c, float s, const Anchor& P, float qx,
-                                           float qy, int k0, int k1, int& klo, int& khi)
+                                           float qy, int k0, int k1, int& klo, int& khi, int which = 0)
 {
     const float w = fmaf(qy, c, -(qx * s)) + P.cu;
     const float ku = 0.5f * (float)(G.nu - 1);
@@ -144,11 +148,11 @@ __device__ __forceinline__ void bp2d_range(const DevGeom& G, int view, float c, 
     float kc, span;
     if (G.kind == KIND_PARALLEL_2D) {
         kc = fmaf(w, inv_du, ku);
-        span = G.kspan[view];
+        span = G.kspan[which * G.n_views + view];
     } else {
         const float rdep = __builtin_amdgcn_rcpf(P.depth - fmaf(qx, c, qy * s));
         kc = fmaf(G.sdd * w * rdep, inv_du, ku);
-        span = G.kspan[view] * rdep;
+        span = G.kspan[which * G.n_views + view] * rdep;
     }
     klo = (int)ceilf(fminf(fmaxf(kc - span - SHADOW_EPS, (float)k0), (float)k1));
     khi = min(k1 - 1, (int)floorf(fmaxf(fminf(kc + span + SHADOW_EPS, (float)k1), (float)k0 - 1.0f)));
@@ -169,16 +173,13 @@ __device__ __forceinline__ void bp_voxel_pair_view_2d(const DevGeom& G, int view
     const float qxa = plane_pos(li[0], vs[0], h[0]) + 0.5f * vs[0];
     const float qxb = plane_pos(li[0] + 1, vs[0], h[0]) + 0.5f * vs[0];
     const float qy = plane_pos(li[1], vs[1], h[1]) + 0.5f * vs[1];
+    // candidates: the shadow of voxel a, or of the two voxels as one 2 x 1 rectangle about
+    // their shared edge (its own support half-width; the bound is the same)
     int lo, hi;
-    bp2d_range(G, view, c, s, P, qxa, qy, k0, k1, lo, hi);
-    if (b_ok) {
-        int lob, hib;
-        bp2d_range(G, view, c, s, P, qxb, qy, k0, k1, lob, hib);
-        if (lob <= hib) {
-            lo = lo <= hi ? min(lo, lob) : lob;
-            hi = max(hi, hib);
-        }
-    }
+    if (b_ok)
+        bp2d_range(G, view, c, s, P, plane_pos(li[0] + 1, vs[0], h[0]), qy, k0, k1, lo, hi, 1);
+    else
+        bp2d_range(G, view, c, s, P, qxa, qy, k0, k1, lo, hi, 0);
     const float4* nrm = G.raynorm + (int64_t)view * G.nu;
     const float4* trp = G.raytrap + (int64_t)view * G.nu;
     const float4* rec = reinterpret_cast<const float4*>(src);
