@@ -23,21 +23,23 @@ def _geom(g, **kw):
     return Geometry(g, **kw)
 
 
-def _box3(v, ny, nx):
-    """Sum over each pixel's 3 x 3 neighbourhood (zero outside the image)."""
-    p = np.pad(v.reshape(ny, nx), 1)
-    return sum(p[dy:dy + ny, dx:dx + nx] for dy in range(3) for dx in range(3)).ravel()
+def _box3(v, nz, ny, nx):
+    """Sum over each voxel's 3 x 3 (x 3) neighbourhood (zero outside the image)."""
+    p = np.pad(v.reshape(nz, ny, nx), 1)
+    return sum(p[dz:dz + nz, dy:dy + ny, dx:dx + nx] for dz in range(3) for dy in range(3)
+               for dx in range(3)).ravel()
 
 
-@pytest.mark.parametrize("name,per_pixel", [("parallel", True), ("fan", True), ("fan_wide", False)])
-def test_back_projection_per_voxel(name, per_pixel):
-    """Every pixel of a 2D back projection against the oracle, with positive residuals so
-    that no sum cancels: a ray the candidate range missed, or a piece of a chord the closed
-    form dropped, shows in its own pixel, not only in the vector norm. Where a ray runs
-    almost along a pixel edge (the 262 x 260 fan has such rays), FP32 splits its chord
-    between the two pixels differently from FP64 (up to 3e-4 of a pixel's sum, the pair's
-    total kept), so there the 3 x 3 neighbourhood sums are compared, which a missed ray
-    still changes."""
+@pytest.mark.parametrize("name,per_voxel", [("parallel", True), ("fan", True), ("fan_wide", False),
+                                            ("cone", True), ("cone_wide", False)])
+def test_back_projection_per_voxel(name, per_voxel):
+    """Every voxel of a back projection against the oracle, with positive residuals so that
+    no sum cancels: a ray the candidate range missed, or a piece of a chord the closed form
+    or the row cut dropped, shows in its own voxel, not only in the vector norm. Where a ray
+    runs almost along a voxel face (the 262 x 260 fan; the 66 x 64 x 26 cone near its middle
+    plane), FP32 splits its chord between the two voxels differently from FP64 (up to 3e-4
+    of a voxel's sum in 2D and 5e-5 in 3D, the pair's total kept), so there the 3 x 3 (x 3)
+    neighbourhood sums are compared, which a missed ray still changes."""
     import torch
     dev = require_gpu()
     g = SMALL[name]
@@ -48,10 +50,10 @@ def test_back_projection_per_voxel(name, per_pixel):
     b = geom.back_project(rd).double().cpu().numpy()
     ref = A.T @ rd.double().cpu().numpy()
     assert ref.max() > 0 and np.count_nonzero(ref) > ref.size // 2
-    if per_pixel:
+    if per_voxel:
         assert np.all(np.abs(b - ref) <= 1e-5 * ref + 1e-6 * ref.max())
     else:
-        bb, rb = _box3(b, g.ny, g.nx), _box3(ref, g.ny, g.nx)
+        bb, rb = _box3(b, g.nz, g.ny, g.nx), _box3(ref, g.nz, g.ny, g.nx)
         assert np.all(np.abs(bb - rb) <= 1e-4 * rb + 1e-6 * rb.max())
 
 
