@@ -57,6 +57,25 @@ def test_back_projection_per_voxel(name, per_voxel):
         assert np.all(np.abs(bb - rb) <= 1e-4 * rb + 1e-6 * rb.max())
 
 
+@pytest.mark.parametrize("name", ["parallel", "fan", "fan_wide", "cone", "cone_wide"])
+def test_forward_projection_per_ray(name):
+    """Every ray of a forward projection against the oracle, with a positive image so that
+    no sum cancels: a walk that stopped early or skipped a voxel shows in its own ray.
+    Rays that miss the image are exactly zero on both sides."""
+    import torch
+    dev = require_gpu()
+    g = SMALL[name]
+    log(f"forward projection per ray {name}")
+    A = oracle_matrix(g)
+    geom = _geom(g)
+    xd = torch.tensor(random_image(A.shape[1], 22, 1.0, 2.0), dtype=torch.float32, device=dev)
+    y = geom.forward_project(xd).double().cpu().numpy()
+    ref = A @ xd.double().cpu().numpy()
+    assert np.count_nonzero(ref) > ref.size // 4
+    assert np.all(y[ref == 0] == 0)
+    assert np.all(np.abs(y - ref) <= 1e-5 * ref + 1e-6 * ref.max())
+
+
 @pytest.mark.parametrize("name", ["parallel", "fan", "cone"])
 def test_fp_bp_match_oracle_small(name):
     import torch
