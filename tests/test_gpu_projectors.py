@@ -193,6 +193,12 @@ def test_full_size_fan_back_projection():
     b = geom.back_project(rd).double().cpu().numpy()
     ref = Projector(g).bp(rd.double().cpu().numpy())
     assert rel_l2(b, ref) <= TOL
+    # positive residuals, pixel neighbourhoods (see test_back_projection_per_voxel)
+    rp = torch.tensor(random_image(n_rays, 33, 1.0, 2.0), dtype=torch.float32, device=dev)
+    bp = geom.back_project(rp).double().cpu().numpy()
+    refp = Projector(g).bp(rp.double().cpu().numpy())
+    bb, rb = _box3(bp, g.nz, g.ny, g.nx), _box3(refp, g.nz, g.ny, g.nx)
+    assert np.all(np.abs(bb - rb) <= 1e-4 * rb + 1e-6 * rb.max())
 
 
 def test_full_size_cone_back_projection_view_subset():
@@ -208,6 +214,12 @@ def test_full_size_cone_back_projection_view_subset():
     b = geom.back_project(rd, views=views).double().cpu().numpy()
     ref = Projector(g, rays=rows).bp(rd.double().cpu().numpy())
     assert rel_l2(b, ref) <= TOL
+    # positive residuals, voxel neighbourhoods (see test_back_projection_per_voxel)
+    rp = torch.tensor(random_image(rows.size, 34, 1.0, 2.0), dtype=torch.float32, device=dev)
+    bp = geom.back_project(rp, views=views).double().cpu().numpy()
+    refp = Projector(g, rays=rows).bp(rp.double().cpu().numpy())
+    bb, rb = _box3(bp, g.nz, g.ny, g.nx), _box3(refp, g.nz, g.ny, g.nx)
+    assert np.all(np.abs(bb - rb) <= 1e-4 * rb + 1e-6 * rb.max())
 
 
 @pytest.mark.parametrize("cfg", ["c2_fan512_im", "c3_cone256_tv"])
