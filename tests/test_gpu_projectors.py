@@ -179,6 +179,12 @@ def test_full_size_sampled_rays(cfg):
     P = Projector(g, rays=sample)
     ref = P.fp(xd.double().cpu().numpy())
     assert rel_l2(y[sample], ref) <= TOL
+    # a positive image, each sampled ray on its own (see test_forward_projection_per_ray)
+    xp = torch.tensor(random_image(x.size, 35, 1.0, 2.0), dtype=torch.float32, device=dev)
+    yp = geom.forward_project(xp).double().cpu().numpy()[sample]
+    refp = P.fp(xp.double().cpu().numpy())
+    assert np.count_nonzero(refp) > sample.size // 4 and np.all(yp[refp == 0] == 0)
+    assert np.all(np.abs(yp - refp) <= 1e-5 * refp + 1e-6 * refp.max())
 
 
 def test_full_size_fan_back_projection():
