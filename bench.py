@@ -285,6 +285,26 @@ def measure(geom, spec, solver, n_vox, warmup, steps, n_prof, workload_name):
                 "traffic_unit": "bytes per dispatch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms[dominant],
                 "updates_per_launch": updates_per_launch, "valu": valu}
+    # the same figures for the other projector and, with TV, the prox (context)
+    other = "back_project_step" if dominant == "forward_project" else "forward_project"
+    ob = bytes_bp if other == "back_project_step" else bytes_fp
+    oprof = profiled(workload_name, other)
+    others = {other: {"achieved": ob / (avg_ms[other] * 1e-3) / 1e9, "frac": ob / (avg_ms[other] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "alg_bytes_per_launch": ob, "avg_launch_ms": avg_ms[other],
+                      "traffic": oprof.get("hbm_bytes") if oprof else None,
+                      "valu_lane_slots_per_update": (oprof["valu_insts"] * 64 / updates_per_launch
+                                                     if oprof and oprof.get("valu_insts") else None)}}
+    if times["tv_prox"][1]:
+        K = solver.options.tv_inner_iters
+        xt = 0 if geom.fp_staged else 8  # the copy of x stored y fastest, kept for the global walk
+        tb = n_vox * (12 + 40 * K + 20 + xt)
+        others["tv_prox"] = {"achieved": tb / (avg_ms["tv_prox"] * 1e-3) / 1e9,
+                             "frac": tb / (avg_ms["tv_prox"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "alg_bytes_per_launch": tb, "avg_launch_ms": avg_ms["tv_prox"],
+                             "alg_bytes_rule": f"per voxel: 12 (p = 0) + 40 x {K} fused FGP steps (p_k, p_k-1 and b "
+                                               f"read, p_k+1 written) + 20 (final step) + {xt} (copy of x stored y "
+                                               "fastest, refreshed after the prox)"}
+    roofline["other_kernels"] = others
 
     return {"elapsed": elapsed, "steps": steps, "value": value, "updates": updates, "roofline": roofline,
             "kernels_avg_ms": avg_ms, "times": times, "r0": r0, "r1": r1, "n_prof": n_prof, "t2": t2, "t3": t3}
